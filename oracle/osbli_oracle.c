@@ -1,0 +1,1025 @@
+/*
+ * osbli_oracle.c -- plain, slow, FP64 CPU oracle for the per-Runge-Kutta-
+ * substage residual of the explicit compressible Navier-Stokes method of
+ * Lusher, Jammy & Sandham, "OpenSBLI: automated code-generation for
+ * heterogeneous computing architectures applied to compressible fluid
+ * dynamics on structured grids" (arXiv 2007.14933).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library; the two meet only in the
+ * seeded input generators and in the array layout, which is an interface.
+ *
+ * Every function follows a passage of the paper, cited by section and
+ * equation label.  Where the paper is silent or garbled the reading that is
+ * taken is stated in place; all of them are collected in the design notes.
+ * No blocking, fusion or reordering: each routine is the definition written
+ * out, one interface / one node at a time.  The only parallelism is an
+ * OpenMP "parallel for" over independent grid lines, which does not change
+ * any arithmetic.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no FMA, no
+ * fast-math), so every operation is a correctly rounded IEEE FP64 operation
+ * in the order written.
+ *
+ * Array layout (the interface shared with the GPU library):
+ *   conserved state U[c][k][j][i], c = (rho, rho*u_0..rho*u_{ndim-1}, rho*E),
+ *   i fastest, each active direction padded by 3 ghost nodes per side,
+ *   inactive directions have extent 1 and no ghosts;
+ *   residual / RK register arrays R[c][k][j][i], dU[c][k][j][i] over interior
+ *   nodes only (no ghosts).
+ *   Metrics (oracle private): S[d][m][ext] (area vector of direction d,
+ *   component m, 3 components always), J[ext], on the ghost-extended grid.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NGHOST 3
+#define NCMAX 5
+
+enum { BC_PERIODIC = 0, BC_EXTRAPOLATE = 1, BC_ISOTHERMAL = 2, BC_ADIABATIC = 3 };
+enum { SCHEME_WENOZ5 = 0, SCHEME_TENO5 = 1 };
+
+typedef struct {
+    int32_t ndim;
+    int32_t pad0;
+    int64_t n[3];
+    double gamma, Re, Pr, Minf;   /* Re <= 0: inviscid (Euler) */
+    int32_t sutherland;           /* 1: Sutherland's law, 0: mu = 1 */
+    int32_t scheme;               /* SCHEME_* */
+    double Ts_over_Tref;
+    double teno_CT;
+    double eps;                   /* epsilon of the nonlinear weights */
+    int32_t roe_avg;              /* 1: Roe average, 0: arithmetic mean */
+    int32_t pad1;
+    int32_t bc[3][2];
+    double wall_T[3][2];
+    double period[3];
+    double body_force;            /* test-only x-momentum source (channel) */
+} orc_params;
+
+/* ------------------------------------------------------------------ grid */
+
+typedef struct {
+    int nd, nc;
+    int64_t n[3], h[3], e[3], s[3];
+    int64_t npts, nint;
+} grid_t;
+
+static void grid_make(const orc_params *P, grid_t *g)
+{
+    g->nd = P->ndim;
+    g->nc = P->ndim + 2;
+    for (int d = 0; d < 3; d++) {
+        g->n[d] = d < P->ndim ? P->n[d] : 1;
+        g->h[d] = d < P->ndim ? NGHOST : 0;
+        g->e[d] = g->n[d] + 2 * g->h[d];
+    }
+    g->s[0] = 1;
+    g->s[1] = g->e[0];
+    g->s[2] = g->e[0] * g->e[1];
+    g->npts = g->e[0] * g->e[1] * g->e[2];
+    g->nint = g->n[0] * g->n[1] * g->n[2];
+}
+
+static int64_t gidx(const grid_t *g, int64_t i, int64_t j, int64_t k)
+{
+    return (i + g->h[0]) + (j + g->h[1]) * g->s[1] + (k + g->h[2]) * g->s[2];
+}
+
+static int64_t cidx(const grid_t *g, int64_t i, int64_t j, int64_t k)
+{
+    return i + g->n[0] * (j + g->n[1] * k);
+}
+
+static int64_t wrap(int64_t p, int64_t n) { int64_t r = p % n; return r < 0 ? r + n : r; }
+
+/* ------------------------------------------------- state, EOS and flux --
+ * Governing equations (section 2.1, eq. ns_eqn): conserved variables
+ * (rho, rho u_i, rho E).  Pressure, temperature and sound speed from the
+ * equation of state (eq. pressure_eqn): p = (gamma-1)(rho E - rho u_i u_i/2),
+ * p = rho T / (gamma M^2), a = sqrt(gamma p / rho).
+ */
+typedef struct { double rho, u[3], p, T, a, H; } prim_t;
+
+static void to_prim(const orc_params *P, int nd, const double *U, prim_t *w)
+{
+    double ke = 0.0;
+    w->rho = U[0];
+    for (int m = 0; m < 3; m++) w->u[m] = 0.0;
+    for (int m = 0; m < nd; m++) {
+        w->u[m] = U[1 + m] / U[0];
+        ke += w->u[m] * w->u[m];
+    }
+    w->p = (P->gamma - 1.0) * (U[nd + 1] - 0.5 * w->rho * ke);
+    w->T = P->gamma * P->Minf * P->Minf * w->p / w->rho;
+    w->a = sqrt(P->gamma * w->p / w->rho);
+    w->H = (U[nd + 1] + w->p) / w->rho;
+}
+
+/* Physical inviscid flux projected on the unit vector nv (the convective part
+ * of eq. ns_eqn contracted with n): (rho u_n, rho u_i u_n + p n_i, (rho E + p) u_n). */
+static void phys_flux(int nd, const double *U, const prim_t *w, const double *nv, double *f)
+{
+    double un = 0.0;
+    for (int m = 0; m < nd; m++) un += w->u[m] * nv[m];
+    f[0] = U[0] * un;
+    for (int m = 0; m < nd; m++) f[1 + m] = U[1 + m] * un + w->p * nv[m];
+    f[nd + 1] = (U[nd + 1] + w->p) * un;
+}
+
+/* ----------------------------------------- eigensystem in direction n --
+ * Characteristic decomposition (section 2.2, enumerated algorithm, step 2b).
+ * The paper does not print the eigenvectors; these are the textbook ones of
+ * the Euler equations for a direction n.  Field order:
+ *   0: u_n - a,  1: u_n (entropy),  2..nd: u_n (shear, tangents t_1..),
+ *   nd+1: u_n + a.
+ * Reading for the repeated eigenvalue: t_1 = normalise(e_{d+1} - (e_{d+1}.n)n),
+ * t_2 = n x t_1 (indices cyclic).  Rows of L are left eigenvectors, columns of
+ * R right eigenvectors, L R = I.
+ */
+static void tangents(int nd, int d, const double *nv, double t[2][3])
+{
+    memset(t, 0, sizeof(double) * 6);
+    if (nd < 2) return;
+    double e[3] = {0.0, 0.0, 0.0};
+    e[(d + 1) % nd] = 1.0;
+    double en = 0.0;
+    for (int m = 0; m < nd; m++) en += e[m] * nv[m];
+    double nrm = 0.0;
+    for (int m = 0; m < nd; m++) { t[0][m] = e[m] - en * nv[m]; nrm += t[0][m] * t[0][m]; }
+    nrm = sqrt(nrm);
+    for (int m = 0; m < nd; m++) t[0][m] /= nrm;
+    if (nd == 3) {
+        t[1][0] = nv[1] * t[0][2] - nv[2] * t[0][1];
+        t[1][1] = nv[2] * t[0][0] - nv[0] * t[0][2];
+        t[1][2] = nv[0] * t[0][1] - nv[1] * t[0][0];
+    }
+}
+
+/* Average state at the half node from nodes i (left) and i+1 (right):
+ * Roe average (default; the scheme listing of section 3 selects it) or the
+ * arithmetic mean of u and H (flag).  Returns a^2. */
+static double half_state(const orc_params *P, int nd, const prim_t *L, const prim_t *R,
+                         double *u, double *Hh)
+{
+    if (P->roe_avg) {
+        double sl = sqrt(L->rho), sr = sqrt(R->rho);
+        for (int m = 0; m < 3; m++) u[m] = 0.0;
+        for (int m = 0; m < nd; m++) u[m] = (sl * L->u[m] + sr * R->u[m]) / (sl + sr);
+        *Hh = (sl * L->H + sr * R->H) / (sl + sr);
+    } else {
+        for (int m = 0; m < 3; m++) u[m] = 0.0;
+        for (int m = 0; m < nd; m++) u[m] = 0.5 * (L->u[m] + R->u[m]);
+        *Hh = 0.5 * (L->H + R->H);
+    }
+    double ke = 0.0;
+    for (int m = 0; m < nd; m++) ke += u[m] * u[m];
+    return (P->gamma - 1.0) * (*Hh - 0.5 * ke);
+}
+
+static void eigvecs(const orc_params *P, int nd, int d, const double *u, double Hh, double a,
+                    const double *nv, double Lm[NCMAX][NCMAX], double Rm[NCMAX][NCMAX])
+{
+    int nc = nd + 2;
+    double t[2][3];
+    tangents(nd, d, nv, t);
+    double K = 0.0, un = 0.0;
+    for (int m = 0; m < nd; m++) { K += 0.5 * u[m] * u[m]; un += u[m] * nv[m]; }
+    double b = (P->gamma - 1.0) / (a * a);
+    memset(Lm, 0, sizeof(double) * NCMAX * NCMAX);
+    memset(Rm, 0, sizeof(double) * NCMAX * NCMAX);
+    int jp = nd + 1;
+    /* right eigenvectors (columns) */
+    Rm[0][0] = 1.0; Rm[0][1] = 1.0; Rm[0][jp] = 1.0;
+    for (int m = 0; m < nd; m++) {
+        Rm[1 + m][0] = u[m] - a * nv[m];
+        Rm[1 + m][1] = u[m];
+        Rm[1 + m][jp] = u[m] + a * nv[m];
+    }
+    Rm[nd + 1][0] = Hh - a * un;
+    Rm[nd + 1][1] = K;
+    Rm[nd + 1][jp] = Hh + a * un;
+    for (int s = 0; s < nd - 1; s++) {
+        double ut = 0.0;
+        for (int m = 0; m < nd; m++) { Rm[1 + m][2 + s] = t[s][m]; ut += u[m] * t[s][m]; }
+        Rm[nd + 1][2 + s] = ut;
+    }
+    /* left eigenvectors (rows) */
+    Lm[0][0] = 0.5 * (b * K + un / a);
+    Lm[1][0] = 1.0 - b * K;
+    Lm[jp][0] = 0.5 * (b * K - un / a);
+    for (int m = 0; m < nd; m++) {
+        Lm[0][1 + m] = -0.5 * (b * u[m] + nv[m] / a);
+        Lm[1][1 + m] = b * u[m];
+        Lm[jp][1 + m] = -0.5 * (b * u[m] - nv[m] / a);
+    }
+    Lm[0][nd + 1] = 0.5 * b;
+    Lm[1][nd + 1] = -b;
+    Lm[jp][nd + 1] = 0.5 * b;
+    for (int s = 0; s < nd - 1; s++) {
+        double ut = 0.0;
+        for (int m = 0; m < nd; m++) { Lm[2 + s][1 + m] = t[s][m]; ut += u[m] * t[s][m]; }
+        Lm[2 + s][0] = -ut;
+        Lm[2 + s][nd + 1] = 0.0;
+    }
+    (void)nc;
+}
+
+/* ------------------------------------------- WENO-Z5 / TENO5 (per scalar) --
+ * Input f[0..4] = f_{i-2..i+2}; returns the reconstruction at x_{i+1/2}.
+ * Candidate stencils S_r = {i-r .. i-r+2} (eq. eno_rhs) with the standard
+ * third-order coefficients and optimal weights d = (3/10, 3/5, 1/10);
+ * Jiang-Shu indicators exactly as eq. fifth_smoothness; tau_5 = |beta_0 -
+ * beta_2| (section 2.4 and eq. tau_5).
+ *   WENO-Z (eq. wenoz_weights, sigma_r read as beta_r):
+ *       alpha_r = d_r (1 + (tau/(beta_r + eps))^2),  omega = alpha / sum alpha
+ *   TENO5 (section 2.5): gamma_r = (1 + tau/(beta_r + eps))^6,
+ *       chi_r = gamma_r / sum gamma, delta_r = 0 if chi_r < C_T else 1,
+ *       omega_r = d_r delta_r / sum d delta.
+ * delta (may be NULL) receives the TENO cut-off flags (all 1 for WENO-Z).
+ */
+static void smoothness5(const double *f, double *beta)
+{
+    const double fm2 = f[0], fm1 = f[1], f0 = f[2], fp1 = f[3], fp2 = f[4];
+    double s, t;
+    s = f0 - 2.0 * fp1 + fp2;   t = 3.0 * f0 - 4.0 * fp1 + fp2;
+    beta[0] = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    s = fm1 - 2.0 * f0 + fp1;   t = fm1 - fp1;
+    beta[1] = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    s = fm2 - 2.0 * fm1 + f0;   t = fm2 - 4.0 * fm1 + 3.0 * f0;
+    beta[2] = (13.0 / 12.0) * s * s + 0.25 * t * t;
+}
+
+static double recon5(int scheme, double CT, double eps, const double *f, int *delta)
+{
+    const double fm2 = f[0], fm1 = f[1], f0 = f[2], fp1 = f[3], fp2 = f[4];
+    double q[3], beta[3], w[3];
+    q[0] = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
+    q[1] = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
+    q[2] = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
+    smoothness5(f, beta);
+    const double dr[3] = {3.0 / 10.0, 3.0 / 5.0, 1.0 / 10.0};
+    double tau = fabs(beta[0] - beta[2]);
+    if (scheme == SCHEME_WENOZ5) {
+        double a[3], sum = 0.0;
+        for (int r = 0; r < 3; r++) {
+            double x = tau / (beta[r] + eps);
+            a[r] = dr[r] * (1.0 + x * x);
+            sum += a[r];
+        }
+        for (int r = 0; r < 3; r++) w[r] = a[r] / sum;
+        if (delta) delta[0] = delta[1] = delta[2] = 1;
+    } else {
+        double g[3], sum = 0.0;
+        for (int r = 0; r < 3; r++) {
+            double c = 1.0 + tau / (beta[r] + eps);
+            double c3 = c * c * c;
+            g[r] = c3 * c3;
+            sum += g[r];
+        }
+        int dl[3];
+        double sd = 0.0;
+        for (int r = 0; r < 3; r++) {
+            double chi = g[r] / sum;
+            dl[r] = chi < CT ? 0 : 1;
+            sd += dr[r] * dl[r];
+        }
+        for (int r = 0; r < 3; r++) w[r] = dr[r] * dl[r] / sd;
+        if (delta) { delta[0] = dl[0]; delta[1] = dl[1]; delta[2] = dl[2]; }
+    }
+    return w[0] * q[0] + w[1] * q[1] + w[2] * q[2];
+}
+
+/* --------------------------------------------- characteristic LLF flux --
+ * One half node x_{i+1/2} in direction d (section 2.2, enumerated algorithm):
+ *   n = S/|S| with S the half-node area vector; for k = i-2..i+3:
+ *   V_k = L U_k, g_k = L f_k(n); alpha_j = max_k |lambda_j(U_k)| over the six
+ *   stencil points (reading of "local stencil points k", pointwise
+ *   eigenvalues, the averaged state's own eigenvalue not included);
+ *   g^{+-}_k = (g_k +- alpha_j V_k)/2 (eq. lax_scalar per field);
+ *   ghat^+ from g^+_{i-2..i+2}, ghat^- from the mirror image
+ *   g^-_{i+3..i-1}; F = |S| R (ghat^+ + ghat^-).
+ * Uk holds the six stencil states, Uk[k*nc + c].  delta (may be NULL)
+ * receives the TENO flags as delta[(j*2 + side)*3 + r], side 0 = plus.
+ */
+static void iface_flux(const orc_params *P, int d, const double *Uk, const double *S,
+                       double *F, int *delta)
+{
+    const int nd = P->ndim, nc = nd + 2;
+    double Smag = 0.0, nv[3] = {0.0, 0.0, 0.0};
+    for (int m = 0; m < nd; m++) Smag += S[m] * S[m];
+    Smag = sqrt(Smag);
+    for (int m = 0; m < nd; m++) nv[m] = S[m] / Smag;
+
+    prim_t w[6];
+    double fk[6][NCMAX], lam[6][NCMAX];
+    for (int k = 0; k < 6; k++) {
+        to_prim(P, nd, Uk + k * nc, &w[k]);
+        phys_flux(nd, Uk + k * nc, &w[k], nv, fk[k]);
+        double un = 0.0;
+        for (int m = 0; m < nd; m++) un += w[k].u[m] * nv[m];
+        lam[k][0] = un - w[k].a;
+        for (int j = 1; j <= nd; j++) lam[k][j] = un;
+        lam[k][nd + 1] = un + w[k].a;
+    }
+    double uh[3], Hh;
+    double a2 = half_state(P, nd, &w[2], &w[3], uh, &Hh);
+    double ah = sqrt(a2);
+    double Lm[NCMAX][NCMAX], Rm[NCMAX][NCMAX];
+    eigvecs(P, nd, d, uh, Hh, ah, nv, Lm, Rm);
+
+    double V[6][NCMAX], G[6][NCMAX];
+    for (int k = 0; k < 6; k++)
+        for (int j = 0; j < nc; j++) {
+            double sv = 0.0, sg = 0.0;
+            for (int c = 0; c < nc; c++) {
+                sv += Lm[j][c] * Uk[k * nc + c];
+                sg += Lm[j][c] * fk[k][c];
+            }
+            V[k][j] = sv;
+            G[k][j] = sg;
+        }
+    double ghat[NCMAX];
+    for (int j = 0; j < nc; j++) {
+        double alpha = 0.0;
+        for (int k = 0; k < 6; k++) alpha = fmax(alpha, fabs(lam[k][j]));
+        double gp[5], gm[5];
+        for (int m = 0; m < 5; m++) {
+            gp[m] = 0.5 * (G[m][j] + alpha * V[m][j]);          /* k = i-2+m   */
+            gm[m] = 0.5 * (G[5 - m][j] - alpha * V[5 - m][j]);  /* k = i+3-m   */
+        }
+        int *dp = delta ? delta + (j * 2 + 0) * 3 : NULL;
+        int *dm = delta ? delta + (j * 2 + 1) * 3 : NULL;
+        ghat[j] = recon5(P->scheme, P->teno_CT, P->eps, gp, dp)
+                + recon5(P->scheme, P->teno_CT, P->eps, gm, dm);
+    }
+    for (int c = 0; c < nc; c++) {
+        double s = 0.0;
+        for (int j = 0; j < nc; j++) s += Rm[c][j] * ghat[j];
+        F[c] = Smag * s;
+    }
+}
+
+/* --------------------------------------- fourth-order central operators --
+ * First derivative per unit index spacing (section 2.6).  Interior:
+ * (f_{i-2} - 8 f_{i-1} + 8 f_{i+1} - f_{i+2})/12; the sign of the printed
+ * interior formula is taken from the generated OPS kernel of section 4 (the
+ * displayed equation has both signs flipped), written difference-first so a
+ * constant gives exactly zero.  Non-periodic ends: the one-sided closures at
+ * nodes 0, 1, N-2, N-1 exactly as printed.  Periodic: wrap-around.
+ * fn(ctx, pos) evaluates the operand at index pos along the line (for
+ * periodic lines it is called with pos outside [0, N)).
+ */
+typedef double (*line_fn)(const void *ctx, int64_t pos);
+
+static double dline(line_fn fn, const void *ctx, int64_t N, int periodic, int64_t p)
+{
+    if (periodic || (p >= 2 && p <= N - 3)) {
+        return (2.0 / 3.0) * (fn(ctx, p + 1) - fn(ctx, p - 1))
+             - (1.0 / 12.0) * (fn(ctx, p + 2) - fn(ctx, p - 2));
+    }
+    if (p == 0)
+        return (-25.0 * fn(ctx, 0) + 48.0 * fn(ctx, 1) - 36.0 * fn(ctx, 2)
+                + 16.0 * fn(ctx, 3) - 3.0 * fn(ctx, 4)) / 12.0;
+    if (p == 1)
+        return (-3.0 * fn(ctx, 0) - 10.0 * fn(ctx, 1) + 18.0 * fn(ctx, 2)
+                - 6.0 * fn(ctx, 3) + fn(ctx, 4)) / 12.0;
+    if (p == N - 2)
+        return (-fn(ctx, N - 5) + 6.0 * fn(ctx, N - 4) - 18.0 * fn(ctx, N - 3)
+                + 10.0 * fn(ctx, N - 2) + 3.0 * fn(ctx, N - 1)) / 12.0;
+    /* p == N - 1 */
+    return (3.0 * fn(ctx, N - 5) - 16.0 * fn(ctx, N - 4) + 36.0 * fn(ctx, N - 3)
+            - 48.0 * fn(ctx, N - 2) + 25.0 * fn(ctx, N - 1)) / 12.0;
+}
+
+/* operand = plain array over interior nodes, periodic lines wrapped */
+typedef struct { const grid_t *g; const double *a; int dir; int64_t i, j, k; } arr_line;
+
+static double arr_line_at(const void *vctx, int64_t pos)
+{
+    const arr_line *c = (const arr_line *)vctx;
+    int64_t q[3] = {c->i, c->j, c->k};
+    q[c->dir] = wrap(pos, c->g->n[c->dir]);
+    return c->a[cidx(c->g, q[0], q[1], q[2])];
+}
+
+static int is_periodic(const orc_params *P, int d) { return P->bc[d][0] == BC_PERIODIC; }
+
+/* D_dir of an interior-node array at node (i, j, k) */
+static double darr(const orc_params *P, const grid_t *g, const double *a, int dir,
+                   int64_t i, int64_t j, int64_t k)
+{
+    arr_line c = {g, a, dir, i, j, k};
+    int64_t q[3] = {i, j, k};
+    return dline(arr_line_at, &c, g->n[dir], is_periodic(P, dir), q[dir]);
+}
+
+/* --------------------------------------------------------------- metrics --
+ * Curvilinear transformation (section 2.6, last paragraph): metrics computed
+ * once, with the same central scheme and boundary closures, multiplied into
+ * the derivatives.  The discrete form is not printed; the reading taken is
+ * the strong-conservation one: area vectors S_d = grad(xi_d)/J,
+ *   1D: S = 1, J = 1/x_xi;
+ *   2D: S_xi = (y_eta, -x_eta), S_eta = (-y_xi, x_xi),
+ *       J = 1/(x_xi y_eta - x_eta y_xi);
+ *   3D: S_a = x_b x x_c for (a,b,c) cyclic, each component written in the
+ *       conservative Thomas-Lombard form D_c(x_q D_b x_p) - D_b(x_q D_c x_p),
+ *       J = 1/det(dx/dxi).
+ * Periodic directions: coordinate component d of a node shifted by N_d is
+ * shifted by period[d].  Ghost-node metrics: periodic copy, otherwise copied
+ * from the boundary node (zero-order extension).
+ */
+typedef struct {
+    const orc_params *P; const grid_t *g; const double *X[3];
+    int comp; int dir; int64_t i, j, k;
+} coord_line;
+
+/* coordinate component comp at a node whose index along dir may be outside */
+static double coord_at(const orc_params *P, const grid_t *g, const double *const *X, int comp,
+                       int64_t i, int64_t j, int64_t k)
+{
+    int64_t q[3] = {i, j, k};
+    double shift = 0.0;
+    for (int d = 0; d < g->nd; d++) {
+        int64_t N = g->n[d];
+        if (q[d] < 0 || q[d] >= N) {
+            int64_t m = (q[d] >= 0) ? q[d] / N : -((-q[d] + N - 1) / N);
+            q[d] -= m * N;
+            if (comp == d) shift += (double)m * P->period[d];
+        }
+    }
+    return X[comp][cidx(g, q[0], q[1], q[2])] + shift;
+}
+
+static double coord_line_at(const void *vctx, int64_t pos)
+{
+    const coord_line *c = (const coord_line *)vctx;
+    int64_t q[3] = {c->i, c->j, c->k};
+    q[c->dir] = pos;
+    return coord_at(c->P, c->g, c->X, c->comp, q[0], q[1], q[2]);
+}
+
+/* D_dir x_comp at node */
+static double dcoord(const orc_params *P, const grid_t *g, const double *const *X, int comp,
+                     int dir, int64_t i, int64_t j, int64_t k)
+{
+    coord_line c = {P, g, {X[0], X[1], X[2]}, comp, dir, i, j, k};
+    int64_t q[3] = {i, j, k};
+    return dline(coord_line_at, &c, g->n[dir], is_periodic(P, dir), q[dir]);
+}
+
+/* operand x_q * Xpb where Xpb (= D_b x_p) is periodic without shift */
+typedef struct {
+    const orc_params *P; const grid_t *g; const double *X[3]; const double *Xpb;
+    int q; int dir; int64_t i, j, k;
+} prod_line;
+
+static double prod_line_at(const void *vctx, int64_t pos)
+{
+    const prod_line *c = (const prod_line *)vctx;
+    int64_t qq[3] = {c->i, c->j, c->k};
+    qq[c->dir] = pos;
+    double xq = coord_at(c->P, c->g, c->X, c->q, qq[0], qq[1], qq[2]);
+    int64_t w[3] = {qq[0], qq[1], qq[2]};
+    w[c->dir] = wrap(pos, c->g->n[c->dir]);
+    return xq * c->Xpb[cidx(c->g, w[0], w[1], w[2])];
+}
+
+static void fill_ghost_metrics(const orc_params *P, const grid_t *g, double *A)
+{
+    /* A on the extended grid; interior filled.  Fill ghosts direction by
+     * direction over the full extent of the other directions. */
+    for (int d = 0; d < g->nd; d++) {
+        int64_t lo[3], hi[3];
+        for (int e = 0; e < 3; e++) { lo[e] = -g->h[e]; hi[e] = g->n[e] + g->h[e]; }
+        for (int64_t k = lo[2]; k < hi[2]; k++)
+            for (int64_t j = lo[1]; j < hi[1]; j++)
+                for (int64_t i = lo[0]; i < hi[0]; i++) {
+                    int64_t q[3] = {i, j, k};
+                    int64_t N = g->n[d];
+                    if (q[d] >= 0 && q[d] < N) continue;
+                    int64_t src[3] = {i, j, k};
+                    if (is_periodic(P, d)) src[d] = wrap(q[d], N);
+                    else src[d] = q[d] < 0 ? 0 : N - 1;
+                    A[gidx(g, i, j, k)] = A[gidx(g, src[0], src[1], src[2])];
+                }
+    }
+}
+
+/* X[3]: coordinates on interior nodes (compact, x fastest; unused comps may be
+ * NULL).  S: 9*npts doubles, J: npts doubles (extended grid). */
+int orc_metrics(const orc_params *P, const double *x, const double *y, const double *z,
+                double *S, double *J)
+{
+    grid_t g;
+    grid_make(P, &g);
+    const int nd = g.nd;
+    const double *X[3] = {x, y, z};
+    memset(S, 0, sizeof(double) * 9 * g.npts);
+    memset(J, 0, sizeof(double) * g.npts);
+    double *Xd = (double *)malloc(sizeof(double) * 9 * g.nint); /* Xd[(p*3+b)] = D_b x_p */
+    if (!Xd) return -1;
+    #pragma omp parallel for collapse(2)
+    for (int64_t k = 0; k < g.n[2]; k++)
+        for (int64_t j = 0; j < g.n[1]; j++)
+            for (int64_t i = 0; i < g.n[0]; i++)
+                for (int p = 0; p < nd; p++)
+                    for (int b = 0; b < nd; b++)
+                        Xd[(p * 3 + b) * g.nint + cidx(&g, i, j, k)] = dcoord(P, &g, X, p, b, i, j, k);
+
+    #pragma omp parallel for collapse(2)
+    for (int64_t k = 0; k < g.n[2]; k++)
+        for (int64_t j = 0; j < g.n[1]; j++)
+            for (int64_t i = 0; i < g.n[0]; i++) {
+                int64_t c = cidx(&g, i, j, k), e = gidx(&g, i, j, k);
+#define XD(p, b) Xd[((p) * 3 + (b)) * g.nint + c]
+                if (nd == 1) {
+                    S[0 * g.npts + e] = 1.0;
+                    J[e] = 1.0 / XD(0, 0);
+                } else if (nd == 2) {
+                    S[(0 * 3 + 0) * g.npts + e] = XD(1, 1);
+                    S[(0 * 3 + 1) * g.npts + e] = -XD(0, 1);
+                    S[(1 * 3 + 0) * g.npts + e] = -XD(1, 0);
+                    S[(1 * 3 + 1) * g.npts + e] = XD(0, 0);
+                    J[e] = 1.0 / (XD(0, 0) * XD(1, 1) - XD(0, 1) * XD(1, 0));
+                } else {
+                    for (int a = 0; a < 3; a++) {
+                        int b = (a + 1) % 3, cc = (a + 2) % 3;
+                        for (int m = 0; m < 3; m++) {
+                            int p = (m + 1) % 3, q = (m + 2) % 3;
+                            /* D_c(x_q D_b x_p) - D_b(x_q D_c x_p) */
+                            prod_line c1 = {P, &g, {x, y, z}, Xd + (p * 3 + b) * g.nint, q, cc, i, j, k};
+                            prod_line c2 = {P, &g, {x, y, z}, Xd + (p * 3 + cc) * g.nint, q, b, i, j, k};
+                            int64_t qq[3] = {i, j, k};
+                            double t1 = dline(prod_line_at, &c1, g.n[cc], is_periodic(P, cc), qq[cc]);
+                            double t2 = dline(prod_line_at, &c2, g.n[b], is_periodic(P, b), qq[b]);
+                            S[(a * 3 + m) * g.npts + e] = t1 - t2;
+                        }
+                    }
+                    double det = XD(0, 0) * (XD(1, 1) * XD(2, 2) - XD(1, 2) * XD(2, 1))
+                               - XD(0, 1) * (XD(1, 0) * XD(2, 2) - XD(1, 2) * XD(2, 0))
+                               + XD(0, 2) * (XD(1, 0) * XD(2, 1) - XD(1, 1) * XD(2, 0));
+                    J[e] = 1.0 / det;
+                }
+#undef XD
+            }
+    free(Xd);
+    for (int q = 0; q < 9; q++) fill_ghost_metrics(P, &g, S + q * g.npts);
+    fill_ghost_metrics(P, &g, J);
+    return 0;
+}
+
+/* Half-node area vector of direction d between nodes p and p+1:
+ * S_{i+1/2} = (-S_{i-1} + 7 S_i + 7 S_{i+1} - S_{i+2})/12 (reading: the
+ * four-point interpolation whose difference is the interior operator D, so
+ * the discrete geometric conservation law holds). */
+static void half_area(const grid_t *g, const double *S, int d, int64_t e, double *Sh)
+{
+    int64_t st = g->s[d];
+    for (int m = 0; m < 3; m++) {
+        const double *A = S + (d * 3 + m) * g->npts;
+        Sh[m] = (-A[e - st] + 7.0 * A[e] + 7.0 * A[e + st] - A[e + 2 * st]) / 12.0;
+    }
+}
+
+/* ----------------------------------------------------- boundary conditions --
+ * Section 3.1 (boundary and initial conditions): BCs per (direction, side),
+ * enforced through three ghost nodes.
+ *   periodic: copy; extrapolation (reading: zero-gradient copy of the
+ *   boundary node);
+ *   isothermal wall (eq. wall_energy, eq. halo_density and the momentum
+ *   reflection): wall node momentum = 0, rho E_w = rho_w T_w/(M^2 gamma
+ *   (gamma-1)) with rho_w floating; p_w = rho_w T_w/(gamma M^2) (reading);
+ *   ghost T_{-i} = (i+1) T_w - i T_1; rho_{-i} = gamma M^2 p_w / T_{-i}
+ *   (the printed rho_{-1} read as rho_{-i}); rho u_{-i} = -rho_{-i} u_i;
+ *   rho E_{-i} = p_w/(gamma-1) + rho_{-i}|u_i|^2/2 (reading: zero normal
+ *   pressure gradient).
+ *   adiabatic wall: T_w from the fourth-order one-sided dT/dn = 0 closure,
+ *   T_w = (48 T_1 - 36 T_2 + 16 T_3 - 3 T_4)/25, then as isothermal.
+ * Phase 1 sets the wall-node values of every wall face; phase 2 fills
+ * ghosts direction by direction over the full extent of the other
+ * directions (corner ghosts are never read by the stencils).
+ */
+static void node_T(const orc_params *P, int nd, const double *U, int64_t e, int64_t npts,
+                   double *T, double *u)
+{
+    double Uc[NCMAX];
+    for (int c = 0; c < nd + 2; c++) Uc[c] = U[c * npts + e];
+    prim_t w;
+    to_prim(P, nd, Uc, &w);
+    *T = w.T;
+    if (u) for (int m = 0; m < 3; m++) u[m] = w.u[m];
+}
+
+void orc_apply_bc(const orc_params *P, double *U)
+{
+    grid_t g;
+    grid_make(P, &g);
+    const int nd = g.nd, nc = g.nc;
+    const double gm = P->gamma, M2 = P->Minf * P->Minf;
+    /* phase 1: wall nodes */
+    for (int d = 0; d < nd; d++)
+        for (int side = 0; side < 2; side++) {
+            int kind = P->bc[d][side];
+            if (kind != BC_ISOTHERMAL && kind != BC_ADIABATIC) continue;
+            int64_t N = g.n[d];
+            int64_t lo[3], hi[3];
+            for (int e = 0; e < 3; e++) { lo[e] = 0; hi[e] = g.n[e]; }
+            lo[d] = side ? N - 1 : 0; hi[d] = lo[d] + 1;
+            int sgn = side ? -1 : 1;
+            for (int64_t k = lo[2]; k < hi[2]; k++)
+                for (int64_t j = lo[1]; j < hi[1]; j++)
+                    for (int64_t i = lo[0]; i < hi[0]; i++) {
+                        int64_t ew = gidx(&g, i, j, k);
+                        double Tw;
+                        if (kind == BC_ISOTHERMAL) {
+                            Tw = P->wall_T[d][side];
+                        } else {
+                            double Tm[5];
+                            for (int m = 1; m <= 4; m++) {
+                                node_T(P, nd, U, ew + sgn * m * g.s[d], g.npts, &Tm[m], NULL);
+                            }
+                            Tw = (48.0 * Tm[1] - 36.0 * Tm[2] + 16.0 * Tm[3] - 3.0 * Tm[4]) / 25.0;
+                        }
+                        double rw = U[ew];
+                        for (int m = 0; m < nd; m++) U[(1 + m) * g.npts + ew] = 0.0;
+                        U[(nd + 1) * g.npts + ew] = rw * Tw / (M2 * gm * (gm - 1.0));
+                    }
+        }
+    /* phase 2: ghosts */
+    for (int d = 0; d < nd; d++) {
+        int64_t N = g.n[d];
+        for (int side = 0; side < 2; side++) {
+            int kind = P->bc[d][side];
+            int64_t lo[3], hi[3];
+            for (int e = 0; e < 3; e++) { lo[e] = -g.h[e]; hi[e] = g.n[e] + g.h[e]; }
+            lo[d] = 0; hi[d] = 1;  /* iterate the face; ghost index set below */
+            int sgn = side ? -1 : 1;
+            for (int64_t k = lo[2]; k < hi[2]; k++)
+                for (int64_t j = lo[1]; j < hi[1]; j++)
+                    for (int64_t i = lo[0]; i < hi[0]; i++) {
+                        int64_t q[3] = {i, j, k};
+                        q[d] = side ? N - 1 : 0;
+                        int64_t ew = gidx(&g, q[0], q[1], q[2]);   /* boundary node */
+                        for (int m = 1; m <= NGHOST; m++) {
+                            int64_t eg = ew - sgn * m * g.s[d];      /* ghost m */
+                            if (kind == BC_PERIODIC) {
+                                int64_t es = ew - sgn * m * g.s[d] + sgn * N * g.s[d];
+                                for (int c = 0; c < nc; c++) U[c * g.npts + eg] = U[c * g.npts + es];
+                            } else if (kind == BC_EXTRAPOLATE) {
+                                for (int c = 0; c < nc; c++) U[c * g.npts + eg] = U[c * g.npts + ew];
+                            } else {
+                                double Tw, T1, ui[3], Ti;
+                                node_T(P, nd, U, ew, g.npts, &Tw, NULL);
+                                node_T(P, nd, U, ew + sgn * g.s[d], g.npts, &T1, NULL);
+                                node_T(P, nd, U, ew + sgn * m * g.s[d], g.npts, &Ti, ui);
+                                (void)Ti;
+                                double rw = U[ew];
+                                double pw = rw * Tw / (gm * M2);
+                                double Tg = (m + 1) * Tw - m * T1;
+                                double rg = gm * M2 * pw / Tg;
+                                double ke = 0.0;
+                                U[eg] = rg;
+                                for (int c = 0; c < nd; c++) {
+                                    U[(1 + c) * g.npts + eg] = -rg * ui[c];
+                                    ke += ui[c] * ui[c];
+                                }
+                                U[(nd + 1) * g.npts + eg] = pw / (gm - 1.0) + 0.5 * rg * ke;
+                            }
+                        }
+                    }
+        }
+    }
+}
+
+/* ------------------------------------------------------- viscous terms --
+ * Heat flux (eq. heat_flux), stress tensor (eq. stress_tensor), Sutherland's
+ * law (eq. sutherland).  Discrete form (reading: divergence form):
+ *   gradients at nodes  d phi/dx_j = J sum_k (S_k)_j D_k phi,
+ *   Fv_j = (0, tau_1j .. tau_nj, u_i tau_ij - q_j),
+ *   G_k = sum_j (S_k)_j Fv_j at nodes,
+ *   R_visc = J sum_k D_k G_k,
+ * with D the central operator above (closures at non-periodic ends, wrap on
+ * periodic ones); ghost nodes are never used.
+ */
+static double viscosity(const orc_params *P, double T)
+{
+    if (!P->sutherland) return 1.0;
+    double Ts = P->Ts_over_Tref;
+    return pow(T, 1.5) * (1.0 + Ts) / (T + Ts);
+}
+
+static void viscous_residual(const orc_params *P, const grid_t *g, const double *S,
+                             const double *J, const double *U, double *R)
+{
+    const int nd = g->nd, nv = nd + 1;  /* velocity comps + T */
+    const int64_t ni = g->nint;
+    double *phi = (double *)malloc(sizeof(double) * nv * ni);
+    double *Gv = (double *)malloc(sizeof(double) * nd * nv * ni);
+    if (!phi || !Gv) { free(phi); free(Gv); return; }
+    #pragma omp parallel for collapse(2)
+    for (int64_t k = 0; k < g->n[2]; k++)
+        for (int64_t j = 0; j < g->n[1]; j++)
+            for (int64_t i = 0; i < g->n[0]; i++) {
+                double T, u[3];
+                node_T(P, nd, U, gidx(g, i, j, k), g->npts, &T, u);
+                int64_t c = cidx(g, i, j, k);
+                for (int m = 0; m < nd; m++) phi[m * ni + c] = u[m];
+                phi[nd * ni + c] = T;
+            }
+    const double Re = P->Re, Pr = P->Pr, gm = P->gamma, M2 = P->Minf * P->Minf;
+    #pragma omp parallel for collapse(2)
+    for (int64_t k = 0; k < g->n[2]; k++)
+        for (int64_t j = 0; j < g->n[1]; j++)
+            for (int64_t i = 0; i < g->n[0]; i++) {
+                int64_t c = cidx(g, i, j, k), e = gidx(g, i, j, k);
+                double Dk[4][3], grad[4][3];
+                for (int v = 0; v < nv; v++)
+                    for (int kk = 0; kk < nd; kk++)
+                        Dk[v][kk] = darr(P, g, phi + v * ni, kk, i, j, k);
+                for (int v = 0; v < nv; v++)
+                    for (int jj = 0; jj < nd; jj++) {
+                        double s = 0.0;
+                        for (int kk = 0; kk < nd; kk++) s += S[(kk * 3 + jj) * g->npts + e] * Dk[v][kk];
+                        grad[v][jj] = J[e] * s;
+                    }
+                double T = phi[nd * ni + c];
+                double mu = viscosity(P, T);
+                double divu = 0.0;
+                for (int m = 0; m < nd; m++) divu += grad[m][m];
+                double tau[3][3], q[3], Fv[3][4];
+                for (int a = 0; a < nd; a++)
+                    for (int b = 0; b < nd; b++)
+                        tau[a][b] = mu / Re * (grad[a][b] + grad[b][a] - (a == b ? 2.0 / 3.0 * divu : 0.0));
+                for (int b = 0; b < nd; b++)
+                    q[b] = -mu / ((gm - 1.0) * M2 * Pr * Re) * grad[nd][b];
+                for (int b = 0; b < nd; b++) {
+                    double work = 0.0;
+                    for (int a = 0; a < nd; a++) { Fv[b][a] = tau[a][b]; work += phi[a * ni + c] * tau[a][b]; }
+                    Fv[b][nd] = work - q[b];
+                }
+                for (int kk = 0; kk < nd; kk++)
+                    for (int v = 0; v < nv; v++) {
+                        double s = 0.0;
+                        for (int b = 0; b < nd; b++) s += S[(kk * 3 + b) * g->npts + e] * Fv[b][v];
+                        Gv[(kk * nv + v) * ni + c] = s;
+                    }
+            }
+    #pragma omp parallel for collapse(2)
+    for (int64_t k = 0; k < g->n[2]; k++)
+        for (int64_t j = 0; j < g->n[1]; j++)
+            for (int64_t i = 0; i < g->n[0]; i++) {
+                int64_t c = cidx(g, i, j, k), e = gidx(g, i, j, k);
+                for (int v = 0; v < nv; v++) {
+                    double s = 0.0;
+                    for (int kk = 0; kk < nd; kk++) s += darr(P, g, Gv + (kk * nv + v) * ni, kk, i, j, k);
+                    R[(1 + v) * ni + c] += J[e] * s;
+                }
+            }
+    free(phi);
+    free(Gv);
+}
+
+/* ------------------------------------------------------------ residual --
+ * R = dU/dt on interior nodes: convective part -J sum_d (F_{i+1/2} -
+ * F_{i-1/2}) (eq. FD_reconstruct in computational space, all directions,
+ * enumerated algorithm step 4), plus the viscous part when Re > 0, plus the
+ * test-only body force.
+ */
+int orc_residual(const orc_params *P, const double *S, const double *J, const double *U, double *R)
+{
+    grid_t g;
+    grid_make(P, &g);
+    const int nd = g.nd, nc = g.nc;
+    const int64_t ni = g.nint;
+    memset(R, 0, sizeof(double) * nc * ni);
+    for (int d = 0; d < nd; d++) {
+        int64_t N = g.n[d];
+        int o1 = (d + 1) % 3, o2 = (d + 2) % 3;
+        int64_t n1 = g.n[o1], n2 = g.n[o2];
+        #pragma omp parallel for collapse(2)
+        for (int64_t b = 0; b < n2; b++)
+            for (int64_t a = 0; a < n1; a++) {
+                double *Fl = (double *)malloc(sizeof(double) * nc * (N + 1));
+                for (int64_t p = -1; p < N; p++) {
+                    int64_t q[3];
+                    q[d] = p; q[o1] = a; q[o2] = b;
+                    int64_t e = gidx(&g, q[0], q[1], q[2]);
+                    double Uk[6 * NCMAX], Sh[3];
+                    for (int k = 0; k < 6; k++)
+                        for (int c = 0; c < nc; c++) Uk[k * nc + c] = U[c * g.npts + e + (k - 2) * g.s[d]];
+                    half_area(&g, S, d, e, Sh);
+                    iface_flux(P, d, Uk, Sh, Fl + (p + 1) * nc, NULL);
+                }
+                for (int64_t p = 0; p < N; p++) {
+                    int64_t q[3];
+                    q[d] = p; q[o1] = a; q[o2] = b;
+                    int64_t e = gidx(&g, q[0], q[1], q[2]);
+                    int64_t ci = cidx(&g, q[0], q[1], q[2]);
+                    for (int c = 0; c < nc; c++)
+                        R[c * ni + ci] -= J[e] * (Fl[(p + 1) * nc + c] - Fl[p * nc + c]);
+                }
+                free(Fl);
+            }
+    }
+    if (P->Re > 0.0) viscous_residual(P, &g, S, J, U, R);
+    if (P->body_force != 0.0) {
+        for (int64_t k = 0; k < g.n[2]; k++)
+            for (int64_t j = 0; j < g.n[1]; j++)
+                for (int64_t i = 0; i < g.n[0]; i++) {
+                    double T, u[3];
+                    node_T(P, nd, U, gidx(&g, i, j, k), g.npts, &T, u);
+                    int64_t ci = cidx(&g, i, j, k);
+                    R[1 * ni + ci] += P->body_force;
+                    R[(nd + 1) * ni + ci] += P->body_force * u[0];
+                }
+    }
+    return 0;
+}
+
+/* --------------------------------------------------------- time stepping --
+ * Low-storage Runge-Kutta in Williamson's 2N form (section 2.7):
+ *   dU^(s) = A_s dU^(s-1) + dt R(U^(s-1)),  U^(s) = U^(s-1) + B_s dU^(s).
+ * The coefficients are not printed (cited to Carpenter & Kennedy); reading:
+ * the three-stage third-order 2N scheme A = (0, -5/9, -153/128),
+ * B = (1/3, 15/16, 8/15).  Stage 0 does not read dU.
+ */
+static const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+static const double RK_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+int orc_rk_update(const orc_params *P, int stage, double dt, const double *R, double *U, double *dU)
+{
+    grid_t g;
+    grid_make(P, &g);
+    const int64_t ni = g.nint;
+    for (int c = 0; c < g.nc; c++)
+        for (int64_t k = 0; k < g.n[2]; k++)
+            for (int64_t j = 0; j < g.n[1]; j++)
+                for (int64_t i = 0; i < g.n[0]; i++) {
+                    int64_t ci = c * ni + cidx(&g, i, j, k);
+                    int64_t e = c * g.npts + gidx(&g, i, j, k);
+                    double du = (stage == 0 ? 0.0 : RK_A[stage] * dU[ci]) + dt * R[ci];
+                    dU[ci] = du;
+                    U[e] = U[e] + RK_B[stage] * du;
+                }
+    return 0;
+}
+
+int orc_rk_substep(const orc_params *P, const double *S, const double *J, int stage, double dt,
+                   double *U, double *dU)
+{
+    grid_t g;
+    grid_make(P, &g);
+    double *R = (double *)malloc(sizeof(double) * g.nc * g.nint);
+    if (!R) return -1;
+    orc_residual(P, S, J, U, R);
+    orc_rk_update(P, stage, dt, R, U, dU);
+    free(R);
+    return 0;
+}
+
+/* Time step (the paper advances with a constant dt; reading for a CFL
+ * number): dt = CFL / max over interior nodes of
+ *   sum_d J|S_d| (|u.n_d| + a) + 2 nu_eff sum_d (J|S_d|)^2,
+ * nu_eff = max(4/3, gamma/Pr) mu / (rho Re) when viscous, else 0. */
+double orc_compute_dt(const orc_params *P, const double *S, const double *J, const double *U, double cfl)
+{
+    grid_t g;
+    grid_make(P, &g);
+    const int nd = g.nd;
+    double smax = 0.0;
+    for (int64_t k = 0; k < g.n[2]; k++)
+        for (int64_t j = 0; j < g.n[1]; j++)
+            for (int64_t i = 0; i < g.n[0]; i++) {
+                int64_t e = gidx(&g, i, j, k);
+                double Uc[NCMAX];
+                for (int c = 0; c < g.nc; c++) Uc[c] = U[c * g.npts + e];
+                prim_t w;
+                to_prim(P, nd, Uc, &w);
+                double nu = 0.0;
+                if (P->Re > 0.0) {
+                    double f = fmax(4.0 / 3.0, P->gamma / P->Pr);
+                    nu = f * viscosity(P, w.T) / (w.rho * P->Re);
+                }
+                double conv = 0.0, diff = 0.0;
+                for (int d = 0; d < nd; d++) {
+                    double s2 = 0.0, us = 0.0;
+                    for (int m = 0; m < nd; m++) {
+                        double sm = S[(d * 3 + m) * g.npts + e];
+                        s2 += sm * sm;
+                        us += w.u[m] * sm;
+                    }
+                    double smag = sqrt(s2);
+                    double js = J[e] * smag;
+                    conv += js * (fabs(us / smag) + w.a);
+                    diff += js * js;
+                }
+                double s = conv + 2.0 * nu * diff;
+                if (s > smax) smax = s;
+            }
+    return cfl / smax;
+}
+
+/* Whole run: BCs at t = 0, then per step dt (fixed, or from CFL, clipped to
+ * t_end), three substeps each followed by the BCs. */
+int orc_run(const orc_params *P, const double *S, const double *J, double *U, double *dU,
+            int64_t nsteps, double cfl, double dt_fixed, double t_end, double *t_out)
+{
+    double t = t_out ? *t_out : 0.0;
+    orc_apply_bc(P, U);
+    for (int64_t it = 0; it < nsteps; it++) {
+        if (t_end > 0.0 && t >= t_end) break;
+        double dt = dt_fixed > 0.0 ? dt_fixed : orc_compute_dt(P, S, J, U, cfl);
+        if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
+        for (int s = 0; s < 3; s++) {
+            orc_rk_substep(P, S, J, s, dt, U, dU);
+            orc_apply_bc(P, U);
+        }
+        t += dt;
+    }
+    if (t_out) *t_out = t;
+    return 0;
+}
+
+/* ------------------------------------------------ exported unit pieces -- */
+
+void orc_smoothness5(const double *f, double *beta) { smoothness5(f, beta); }
+
+double orc_recon5(int scheme, double CT, double eps, const double *f, int *delta)
+{
+    return recon5(scheme, CT, eps, f, delta);
+}
+
+void orc_iface_flux(const orc_params *P, int d, const double *Uk, const double *S, double *F, int *delta)
+{
+    iface_flux(P, d, Uk, S, F, delta);
+}
+
+void orc_phys_flux(const orc_params *P, const double *U, const double *nv, double *f)
+{
+    prim_t w;
+    to_prim(P, P->ndim, U, &w);
+    phys_flux(P->ndim, U, &w, nv, f);
+}
+
+/* averaged state and eigenvectors at the half node between UL and UR */
+void orc_eigen(const orc_params *P, int d, const double *UL, const double *UR, const double *nv,
+               double *Lout, double *Rout, double *lam)
+{
+    const int nd = P->ndim, nc = nd + 2;
+    prim_t wl, wr;
+    to_prim(P, nd, UL, &wl);
+    to_prim(P, nd, UR, &wr);
+    double uh[3], Hh;
+    double a = sqrt(half_state(P, nd, &wl, &wr, uh, &Hh));
+    double Lm[NCMAX][NCMAX], Rm[NCMAX][NCMAX];
+    eigvecs(P, nd, d, uh, Hh, a, nv, Lm, Rm);
+    double un = 0.0;
+    for (int m = 0; m < nd; m++) un += uh[m] * nv[m];
+    for (int j = 0; j < nc; j++)
+        for (int c = 0; c < nc; c++) { Lout[j * nc + c] = Lm[j][c]; Rout[c * nc + j] = Rm[c][j]; }
+    lam[0] = un - a;
+    for (int j = 1; j <= nd; j++) lam[j] = un;
+    lam[nd + 1] = un + a;
+}
+
+/* D of a 1D array (n points; periodic flag) */
+void orc_deriv_line(const double *f, int64_t n, int periodic, double *out)
+{
+    orc_params P;
+    memset(&P, 0, sizeof(P));
+    P.ndim = 1;
+    P.n[0] = n;
+    P.bc[0][0] = P.bc[0][1] = periodic ? BC_PERIODIC : BC_EXTRAPOLATE;
+    grid_t g;
+    grid_make(&P, &g);
+    for (int64_t i = 0; i < n; i++) out[i] = darr(&P, &g, f, 0, i, 0, 0);
+}
+
+/* D along direction dir of an interior-node array (for the GCL test) */
+void orc_deriv_field(const orc_params *P, const double *a, int dir, double *out)
+{
+    grid_t g;
+    grid_make(P, &g);
+    for (int64_t k = 0; k < g.n[2]; k++)
+        for (int64_t j = 0; j < g.n[1]; j++)
+            for (int64_t i = 0; i < g.n[0]; i++)
+                out[cidx(&g, i, j, k)] = darr(P, &g, a, dir, i, j, k);
+}
+
+double orc_viscosity(const orc_params *P, double T) { return viscosity(P, T); }
+
+int orc_abi_version(void) { return 1; }
+
+/* viscous part of the residual alone (interior nodes, R overwritten) */
+int orc_viscous_residual(const orc_params *P, const double *S, const double *J, const double *U, double *R)
+{
+    grid_t g;
+    grid_make(P, &g);
+    memset(R, 0, sizeof(double) * g.nc * g.nint);
+    viscous_residual(P, &g, S, J, U, R);
+    return 0;
+}
