@@ -1,0 +1,181 @@
+/*
+ * osbli.h -- C ABI of the MI355X (gfx950) library for the per-Runge-Kutta-
+ * substage residual of the explicit compressible Navier-Stokes method of
+ * Lusher, Jammy & Sandham (OpenSBLI, arXiv 2007.14933).
+ *
+ * The library computes, on one GPU, the right-hand side R(U) of the
+ * conservation laws of section 2.1 (eq. ns_eqn) on a structured, possibly
+ * curvilinear grid, and advances U with the low-storage Runge-Kutta scheme
+ * of section 2.7:
+ *   - convective terms: characteristic (Roe-averaged) reconstruction with
+ *     local Lax-Friedrichs splitting, WENO-Z5 (section 2.4) or TENO5
+ *     (section 2.5), per direction (section 2.2, enumerated algorithm);
+ *   - viscous and heat-flux terms (eqs. heat_flux, stress_tensor, sutherland)
+ *     with the fourth-order central scheme and one-sided closures of
+ *     section 2.6, in divergence form;
+ *   - metrics computed once (section 2.6, last paragraph), in FP64;
+ *   - boundary conditions through three ghost nodes per side (section 3.1:
+ *     periodic, extrapolation, isothermal and adiabatic no-slip walls).
+ *
+ * Conventions (all calls):
+ *   - Arrays are device pointers unless stated otherwise, FP64, owned by the
+ *     caller (the library never allocates or frees device memory except in
+ *     osbli_init_grid's host-side context).  The state U is laid out
+ *     component-major U[c][k][j][i], c = (rho, rho u_0 .. rho u_{ndim-1},
+ *     rho E), i fastest, with 3 ghost nodes on both sides of each active
+ *     direction (extent n[d] + 6) and extent 1 in unused directions.
+ *     R and dU are laid out [c][k][j][i] over interior nodes only.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Calls are
+ *     stream-ordered and asynchronous unless documented as synchronising.
+ *   - Return value: OSBLI_OK (0) or a negative OSBLI_E* code; a message is
+ *     kept in the context (osbli_last_error).  No call aborts, exits or
+ *     throws across the ABI.
+ */
+#ifndef OSBLI_H
+#define OSBLI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OSBLI_ABI_VERSION 1
+#define OSBLI_NGHOST 3
+
+enum osbli_status {
+    OSBLI_OK = 0,
+    OSBLI_EINVAL = -1,    /* bad parameters, sizes or arguments */
+    OSBLI_EDEVICE = -2,   /* a HIP runtime call failed */
+    OSBLI_ENONPHYS = -3,  /* a kernel met rho <= 0, p <= 0 or NaN */
+    OSBLI_ENOSPACE = -4   /* workspace too small */
+};
+
+/* boundary kinds per (direction, side), section 3.1 */
+enum osbli_bc {
+    OSBLI_PERIODIC = 0,        /* must be set on both sides of a direction */
+    OSBLI_EXTRAPOLATE = 1,     /* zero-gradient copy of the boundary node  */
+    OSBLI_ISOTHERMAL_WALL = 2, /* T = wall_T[d][side] at the boundary node */
+    OSBLI_ADIABATIC_WALL = 3   /* dT/dn = 0 (fourth-order one-sided)       */
+};
+
+enum osbli_scheme { OSBLI_WENOZ5 = 0, OSBLI_TENO5 = 1 };
+
+/* arithmetic of the reconstruction and flux evaluation (state, RK
+ * accumulation, metrics and dt reduction are FP64 in every form) */
+enum osbli_form { OSBLI_FORM_FP64 = 0, OSBLI_FORM_MIXED = 1 };
+
+/* coordinate input of osbli_init_grid */
+enum osbli_mesh {
+    OSBLI_MESH_SEPARABLE = 0, /* x[n0], y[n1], z[n2]: x_d depends on index d only */
+    OSBLI_MESH_GENERAL = 1    /* x, y, z each n0*n1*n2, i fastest              */
+};
+
+typedef struct osbli_params {
+    int32_t ndim;              /* 1, 2 or 3 */
+    int32_t mesh;              /* enum osbli_mesh */
+    int64_t n[3];              /* interior nodes per direction; 1 when unused */
+    double gamma;              /* ratio of heat capacities */
+    double Re;                 /* Reynolds number; <= 0 means inviscid (Euler) */
+    double Pr;                 /* Prandtl number */
+    double Minf;               /* reference Mach number M_ref */
+    int32_t sutherland;        /* 1: Sutherland's law, 0: mu = 1 */
+    int32_t scheme;            /* enum osbli_scheme */
+    double Ts_over_Tref;       /* Sutherland constant T_s / T_ref */
+    double teno_CT;            /* TENO cut-off C_T */
+    double eps;                /* epsilon of the nonlinear weights (1e-16) */
+    int32_t roe_avg;           /* 1: Roe average, 0: arithmetic mean of u, H */
+    int32_t form;              /* enum osbli_form */
+    int32_t sensor;            /* 0: off (learned routing is a later form) */
+    int32_t reserved;
+    int32_t bc_kind[3][2];     /* enum osbli_bc per (direction, side) */
+    double wall_T[3][2];       /* isothermal wall temperature per face */
+    double period[3];          /* coordinate shift of a periodic direction */
+} osbli_params;
+
+typedef struct osbli_ctx osbli_ctx;
+
+/* Bytes of device workspace osbli_init_grid needs for these parameters
+ * (metrics, residual accumulator, viscous fluxes, reduction slots and the
+ * coordinate staging used once at set-up).  Pure host function; returns 0
+ * for invalid parameters. */
+size_t osbli_workspace_bytes(const osbli_params *p);
+
+/* Validate parameters, create the context and compute the metrics and
+ * Jacobian once, in FP64, on the device (section 2.6, last paragraph).
+ *   x, y, z    host FP64 coordinates of the interior nodes; layout given by
+ *              p->mesh; pointers beyond ndim are ignored.  Periodic
+ *              directions are shifted by period[d] across the wrap.
+ *   workspace  device buffer of at least osbli_workspace_bytes(p) bytes,
+ *              owned by the caller, which must outlive the context.
+ * Errors: OSBLI_EINVAL (bad ndim / sizes / BC kinds, periodic on one side
+ * only, fewer than 5 nodes along a non-periodic direction, fewer than 6
+ * along a periodic one), OSBLI_ENOSPACE, OSBLI_EDEVICE.  Synchronising. */
+int osbli_init_grid(osbli_ctx **ctx, const osbli_params *p, const double *x, const double *y,
+                    const double *z, void *workspace, size_t ws_bytes, void *stream);
+
+/* Impose the boundary conditions on U in place (section 3.1): wall-node
+ * momentum and energy of every wall face, then the three ghost layers of
+ * each direction in turn. */
+int osbli_apply_bc(osbli_ctx *ctx, double *U, void *stream);
+
+/* R = dU/dt at interior nodes: convective part (section 2.2 algorithm, all
+ * directions) plus viscous part when Re > 0.  U's ghosts must be valid.
+ * R: device, interior layout, may not alias U. */
+int osbli_residual(osbli_ctx *ctx, const double *U, double *R, void *stream);
+
+/* One Runge-Kutta substage (section 2.7, three stages, 2N form):
+ *   dU <- A_s dU + dt R(U),  U <- U + B_s dU,
+ * with (A, B) = ((0, -5/9, -153/128), (1/3, 15/16, 8/15)); stage 0 ignores
+ * the incoming dU.  Does not apply boundary conditions.  U (ghosted layout)
+ * and dU (interior layout) must not alias. */
+int osbli_rk_substep(osbli_ctx *ctx, int stage, double dt, double *U, double *dU, void *stream);
+
+/* dt = cfl / max over interior nodes of
+ *   sum_d J|S_d| (|u.n_d| + a) + 2 nu_eff sum_d (J|S_d|)^2,
+ * nu_eff = max(4/3, gamma/Pr) mu/(rho Re) when viscous.  Deterministic
+ * device max-reduction; synchronising (one host read-back). */
+int osbli_compute_dt(osbli_ctx *ctx, const double *U, double cfl, double *dt_out, void *stream);
+
+/* Synchronises the context's last stream; returns OSBLI_ENONPHYS if any
+ * kernel met rho <= 0, p <= 0 or NaN since the previous check, and clears
+ * the flag. */
+int osbli_check(osbli_ctx *ctx);
+
+/* Last error message of the context (never NULL). */
+const char *osbli_last_error(const osbli_ctx *ctx);
+
+/* Release the host-side context (the workspace stays with its owner). */
+void osbli_destroy(osbli_ctx *ctx);
+
+/* Kernel classes timed by the optional profiler. */
+enum osbli_kernel_class {
+    OSBLI_K_SWEEP_X = 0,   /* convective sweep along x (y = 1, z = 2 follow) */
+    OSBLI_K_SWEEP_Y = 1,
+    OSBLI_K_SWEEP_Z = 2,
+    OSBLI_K_VISC_FLUX = 3, /* viscous-flux pass */
+    OSBLI_K_FINISH = 4,    /* viscous divergence + RK update (or residual store) */
+    OSBLI_K_BC = 5,        /* boundary-condition launches of one osbli_apply_bc */
+    OSBLI_K_DT = 6,        /* time-step reduction */
+    OSBLI_K_COUNT = 7
+};
+
+/* Instrumentation (not part of the method): when enabled, each launch group
+ * of the classes above is bracketed by HIP events on the stream it runs on.
+ * Enabling or disabling clears the totals.  Host-side events only; no device
+ * memory is allocated. */
+int osbli_profile_enable(osbli_ctx *ctx, int enable);
+
+/* Number of timed launch groups of a class and their summed duration in
+ * milliseconds since profiling was enabled.  Synchronises on the events. */
+int osbli_profile_read(osbli_ctx *ctx, int kernel_class, int64_t *count, double *total_ms);
+
+/* Version of this ABI (OSBLI_ABI_VERSION). */
+int osbli_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OSBLI_H */

@@ -82,6 +82,7 @@ def _load():
                 "orc_deriv_line": (None, [_D, C.c_int64, C.c_int, _D]),
                 "orc_deriv_field": (None, [P, _D, C.c_int, _D]),
                 "orc_viscosity": (C.c_double, [P, C.c_double]),
+                "orc_num_threads": (C.c_int, []),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -260,3 +261,7 @@ def deriv_field(prob, a, d):
 
 def viscosity(prob, T):
     return _load().orc_viscosity(C.byref(params(prob)), float(T))
+
+
+def num_threads():
+    return int(_load().orc_num_threads())

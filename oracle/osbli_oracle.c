@@ -1023,3 +1023,16 @@ int orc_viscous_residual(const orc_params *P, const double *S, const double *J, 
     viscous_residual(P, &g, S, J, U, R);
     return 0;
 }
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* threads the OpenMP loops of this library use */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,416 @@
+// C ABI of libosbli (declared in include/osbli.h): parameter validation,
+// workspace carve-up, context lifecycle and the per-call launch sequences.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace osbli;
+
+// optional HIP-event timing of each kernel class on the launch stream
+struct Prof {
+    int on = 0;
+    std::vector<hipEvent_t> pool;
+    struct Pending { int cls; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    double ms[OSBLI_K_COUNT] = {0};
+    long long cnt[OSBLI_K_COUNT] = {0};
+};
+
+struct osbli_ctx {
+    Prof prof;
+    osbli_params p;
+    Grid g;
+    Phys ph;
+    Metrics m;
+    Layout L;
+    char *ws;
+    size_t ws_bytes;
+    unsigned *flags;
+    unsigned long long *red;
+    double *Racc, *G;
+    hipStream_t last;
+    int device;
+    char err[320];
+};
+
+namespace {
+
+int set_err(osbli_ctx *c, int code, const char *fmt, ...) {
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->err, sizeof(c->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                              \
+    do {                                                                                                \
+        hipError_t e__ = (call);                                                                        \
+        if (e__ != hipSuccess)                                                                          \
+            return set_err((ctx), OSBLI_EDEVICE, "%s: %s", #call, hipGetErrorString(e__));             \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// validates p; fills Grid; returns 0 or a message in buf
+int make_grid(const osbli_params *p, Grid &g, char *buf, size_t nb) {
+    if (!p) { snprintf(buf, nb, "null params"); return -1; }
+    if (p->ndim < 1 || p->ndim > 3) { snprintf(buf, nb, "ndim must be 1..3"); return -1; }
+    g.nd = p->ndim;
+    g.nc = p->ndim + 2;
+    for (int d = 0; d < 3; ++d) {
+        const bool act = d < p->ndim;
+        g.n[d] = act ? p->n[d] : 1;
+        g.h[d] = act ? kGhost : 0;
+        g.e[d] = g.n[d] + 2 * g.h[d];
+        g.periodic[d] = 0;
+        if (!act) {
+            if (p->n[d] != 1 && p->n[d] != 0) { snprintf(buf, nb, "n[%d] must be 1 for unused directions", d); return -1; }
+            continue;
+        }
+        const int k0 = p->bc_kind[d][0], k1 = p->bc_kind[d][1];
+        if (k0 < 0 || k0 > 3 || k1 < 0 || k1 > 3) { snprintf(buf, nb, "bad bc kind in direction %d", d); return -1; }
+        if ((k0 == OSBLI_PERIODIC) != (k1 == OSBLI_PERIODIC)) {
+            snprintf(buf, nb, "periodic must be set on both sides of direction %d", d);
+            return -1;
+        }
+        g.periodic[d] = k0 == OSBLI_PERIODIC;
+        const int64_t nmin = g.periodic[d] ? 6 : 5;
+        if (p->n[d] < nmin) { snprintf(buf, nb, "n[%d] = %lld below %lld", d, (long long)p->n[d], (long long)nmin); return -1; }
+        if (p->n[d] > (int64_t(1) << 24)) { snprintf(buf, nb, "n[%d] too large", d); return -1; }
+    }
+    g.es[0] = 1;
+    g.es[1] = g.e[0];
+    g.es[2] = g.e[0] * g.e[1];
+    g.enpts = g.e[0] * g.e[1] * g.e[2];
+    g.is[0] = 1;
+    g.is[1] = g.n[0];
+    g.is[2] = g.n[0] * g.n[1];
+    g.nint = g.n[0] * g.n[1] * g.n[2];
+    if (!(p->gamma > 1.0)) { snprintf(buf, nb, "gamma must exceed 1"); return -1; }
+    if (p->scheme != OSBLI_WENOZ5 && p->scheme != OSBLI_TENO5) { snprintf(buf, nb, "bad scheme"); return -1; }
+    if (p->form != OSBLI_FORM_FP64) { snprintf(buf, nb, "form %d not available", p->form); return -1; }
+    if (p->sensor != 0) { snprintf(buf, nb, "sensor routing not available"); return -1; }
+    if (p->mesh != OSBLI_MESH_SEPARABLE && p->mesh != OSBLI_MESH_GENERAL) { snprintf(buf, nb, "bad mesh kind"); return -1; }
+    bool walls = false;
+    for (int d = 0; d < p->ndim; ++d)
+        for (int s = 0; s < 2; ++s)
+            walls |= p->bc_kind[d][s] == OSBLI_ISOTHERMAL_WALL || p->bc_kind[d][s] == OSBLI_ADIABATIC_WALL;
+    if ((p->Re > 0.0 || walls) && !(p->Minf > 0.0)) { snprintf(buf, nb, "Minf must be positive"); return -1; }
+    if (p->Re > 0.0 && !(p->Pr > 0.0)) { snprintf(buf, nb, "Pr must be positive"); return -1; }
+    if (p->scheme == OSBLI_TENO5 && !(p->teno_CT > 0.0 && p->teno_CT < 1.0 / 3.0)) {
+        snprintf(buf, nb, "teno_CT must lie in (0, 1/3)");
+        return -1;
+    }
+    if (!(p->eps > 0.0)) { snprintf(buf, nb, "eps must be positive"); return -1; }
+    return 0;
+}
+
+bool general_mesh(const osbli_params *p) { return p->mesh == OSBLI_MESH_GENERAL && p->ndim >= 2; }
+
+Layout make_layout(const osbli_params *p, const Grid &g) {
+    Layout L;
+    size_t off = 0;
+    L.flags = off; off += 256;
+    L.red = off; off += 256;
+    const bool gen = general_mesh(p);
+    for (int d = 0; d < 3; ++d) {
+        L.invh[d] = off;
+        if (!gen && d < g.nd) off += align256(sizeof(double) * g.n[d]);
+    }
+    L.S = off;
+    if (gen) off += align256(sizeof(double) * g.nd * g.nd * g.enpts);
+    L.J = off;
+    if (gen) off += align256(sizeof(double) * g.enpts);
+    // region shared by the per-substage arrays and the one-off coordinate staging
+    L.Racc = off;
+    size_t racc = align256(sizeof(double) * g.nc * g.nint);
+    L.G = L.Racc + racc;
+    size_t gsz = p->Re > 0.0 ? align256(sizeof(double) * g.nd * (g.nd + 1) * g.nint) : 0;
+    size_t stage;
+    if (p->mesh == OSBLI_MESH_GENERAL && g.nd >= 2)
+        stage = align256(sizeof(double) * g.nd * g.nint) + (g.nd == 3 ? align256(sizeof(double) * 9 * g.nint) : 0);
+    else
+        stage = align256(sizeof(double) * (g.n[0] + g.n[1] + g.n[2]));
+    L.stage = off;
+    size_t region = racc + gsz > stage ? racc + gsz : stage;
+    off += region;
+    L.total = off;
+    return L;
+}
+
+Phys make_phys(const osbli_params *p) {
+    Phys ph;
+    ph.gamma = p->gamma;
+    ph.gm1 = p->gamma - 1.0;
+    ph.Re = p->Re;
+    ph.Pr = p->Pr;
+    ph.Minf = p->Minf;
+    ph.M2 = p->Minf * p->Minf;
+    ph.Ts = p->Ts_over_Tref;
+    ph.CT = p->teno_CT;
+    ph.eps = p->eps;
+    ph.viscous = p->Re > 0.0;
+    ph.mu_re = ph.viscous ? 1.0 / p->Re : 0.0;
+    ph.kheat = ph.viscous ? 1.0 / ((p->gamma - 1.0) * ph.M2 * p->Pr * p->Re) : 0.0;
+    const double gp = ph.viscous ? p->gamma / p->Pr : 0.0;
+    ph.nu_fac = gp > 4.0 / 3.0 ? gp : 4.0 / 3.0;
+    ph.sutherland = p->sutherland;
+    ph.scheme = p->scheme;
+    ph.roe = p->roe_avg;
+    return ph;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+hipEvent_t take_event(osbli_ctx *c) {
+    if (!c->prof.pool.empty()) {
+        hipEvent_t e = c->prof.pool.back();
+        c->prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// brackets one launch group with events when profiling is on
+struct Timed {
+    osbli_ctx *c;
+    int cls;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Timed(osbli_ctx *c_, int cls_, hipStream_t s_) : c(c_), cls(cls_), s(s_) {
+        if (c->prof.on && (a = take_event(c)) != nullptr) hipEventRecord(a, s);
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (!b) { c->prof.pool.push_back(a); return; }
+        hipEventRecord(b, s);
+        c->prof.pending.push_back({cls, a, b});
+    }
+};
+
+int resolve_profile(osbli_ctx *c) {
+    for (auto &p : c->prof.pending) {
+        if (hipEventSynchronize(p.b) != hipSuccess) return set_err(c, OSBLI_EDEVICE, "event synchronize failed");
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) return set_err(c, OSBLI_EDEVICE, "event timing failed");
+        c->prof.ms[p.cls] += ms;
+        c->prof.cnt[p.cls] += 1;
+        c->prof.pool.push_back(p.a);
+        c->prof.pool.push_back(p.b);
+    }
+    c->prof.pending.clear();
+    return OSBLI_OK;
+}
+
+// convective sweeps of every direction into R (first stores, later accumulate)
+hipError_t convective_all(osbli_ctx *c, const double *U, double *R, hipStream_t s) {
+    for (int d = 0; d < c->g.nd; ++d) {
+        Timed t(c, OSBLI_K_SWEEP_X + d, s);
+        hipError_t e = launch_convective(c->g, c->ph, c->m, U, R, c->flags, d, d == 0, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int osbli_abi_version(void) { return OSBLI_ABI_VERSION; }
+
+size_t osbli_workspace_bytes(const osbli_params *p) {
+    Grid g;
+    char buf[200];
+    if (make_grid(p, g, buf, sizeof buf) != 0) return 0;
+    return make_layout(p, g).total;
+}
+
+int osbli_init_grid(osbli_ctx **out, const osbli_params *p, const double *x, const double *y, const double *z,
+                    void *workspace, size_t ws_bytes, void *stream) {
+    if (!out) return OSBLI_EINVAL;
+    *out = nullptr;
+    osbli_ctx *c = new (std::nothrow) osbli_ctx();
+    if (!c) return OSBLI_EINVAL;
+    c->err[0] = 0;
+    *out = c;
+    if (make_grid(p, c->g, c->err, sizeof c->err) != 0) return OSBLI_EINVAL;
+    c->p = *p;
+    for (int d = p->ndim; d < 3; ++d) c->p.n[d] = 1;
+    c->ph = make_phys(p);
+    c->L = make_layout(p, c->g);
+    if (!workspace) return set_err(c, OSBLI_EINVAL, "null workspace");
+    if (ws_bytes < c->L.total)
+        return set_err(c, OSBLI_ENOSPACE, "workspace %zu bytes, need %zu", ws_bytes, c->L.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return set_err(c, OSBLI_EINVAL, "workspace not 256-byte aligned");
+    const double *X[3] = {x, y, z};
+    for (int d = 0; d < p->ndim; ++d)
+        if (!X[d]) return set_err(c, OSBLI_EINVAL, "coordinates of direction %d missing", d);
+    HIP_TRY(c, hipGetDevice(&c->device));
+    hipStream_t s = as_stream(stream);
+    c->last = s;
+    c->ws = static_cast<char *>(workspace);
+    c->ws_bytes = ws_bytes;
+    c->flags = reinterpret_cast<unsigned *>(c->ws + c->L.flags);
+    c->red = reinterpret_cast<unsigned long long *>(c->ws + c->L.red);
+    c->Racc = reinterpret_cast<double *>(c->ws + c->L.Racc);
+    c->G = reinterpret_cast<double *>(c->ws + c->L.G);
+    HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long *>(c->ws), 0ull, 64, s));
+
+    const bool gen = general_mesh(p);
+    c->m.general = gen;
+    const Grid &g = c->g;
+    double *stage = reinterpret_cast<double *>(c->ws + c->L.stage);
+    if (!gen) {
+        // separable: 1D coordinate arrays (a 1D or separable mesh)
+        int64_t off = 0;
+        for (int d = 0; d < p->ndim; ++d) {
+            if (p->mesh == OSBLI_MESH_SEPARABLE) {
+                HIP_TRY(c, hipMemcpyAsync(stage + off, X[d], sizeof(double) * g.n[d], hipMemcpyHostToDevice, s));
+            } else {
+                // 1D general mesh == separable
+                HIP_TRY(c, hipMemcpyAsync(stage + off, X[d], sizeof(double) * g.n[d], hipMemcpyHostToDevice, s));
+            }
+            off += g.n[d];
+        }
+        double *invh[3];
+        for (int d = 0; d < 3; ++d) {
+            invh[d] = reinterpret_cast<double *>(c->ws + c->L.invh[d]);
+            c->m.invh[d] = d < p->ndim ? invh[d] : nullptr;
+        }
+        HIP_TRY(c, launch_metrics_separable(g, stage, invh, p->period, s));
+        c->m.S = nullptr;
+        c->m.J = nullptr;
+    } else {
+        for (int d = 0; d < p->ndim; ++d)
+            HIP_TRY(c, hipMemcpyAsync(stage + d * g.nint, X[d], sizeof(double) * g.nint, hipMemcpyHostToDevice, s));
+        double *S = reinterpret_cast<double *>(c->ws + c->L.S);
+        double *J = reinterpret_cast<double *>(c->ws + c->L.J);
+        double *extra = stage + ((sizeof(double) * g.nd * g.nint + 255) / 256) * 32;
+        HIP_TRY(c, launch_metrics_general(g, stage, extra, S, J, p->period, s));
+        c->m.S = S;
+        c->m.J = J;
+        for (int d = 0; d < 3; ++d) c->m.invh[d] = nullptr;
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return OSBLI_OK;
+}
+
+int osbli_apply_bc(osbli_ctx *c, double *U, void *stream) {
+    if (!c || !U) return set_err(c, OSBLI_EINVAL, "null argument");
+    hipStream_t s = as_stream(stream);
+    c->last = s;
+    Timed t(c, OSBLI_K_BC, s);
+    HIP_TRY(c, launch_bc(c->g, c->ph, c->p, U, s));
+    return OSBLI_OK;
+}
+
+int osbli_residual(osbli_ctx *c, const double *U, double *R, void *stream) {
+    if (!c || !U || !R) return set_err(c, OSBLI_EINVAL, "null argument");
+    if ((const void *)U == (const void *)R) return set_err(c, OSBLI_EINVAL, "R aliases U");
+    hipStream_t s = as_stream(stream);
+    c->last = s;
+    if (c->ph.viscous) {
+        Timed t(c, OSBLI_K_VISC_FLUX, s);
+        HIP_TRY(c, launch_viscous_fluxes(c->g, c->ph, c->m, U, c->G, s));
+    }
+    HIP_TRY(c, convective_all(c, U, R, s));
+    if (c->ph.viscous) {
+        Timed t(c, OSBLI_K_FINISH, s);
+        HIP_TRY(c, launch_finish(c->g, c->ph, c->m, R, c->G, R, 0, 0.0, nullptr, nullptr, 0, s));
+    }
+    return OSBLI_OK;
+}
+
+int osbli_rk_substep(osbli_ctx *c, int stage, double dt, double *U, double *dU, void *stream) {
+    if (!c || !U || !dU) return set_err(c, OSBLI_EINVAL, "null argument");
+    if (stage < 0 || stage > 2) return set_err(c, OSBLI_EINVAL, "stage must be 0..2");
+    if ((void *)U == (void *)dU) return set_err(c, OSBLI_EINVAL, "dU aliases U");
+    hipStream_t s = as_stream(stream);
+    c->last = s;
+    if (c->ph.viscous) {
+        Timed t(c, OSBLI_K_VISC_FLUX, s);
+        HIP_TRY(c, launch_viscous_fluxes(c->g, c->ph, c->m, U, c->G, s));
+    }
+    HIP_TRY(c, convective_all(c, U, c->Racc, s));
+    {
+        Timed t(c, OSBLI_K_FINISH, s);
+        HIP_TRY(c, launch_finish(c->g, c->ph, c->m, c->Racc, c->G, nullptr, stage, dt, U, dU, 1, s));
+    }
+    return OSBLI_OK;
+}
+
+int osbli_compute_dt(osbli_ctx *c, const double *U, double cfl, double *dt_out, void *stream) {
+    if (!c || !U || !dt_out) return set_err(c, OSBLI_EINVAL, "null argument");
+    hipStream_t s = as_stream(stream);
+    c->last = s;
+    {
+        Timed t(c, OSBLI_K_DT, s);
+        HIP_TRY(c, launch_fill_u64(c->red, 0ull, 1, s));
+        HIP_TRY(c, launch_dt(c->g, c->ph, c->m, U, c->red, s));
+    }
+    unsigned long long bits = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bits, c->red, sizeof bits, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    double smax;
+    memcpy(&smax, &bits, sizeof smax);
+    *dt_out = smax > 0.0 ? cfl / smax : 0.0;
+    if (!(smax < __builtin_inf())) return set_err(c, OSBLI_ENONPHYS, "non-physical state in dt reduction");
+    return OSBLI_OK;
+}
+
+int osbli_check(osbli_ctx *c) {
+    if (!c) return OSBLI_EINVAL;
+    unsigned f = 0;
+    HIP_TRY(c, hipMemcpyAsync(&f, c->flags, sizeof f, hipMemcpyDeviceToHost, c->last));
+    HIP_TRY(c, hipStreamSynchronize(c->last));
+    if (f) {
+        HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long *>(c->flags), 0ull, 1, c->last));
+        HIP_TRY(c, hipStreamSynchronize(c->last));
+        return set_err(c, OSBLI_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or NaN) met by a kernel");
+    }
+    return OSBLI_OK;
+}
+
+const char *osbli_last_error(const osbli_ctx *c) { return c ? c->err : "null context"; }
+
+int osbli_profile_enable(osbli_ctx *c, int enable) {
+    if (!c) return OSBLI_EINVAL;
+    int rc = resolve_profile(c);
+    if (rc != OSBLI_OK) return rc;
+    for (int k = 0; k < OSBLI_K_COUNT; ++k) {
+        c->prof.ms[k] = 0.0;
+        c->prof.cnt[k] = 0;
+    }
+    c->prof.on = enable != 0;
+    return OSBLI_OK;
+}
+
+int osbli_profile_read(osbli_ctx *c, int kernel_class, int64_t *count, double *total_ms) {
+    if (!c || kernel_class < 0 || kernel_class >= OSBLI_K_COUNT || !count || !total_ms)
+        return set_err(c, OSBLI_EINVAL, "bad profile query");
+    int rc = resolve_profile(c);
+    if (rc != OSBLI_OK) return rc;
+    *count = c->prof.cnt[kernel_class];
+    *total_ms = c->prof.ms[kernel_class];
+    return OSBLI_OK;
+}
+
+void osbli_destroy(osbli_ctx *c) {
+    if (!c) return;
+    resolve_profile(c);
+    for (hipEvent_t e : c->prof.pool) hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,416 @@
+// Convective residual: characteristic LLF flux reconstruction (WENO-Z5 or
+// TENO5) in each direction, section 2.2 (enumerated algorithm), sections
+// 2.3-2.5 for the reconstructions.
+//
+// Thread mapping ("pencil march"): a thread owns one grid line along the sweep
+// direction and a segment of it; neighbouring lanes own neighbouring lines
+// (adjacent in x for the y and z sweeps, so every load is coalesced).  Each
+// thread keeps a six-point register window of the stencil (state + 1/rho, p,
+// a computed once per point), marches along the line, computes one interface
+// flux per step and the flux difference of the node behind it, so each
+// interface is evaluated once (plus one per segment).
+//
+// The characteristic algebra is written in the local frame (n, t1, t2) of the
+// interface: with f_k = u_n U_k + p_k (0, n, u_n) the projected flux is
+// g_kj = u_n,k V_kj + p_k (l_j,m . n + l_j,E u_n,k), so only V = L U is
+// formed per point, and L, R are never stored as matrices.
+#include "internal.hpp"
+
+namespace osbli {
+namespace {
+
+template <int ND>
+struct Pt {
+    double U[ND + 2];
+    double ri, p, a;
+};
+
+// Local-frame view of one stencil point: normal / tangential momentum.
+template <int ND>
+struct Loc {
+    double r, mn, mt[2], E, p, a, ri;
+};
+
+template <int ND>
+__device__ __forceinline__ void load_point(const double *__restrict__ U, int64_t e, int64_t cs,
+                                           const Phys &ph, Pt<ND> &w, bool &bad) {
+#pragma unroll
+    for (int c = 0; c < ND + 2; ++c) w.U[c] = U[e + c * cs];
+    const double ri = 1.0 / w.U[0];
+    double ke = 0.0;
+#pragma unroll
+    for (int m = 0; m < ND; ++m) ke += w.U[1 + m] * w.U[1 + m];
+    const double p = ph.gm1 * (w.U[ND + 1] - 0.5 * ke * ri);
+    w.ri = ri;
+    w.p = p;
+    w.a = sqrt(ph.gamma * p * ri);
+    bad |= !(w.U[0] > 0.0 && p > 0.0);
+}
+
+// Fifth-order WENO-Z / TENO reconstruction at x_{i+1/2} from f_{i-2..i+2}.
+// Candidate stencils S_r = {i-r .. i-r+2}, Jiang-Shu indicators,
+// tau_5 = |beta_0 - beta_2|; WENO-Z alpha_r = d_r (1 + (tau/(beta_r+eps))^2);
+// TENO gamma_r = (1 + tau/(beta_r+eps))^6, stencil r cut when
+// gamma_r / sum(gamma) < C_T (evaluated as gamma_r < C_T * sum), weights
+// d_r delta_r / sum(d delta).
+template <int SCHEME>
+__device__ __forceinline__ double recon5(double fm2, double fm1, double f0, double fp1, double fp2,
+                                         double CT, double eps) {
+    const double q0 = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
+    const double q1 = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
+    const double q2 = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
+    double s, t;
+    s = f0 - 2.0 * fp1 + fp2;
+    t = 3.0 * f0 - 4.0 * fp1 + fp2;
+    const double b0 = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    s = fm1 - 2.0 * f0 + fp1;
+    t = fm1 - fp1;
+    const double b1 = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    s = fm2 - 2.0 * fm1 + f0;
+    t = fm2 - 4.0 * fm1 + 3.0 * f0;
+    const double b2 = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    const double tau = fabs(b0 - b2);
+    if (SCHEME == OSBLI_WENOZ5) {
+        const double x0 = tau / (b0 + eps), x1 = tau / (b1 + eps), x2 = tau / (b2 + eps);
+        const double a0 = 0.3 * (1.0 + x0 * x0);
+        const double a1 = 0.6 * (1.0 + x1 * x1);
+        const double a2 = 0.1 * (1.0 + x2 * x2);
+        return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+    } else {
+        double c0 = 1.0 + tau / (b0 + eps), c1 = 1.0 + tau / (b1 + eps), c2 = 1.0 + tau / (b2 + eps);
+        c0 = c0 * c0 * c0;
+        c1 = c1 * c1 * c1;
+        c2 = c2 * c2 * c2;
+        const double g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2;
+        const double lim = CT * (g0 + g1 + g2);
+        const double w0 = g0 < lim ? 0.0 : 0.3;
+        const double w1 = g1 < lim ? 0.0 : 0.6;
+        const double w2 = g2 < lim ? 0.0 : 0.1;
+        return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+    }
+}
+
+// LLF split of one characteristic field over the six points and the two
+// reconstructions: ghat = recon+(g+_{i-2..i+2}) + recon-(g-_{i+3..i-1}).
+template <int SCHEME>
+__device__ __forceinline__ double split_recon(const double (&V)[6], const double (&g)[6], double alpha,
+                                              const Phys &ph) {
+    double gp[6], gm[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        gp[k] = 0.5 * (g[k] + alpha * V[k]);
+        gm[k] = 0.5 * (g[k] - alpha * V[k]);
+    }
+    return recon5<SCHEME>(gp[0], gp[1], gp[2], gp[3], gp[4], ph.CT, ph.eps) +
+           recon5<SCHEME>(gm[5], gm[4], gm[3], gm[2], gm[1], ph.CT, ph.eps);
+}
+
+// Interface flux in the local frame (unit |S|).  Outputs: mass, normal
+// momentum, tangential momenta, energy.
+template <int ND, int SCHEME>
+__device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph, double &Fr, double &Fn,
+                                          double (&Ft)[2], double &FE) {
+    constexpr int NT = ND - 1;  // tangents
+    // averaged state at the half node (Roe, or arithmetic mean with unit weights)
+    double sl = 1.0, sr = 1.0;
+    if (ph.roe) {
+        sl = sqrt(P[2].r);
+        sr = sqrt(P[3].r);
+    }
+    const double iw = 1.0 / (sl + sr);
+    const double un = (sl * (P[2].mn * P[2].ri) + sr * (P[3].mn * P[3].ri)) * iw;
+    double ut[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NT; ++s) ut[s] = (sl * (P[2].mt[s] * P[2].ri) + sr * (P[3].mt[s] * P[3].ri)) * iw;
+    const double Hh = (sl * ((P[2].E + P[2].p) * P[2].ri) + sr * ((P[3].E + P[3].p) * P[3].ri)) * iw;
+    double K = un * un;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) K += ut[s] * ut[s];
+    K *= 0.5;
+    const double ah = sqrt(ph.gm1 * (Hh - K));
+    const double ia = 1.0 / ah;
+    const double b = ph.gm1 * ia * ia;
+
+    double unk[6], A[6], B[6], am[6], ap[6], a0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        unk[k] = P[k].mn * P[k].ri;
+        double um = un * P[k].mn;
+#pragma unroll
+        for (int s = 0; s < NT; ++s) um += ut[s] * P[k].mt[s];
+        A[k] = b * (K * P[k].r - um + P[k].E);
+        B[k] = (un * P[k].r - P[k].mn) * ia;
+        am[k] = fabs(unk[k] - P[k].a);
+        ap[k] = fabs(unk[k] + P[k].a);
+        a0 = fmax(a0, fabs(unk[k]));
+    }
+    double aminus = am[0], aplus = ap[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) {
+        aminus = fmax(aminus, am[k]);
+        aplus = fmax(aplus, ap[k]);
+    }
+    double V[6], g[6];
+    // field u_n - a
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = 0.5 * (A[k] + B[k]);
+        g[k] = unk[k] * V[k] + P[k].p * (0.5 * b * unk[k] - 0.5 * (b * un + ia));
+    }
+    const double h0 = split_recon<SCHEME>(V, g, aminus, ph);
+    // field u_n + a
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = 0.5 * (A[k] - B[k]);
+        g[k] = unk[k] * V[k] + P[k].p * (0.5 * b * unk[k] - 0.5 * (b * un - ia));
+    }
+    const double h4 = split_recon<SCHEME>(V, g, aplus, ph);
+    // entropy field
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = P[k].r - A[k];
+        g[k] = unk[k] * V[k] + P[k].p * (b * (un - unk[k]));
+    }
+    const double h1 = split_recon<SCHEME>(V, g, a0, ph);
+    // shear fields
+    double ht[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            V[k] = P[k].mt[s] - ut[s] * P[k].r;
+            g[k] = unk[k] * V[k];
+        }
+        ht[s] = split_recon<SCHEME>(V, g, a0, ph);
+    }
+    // back to physical space: F = R ghat
+    const double hs = h0 + h1 + h4;
+    const double hd = h4 - h0;
+    Fr = hs;
+    Fn = un * hs + ah * hd;
+    FE = Hh * (h0 + h4) + ah * un * hd + K * h1;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        Ft[s] = ut[s] * hs + ht[s];
+        FE += ut[s] * ht[s];
+    }
+}
+
+template <int ND, int DIR>
+struct Axes {
+    static constexpr int T1 = (DIR + 1) % ND;
+    static constexpr int T2 = (DIR + 2) % ND;
+};
+
+// One convective sweep along DIR.  first != 0: R = contribution, else R +=.
+template <int ND, int DIR, int SCHEME, bool GEN>
+__global__ void __launch_bounds__(256)
+k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t seg,
+        int64_t nseg, int first, unsigned *flags) {
+    constexpr int NC = ND + 2;
+    constexpr int NT = ND - 1;
+    constexpr int O1 = DIR == 0 ? 1 : 0;
+    constexpr int O2 = DIR == 2 ? 1 : 2;
+    const int64_t n1 = g.n[O1], n2 = g.n[O2], N = g.n[DIR];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t a = t % n1;
+    const int64_t rr = t / n1;
+    const int64_t bb = rr % n2;
+    const int64_t sg = rr / n2;
+    if (sg >= nseg) return;
+    const int64_t p0 = sg * seg;
+    const int64_t p1 = p0 + seg < N ? p0 + seg : N;
+    int64_t q[3];
+    q[DIR] = 0;
+    q[O1] = a;
+    q[O2] = bb;
+    const int64_t base = ext_index(g, q[0], q[1], q[2]);
+    const int64_t st = g.es[DIR];
+    const int64_t cs = g.enpts;
+    const int64_t ibase = int_index(g, q[0], q[1], q[2]);
+    const int64_t ist = g.is[DIR];
+    bool bad = false;
+
+    Pt<ND> w[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) load_point<ND>(U, base + (p0 - 3 + k) * st, cs, ph, w[k], bad);
+
+    // general meshes: node area vectors S_DIR at f-1 .. f+2 for interface f+1/2
+    double Sw[4][3];
+    if (GEN) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < ND; ++c)
+                Sw[k][c] = m.S[(DIR * ND + c) * cs + base + (p0 - 2 + k) * st];
+    }
+
+    double Fp[NC];
+    for (int64_t f = p0 - 1; f < p1; ++f) {
+        if (f >= p0) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) w[k] = w[k + 1];
+            load_point<ND>(U, base + (f + 3) * st, cs, ph, w[5], bad);
+            if (GEN) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int c = 0; c < ND; ++c) Sw[k][c] = Sw[k + 1][c];
+#pragma unroll
+                for (int c = 0; c < ND; ++c) Sw[3][c] = m.S[(DIR * ND + c) * cs + base + (f + 2) * st];
+            }
+        }
+        Loc<ND> P[6];
+        double F[NC];
+        double Smag = 1.0;
+        double nv[3] = {0.0, 0.0, 0.0}, t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
+        if (!GEN) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                P[k].r = w[k].U[0];
+                P[k].mn = w[k].U[1 + DIR];
+                if (NT >= 1) P[k].mt[0] = w[k].U[1 + Axes<ND, DIR>::T1];
+                if (NT >= 2) P[k].mt[1] = w[k].U[1 + Axes<ND, DIR>::T2];
+                P[k].E = w[k].U[ND + 1];
+                P[k].p = w[k].p;
+                P[k].a = w[k].a;
+                P[k].ri = w[k].ri;
+            }
+        } else {
+            double Sh[3] = {0.0, 0.0, 0.0};
+            double s2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < ND; ++c) {
+                Sh[c] = (-Sw[0][c] + 7.0 * Sw[1][c] + 7.0 * Sw[2][c] - Sw[3][c]) / 12.0;
+                s2 += Sh[c] * Sh[c];
+            }
+            Smag = sqrt(s2);
+#pragma unroll
+            for (int c = 0; c < ND; ++c) nv[c] = Sh[c] / Smag;
+            // tangent basis: t1 = normalise(e_{DIR+1} - (e_{DIR+1}.n) n), t2 = n x t1
+            if (ND >= 2) {
+                constexpr int TE = (DIR + 1) % (ND > 1 ? ND : 1);
+                const double en = nv[TE];
+                double tn = 0.0;
+#pragma unroll
+                for (int c = 0; c < ND; ++c) {
+                    t1[c] = (c == TE ? 1.0 : 0.0) - en * nv[c];
+                    tn += t1[c] * t1[c];
+                }
+                tn = sqrt(tn);
+#pragma unroll
+                for (int c = 0; c < ND; ++c) t1[c] /= tn;
+                if (ND == 3) {
+                    t2[0] = nv[1] * t1[2] - nv[2] * t1[1];
+                    t2[1] = nv[2] * t1[0] - nv[0] * t1[2];
+                    t2[2] = nv[0] * t1[1] - nv[1] * t1[0];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                double mn = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+                for (int c = 0; c < ND; ++c) {
+                    mn += w[k].U[1 + c] * nv[c];
+                    m1 += w[k].U[1 + c] * t1[c];
+                    m2 += w[k].U[1 + c] * t2[c];
+                }
+                P[k].r = w[k].U[0];
+                P[k].mn = mn;
+                P[k].mt[0] = m1;
+                P[k].mt[1] = m2;
+                P[k].E = w[k].U[ND + 1];
+                P[k].p = w[k].p;
+                P[k].a = w[k].a;
+                P[k].ri = w[k].ri;
+            }
+        }
+        double Fr, Fn, Ft[2], FE;
+        char_flux<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
+        F[0] = Fr * Smag;
+        F[NC - 1] = FE * Smag;
+        if (!GEN) {
+            F[1 + DIR] = Fn;
+            if (NT >= 1) F[1 + Axes<ND, DIR>::T1] = Ft[0];
+            if (NT >= 2) F[1 + Axes<ND, DIR>::T2] = Ft[1];
+        } else {
+#pragma unroll
+            for (int c = 0; c < ND; ++c) {
+                double v = Fn * nv[c];
+                if (NT >= 1) v += Ft[0] * t1[c];
+                if (NT >= 2) v += Ft[1] * t2[c];
+                F[1 + c] = v * Smag;
+            }
+        }
+        if (f >= p0) {
+            const double sc = GEN ? m.J[base + f * st] : m.invh[DIR][f];
+            const int64_t oi = ibase + f * ist;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double v = -sc * (F[c] - Fp[c]);
+                double *dst = R + c * g.nint + oi;
+                if (first) *dst = v;
+                else *dst += v;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Fp[c] = F[c];
+    }
+    if (bad) atomicOr(flags, kFlagNonPhys);
+}
+
+template <int ND, int DIR, int SCHEME, bool GEN>
+hipError_t launch_one(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
+                      unsigned *flags, int first, hipStream_t s) {
+    constexpr int O1 = DIR == 0 ? 1 : 0;
+    constexpr int O2 = DIR == 2 ? 1 : 2;
+    const int64_t lines = g.n[O1] * g.n[O2];
+    const int64_t N = g.n[DIR];
+    const int64_t target = int64_t(1) << 18;  // threads in flight to aim for
+    int64_t seg = (N * lines + target - 1) / target;
+    if (seg < 8) seg = 8;
+    if (seg > N) seg = N;
+    const int64_t nseg = (N + seg - 1) / seg;
+    const int64_t threads = lines * nseg;
+    const int bs = 256;
+    const int64_t nb = (threads + bs - 1) / bs;
+    hipLaunchKernelGGL((k_sweep<ND, DIR, SCHEME, GEN>), dim3((unsigned)nb), dim3(bs), 0, s, U, R, g, ph, m,
+                       seg, nseg, first, flags);
+    return hipGetLastError();
+}
+
+template <int ND, int SCHEME, bool GEN>
+hipError_t launch_dir(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
+                      unsigned *flags, int dir, int first, hipStream_t s) {
+    if (dir == 0) return launch_one<ND, 0, SCHEME, GEN>(g, ph, m, U, R, flags, first, s);
+    if (dir == 1) return launch_one<ND, (ND >= 2 ? 1 : 0), SCHEME, GEN>(g, ph, m, U, R, flags, first, s);
+    return launch_one<ND, (ND >= 3 ? 2 : 0), SCHEME, GEN>(g, ph, m, U, R, flags, first, s);
+}
+
+template <int ND, int SCHEME>
+hipError_t launch_mesh(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
+                       unsigned *flags, int dir, int first, hipStream_t s) {
+    if (ND >= 2 && m.general) return launch_dir<ND, SCHEME, (ND >= 2)>(g, ph, m, U, R, flags, dir, first, s);
+    return launch_dir<ND, SCHEME, false>(g, ph, m, U, R, flags, dir, first, s);
+}
+
+template <int ND>
+hipError_t launch_scheme(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
+                         unsigned *flags, int dir, int first, hipStream_t s) {
+    if (ph.scheme == OSBLI_WENOZ5) return launch_mesh<ND, OSBLI_WENOZ5>(g, ph, m, U, R, flags, dir, first, s);
+    return launch_mesh<ND, OSBLI_TENO5>(g, ph, m, U, R, flags, dir, first, s);
+}
+
+}  // namespace
+
+hipError_t launch_convective(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
+                             unsigned *flags, int dir, int first, hipStream_t s) {
+    if (dir < 0 || dir >= g.nd) return hipErrorInvalidValue;
+    switch (g.nd) {
+        case 1: return launch_scheme<1>(g, ph, m, U, R, flags, dir, first, s);
+        case 2: return launch_scheme<2>(g, ph, m, U, R, flags, dir, first, s);
+        default: return launch_scheme<3>(g, ph, m, U, R, flags, dir, first, s);
+    }
+}
+
+}  // namespace osbli

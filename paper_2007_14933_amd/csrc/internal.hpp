@@ -1,0 +1,84 @@
+// Internal declarations shared by the HIP translation units of libosbli.
+// Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "osbli.h"
+
+namespace osbli {
+
+constexpr int kGhost = OSBLI_NGHOST;
+
+// Index space of one problem.  "ext" = ghost-extended grid of the state U,
+// "int" = compact interior grid of R, dU and the viscous fluxes.
+struct Grid {
+    int nd, nc;
+    int64_t n[3];    // interior nodes per direction (1 when unused)
+    int64_t h[3];    // ghosts per side (3 when active, else 0)
+    int64_t e[3];    // extended extents
+    int64_t es[3];   // extended strides
+    int64_t enpts;   // extended nodes (component stride of U)
+    int64_t is[3];   // interior strides
+    int64_t nint;    // interior nodes (component stride of R, dU)
+    int periodic[3];
+};
+
+// Physical and scheme constants, precomputed once.
+struct Phys {
+    double gamma, gm1, Re, Pr, Minf, M2, Ts, CT, eps;
+    double mu_re;      // 1/Re
+    double kheat;      // 1/((gamma-1) M^2 Pr Re)
+    double nu_fac;     // max(4/3, gamma/Pr)
+    int sutherland, scheme, roe, viscous;
+};
+
+// Metric terms.  Separable meshes keep 1/h_d per direction (h_d = D_d x_d);
+// general meshes keep node area vectors S[d][m] on the extended grid and J.
+struct Metrics {
+    int general;
+    const double *invh[3];   // separable: n[d] values each
+    const double *S;         // general: nd*nd components, stride enpts
+    const double *J;         // general: enpts
+};
+
+// Device workspace carve-up (byte offsets into the caller's buffer).
+struct Layout {
+    size_t flags, red, invh[3], S, J, Racc, G, stage, total;
+};
+
+__host__ __device__ inline int64_t ext_index(const Grid &g, int64_t i, int64_t j, int64_t k) {
+    return (i + g.h[0]) + (j + g.h[1]) * g.es[1] + (k + g.h[2]) * g.es[2];
+}
+__host__ __device__ inline int64_t int_index(const Grid &g, int64_t i, int64_t j, int64_t k) {
+    return i + j * g.is[1] + k * g.is[2];
+}
+
+// flags word bits
+constexpr unsigned kFlagNonPhys = 1u;
+
+// Low-storage RK3 (2N form) coefficients.
+__host__ __device__ inline double rk_A(int s) { return s == 0 ? 0.0 : (s == 1 ? -5.0 / 9.0 : -153.0 / 128.0); }
+__host__ __device__ inline double rk_B(int s) { return s == 0 ? 1.0 / 3.0 : (s == 1 ? 15.0 / 16.0 : 8.0 / 15.0); }
+
+// ---- launchers (each returns hipError_t of the launch) ----
+hipError_t launch_metrics_separable(const Grid &g, const double *coord1d, double *invh_out[3],
+                                    const double period[3], hipStream_t s);
+hipError_t launch_metrics_general(const Grid &g, const double *coords, double *stage,
+                                  double *S, double *J, const double period[3], hipStream_t s);
+hipError_t launch_bc(const Grid &g, const Phys &ph, const osbli_params &p, double *U, hipStream_t s);
+// one convective sweep along dir; first != 0 stores R, otherwise accumulates
+hipError_t launch_convective(const Grid &g, const Phys &ph, const Metrics &m, const double *U,
+                             double *R, unsigned *flags, int dir, int first, hipStream_t s);
+hipError_t launch_viscous_fluxes(const Grid &g, const Phys &ph, const Metrics &m, const double *U,
+                                 double *G, hipStream_t s);
+// mode 0: R_out = Racc + viscous;  mode 1: RK update of U, dU with Racc + viscous
+hipError_t launch_finish(const Grid &g, const Phys &ph, const Metrics &m, const double *Racc,
+                         const double *G, double *Rout, int stage, double dt, double *U, double *dU,
+                         int mode, hipStream_t s);
+hipError_t launch_dt(const Grid &g, const Phys &ph, const Metrics &m, const double *U,
+                     unsigned long long *slot, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int n, hipStream_t s);
+
+}  // namespace osbli

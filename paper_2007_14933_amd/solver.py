@@ -1,0 +1,143 @@
+"""Driver of the HIP library: device buffers owned by PyTorch, calls through
+the C ABI.  PyTorch supplies memory and streams only; every step of the
+residual and the update runs in libosbli's kernels.
+
+    s = Solver(problem)            # allocates U, dU, workspace on cuda:0
+    s.run(nsteps, cfl=0.5)         # BCs at t=0, then dt + 3 substeps per step
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .inputs import NGHOST
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    def __init__(self, prob, device="cuda:0", form=B.FORM_FP64, sensor=0, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU (torch.cuda is not available)")
+        self.lib = B.load()
+        self.prob = prob
+        self.device = torch.device(device)
+        self.params = B.make_params(prob, form=form, sensor=sensor)
+        nbytes = self.lib.osbli_workspace_bytes(C.byref(self.params))
+        if nbytes == 0:
+            raise B.OsbliError(B.OSBLI_EINVAL, "invalid parameters for %s" % prob.name)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = self.ws.data_ptr() + off
+        self.ws_bytes = nbytes
+        coords = self._coords()
+        self.ctx = C.c_void_p()
+        rc = self.lib.osbli_init_grid(C.byref(self.ctx), C.byref(self.params), *coords,
+                                      C.c_void_p(self.ws_ptr), C.c_size_t(self.ws_bytes), self._s())
+        if rc != 0:
+            msg = self.lib.osbli_last_error(self.ctx).decode() if self.ctx else ""
+            raise B.OsbliError(rc, msg)
+        self.U = torch.from_numpy(np.ascontiguousarray(prob.U0)).to(self.device)
+        nd = prob.ndim
+        ishape = (nd + 2,) + tuple(prob.n[d] if d < nd else 1 for d in (2, 1, 0))
+        self.dU = torch.zeros(ishape, dtype=torch.float64, device=self.device)
+        self.t = 0.0
+        self.nsteps_done = 0
+
+    def _s(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def _coords(self):
+        p = self.prob
+        self._coord_keep = []
+        out = []
+        for d in range(3):
+            if d >= p.ndim:
+                out.append(None)
+                continue
+            if p.coords1d is not None:
+                a = np.ascontiguousarray(p.coords1d[d], dtype=np.float64)
+            else:
+                a = np.ascontiguousarray(p.coords_full[d], dtype=np.float64).ravel()
+            self._coord_keep.append(a)
+            out.append(a.ctypes.data_as(C.POINTER(C.c_double)))
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.osbli_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # ---- thin wrappers of the ABI ----
+    def apply_bc(self, U=None):
+        U = self.U if U is None else U
+        B.check(self.lib.osbli_apply_bc(self.ctx, _ptr(U), self._s()), self.ctx)
+
+    def residual(self, U=None, R=None):
+        U = self.U if U is None else U
+        if R is None:
+            R = torch.empty_like(self.dU)
+        B.check(self.lib.osbli_residual(self.ctx, _ptr(U), _ptr(R), self._s()), self.ctx)
+        return R
+
+    def substep(self, stage, dt):
+        B.check(self.lib.osbli_rk_substep(self.ctx, int(stage), float(dt), _ptr(self.U), _ptr(self.dU), self._s()),
+                self.ctx)
+
+    def compute_dt(self, cfl):
+        out = C.c_double(0.0)
+        B.check(self.lib.osbli_compute_dt(self.ctx, _ptr(self.U), float(cfl), C.byref(out), self._s()), self.ctx)
+        return out.value
+
+    def profile(self, enable=True):
+        B.check(self.lib.osbli_profile_enable(self.ctx, int(enable)), self.ctx)
+
+    def profile_read(self):
+        """{kernel class: (launch groups, total ms)} since profiling was enabled."""
+        out = {}
+        for k, name in enumerate(B.K_NAMES):
+            cnt, ms = C.c_int64(0), C.c_double(0.0)
+            B.check(self.lib.osbli_profile_read(self.ctx, k, C.byref(cnt), C.byref(ms)), self.ctx)
+            out[name] = (cnt.value, ms.value)
+        return out
+
+    def check(self):
+        B.check(self.lib.osbli_check(self.ctx), self.ctx)
+
+    # ---- time loop (section 2.7 ordering: residual, update, BCs) ----
+    def step(self, dt):
+        for s in range(3):
+            self.substep(s, dt)
+            self.apply_bc()
+        self.t += dt
+        self.nsteps_done += 1
+
+    def run(self, nsteps, cfl=0.5, dt_fixed=0.0, t_end=0.0, start_bc=True):
+        if start_bc:
+            self.apply_bc()
+        for _ in range(int(nsteps)):
+            if t_end > 0.0 and self.t >= t_end:
+                break
+            dt = dt_fixed if dt_fixed > 0.0 else self.compute_dt(cfl)
+            if t_end > 0.0 and self.t + dt > t_end:
+                dt = t_end - self.t
+            self.step(dt)
+        return self.t
+
+    def state(self):
+        torch.cuda.synchronize(self.device)
+        return self.U.cpu().numpy()
+
+    def interior(self):
+        nd = self.prob.ndim
+        sl = [slice(None)] + [slice(NGHOST, -NGHOST) if d < nd else slice(None) for d in (2, 1, 0)]
+        return self.state()[tuple(sl)]

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol the public header declares, sizes its workspace, and rejects
+invalid parameters before any device call."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2007_14933_amd import binding as B
+from paper_2007_14933_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "osbli.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(osbli_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2007_14933_amd import build
+        build.build()
+    return B.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert "osbli_rk_substep" in names and "osbli_init_grid" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(B.exported_symbols()) | {"osbli_abi_version"}
+    assert lib.osbli_abi_version() == 1
+
+
+def test_params_struct_matches_header_layout(lib):
+    # the ctypes mirror must have the size the C compiler gives the struct
+    assert C.sizeof(B.Params) == 8 + 24 + 32 + 8 + 24 + 16 + 24 + 48 + 24
+
+
+def _ws(prob, **kw):
+    p = B.make_params(prob, **kw)
+    return B.load().osbli_workspace_bytes(C.byref(p))
+
+
+def test_workspace_sizes(lib):
+    tgv = I.tgv(16)
+    n = 16 ** 3
+    ws = _ws(tgv)
+    # residual accumulator 5n + viscous fluxes 12n doubles, plus small tables
+    assert ws >= 8 * (5 * n + 12 * n)
+    assert ws < 8 * (5 * n + 12 * n) + 64 * 1024
+    sod = I.sod(400)
+    assert 8 * 3 * 400 <= _ws(sod) < 64 * 1024
+
+
+@pytest.mark.parametrize("mutate,why", [
+    (lambda p: setattr(p, "ndim", 4), "ndim"),
+    (lambda p: p.bc_kind[0].__setitem__(1, B.EXTRAPOLATE), "periodic on one side"),
+    (lambda p: p.n.__setitem__(0, 5), "too few periodic nodes"),
+    (lambda p: setattr(p, "scheme", 7), "scheme"),
+    (lambda p: setattr(p, "gamma", 1.0), "gamma"),
+    (lambda p: setattr(p, "teno_CT", 0.5), "C_T"),
+    (lambda p: setattr(p, "form", 9), "form"),
+])
+def test_invalid_parameters_rejected_without_device(lib, mutate, why):
+    p = B.make_params(I.tgv(8))
+    mutate(p)
+    assert lib.osbli_workspace_bytes(C.byref(p)) == 0, why
+    ctx = C.c_void_p()
+    rc = lib.osbli_init_grid(C.byref(ctx), C.byref(p), None, None, None, None, 0, None)
+    assert rc == B.OSBLI_EINVAL
+    assert lib.osbli_last_error(ctx)
+    lib.osbli_destroy(ctx)
+
+
+def test_too_few_wall_nodes_rejected(lib):
+    p = B.make_params(I.laminar_channel(8, 9))
+    p.n[1] = 4
+    ctx = C.c_void_p()
+    assert lib.osbli_init_grid(C.byref(ctx), C.byref(p), None, None, None, None, 0, None) == B.OSBLI_EINVAL
+    assert b"below" in lib.osbli_last_error(ctx)
+    lib.osbli_destroy(ctx)
+
+
+def test_small_workspace_rejected(lib):
+    prob = I.sod(50)
+    p = B.make_params(prob)
+    need = lib.osbli_workspace_bytes(C.byref(p))
+    ctx = C.c_void_p()
+    x = (C.c_double * 50)()
+    rc = lib.osbli_init_grid(C.byref(ctx), C.byref(p), x, None, None, C.c_void_p(256), need - 8, None)
+    assert rc == B.OSBLI_ENOSPACE
+    lib.osbli_destroy(ctx)

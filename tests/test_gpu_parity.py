@@ -1,0 +1,134 @@
+"""Parity of the HIP path with the FP64 oracle, element by element on the same
+seeded inputs.  Bar: max normwise relative difference per conserved component
+<= 1e-11 after 100 steps (or the configured end time); single residual
+evaluations and ghost fills <= 1e-13.  Sizes span several tiles and ragged
+tails; every case prints its name before touching the GPU."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2007_14933_amd import inputs as I
+from parity_util import gpu_run, normwise_rel, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+
+TOL_RUN = 1e-11
+TOL_ONE = 1e-13
+
+
+def wavy3d(n=(12, 10, 14), A=0.03):
+    grids = np.meshgrid(*(np.arange(n[d], dtype=float) / n[d] for d in (2, 1, 0)), indexing="ij")
+    K, Jj, Ii = grids
+    X = Ii + A * np.sin(2 * math.pi * Jj) * np.sin(2 * math.pi * K)
+    Y = Jj + A * np.sin(2 * math.pi * K) * np.sin(4 * math.pi * Ii)
+    Z = K + A * np.sin(2 * math.pi * Ii) * np.sin(2 * math.pi * Jj)
+    return X, Y, Z
+
+
+def cases():
+    c = {}
+    c["sod400_wenoz"] = (I.sod(400), dict(nsteps=10 ** 6, t_end=0.2))
+    c["sod203_teno_simpleavg"] = (I.sod(203, scheme=I.TENO5).with_(roe_avg=0), dict(nsteps=100))
+    # density wave on a 40 x 26 sinusoidal mesh (non-square: ragged tiles)
+    X, Y = I.sinusoidal_mesh(40, 26)
+    rho = 1.0 + 0.2 * np.sin(math.pi * (X + Y))
+    U0 = np.zeros(I.ext_shape(2, (40, 26, 1)))
+    Ui = I.interior_view(2, U0)
+    for k, a in enumerate(I.conserved(1.4, rho, [1.0 + 0 * X, -0.5 + 0 * X], 1.0 + 0 * X)):
+        Ui[k] = a
+    dw = I.density_wave(40, mesh="uniform").with_(n=(40, 26, 1), coords1d=None, coords_full=(X, Y, None), U0=U0)
+    c["dwave_sinusoidal_40x26"] = (dw, dict(nsteps=100))
+    c["riemann2d_70"] = (I.riemann2d(70, 5), dict(nsteps=100))
+    sv = I.shock_vortex(nx=96, ny=48, seed=42)
+    c["shockvortex_96x48"] = (sv, dict(nsteps=100))
+    c["tgv32_viscous"] = (I.tgv(32), dict(nsteps=100))
+    wf = I.wall_flow(24, 20, 16, L=(10.0, 8.0, 6.0))
+    c["wall_24x20x16_isothermal_sutherland"] = (wf, dict(nsteps=100))
+    ch = I.laminar_channel(16, 33)
+    c["channel_16x33_walls"] = (ch.with_(body_force=0.0), dict(nsteps=100))
+    X3, Y3, Z3 = wavy3d()
+    base = I.smooth_random(3, (12, 10, 14), seed=7, amp=0.1, Re=200.0, M=0.6)
+    c["wavy3d_12x10x14_viscous_general"] = (base.with_(coords1d=None, coords_full=(X3, Y3, Z3)), dict(nsteps=60))
+    return c
+
+
+CASES = cases()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_run_parity(name):
+    prob, kw = CASES[name]
+    say("[gpu parity run]", name, prob.n, kw)
+    Ug, tg, _ = gpu_run(prob, **kw)
+    Uo, to = oracle_run(prob, **kw)
+    assert abs(tg - to) <= 1e-12 * max(1.0, abs(to)), (tg, to)
+    err = normwise_rel(O.interior(prob, Ug), O.interior(prob, Uo))
+    say("   t=%.6g  normwise rel diff per component:" % tg, err)
+    assert np.all(np.isfinite(err)) and err.max() <= TOL_RUN, err
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_residual_bc_dt_parity(name):
+    """One ghost fill, one residual and one dt on a perturbed state."""
+    prob, _ = CASES[name]
+    say("[gpu parity residual]", name, prob.n)
+    from paper_2007_14933_amd.solver import Solver
+    import torch
+    s = Solver(prob)
+    s.apply_bc()
+    Ug = s.state()
+    Uo = O.apply_bc(prob, prob.U0.copy())
+    # ghosts and wall nodes (corner ghosts are never read; compare edges/faces)
+    nd = prob.ndim
+    core = [slice(None)] + [slice(3, -3) if d < nd else slice(None) for d in (2, 1, 0)]
+    for d in range(nd):
+        sl = list(core)
+        ax = 3 - d
+        sl[ax] = slice(None)
+        a, b = Ug[tuple(sl)], Uo[tuple(sl)]
+        assert np.array_equal(np.isfinite(a), np.isfinite(b))
+        assert normwise_rel(a, b).max() <= TOL_ONE, (d, normwise_rel(a, b))
+    Rg = s.residual().cpu().numpy()
+    S, J = O.metrics(prob)
+    Ro = O.residual(prob, S, J, Uo)
+    scale = np.abs(Ro).max(axis=(1, 2, 3))
+    err = np.abs(Rg - Ro).max(axis=(1, 2, 3)) / np.where(scale > 0, scale, 1.0)
+    say("   residual normwise rel diff:", err)
+    assert err.max() <= 1e-12, err
+    dtg = s.compute_dt(0.5)
+    dto = O.compute_dt(prob, S, J, Uo, 0.5)
+    assert abs(dtg - dto) <= 1e-14 * dto
+    s.check()
+    del torch
+
+
+def test_nonphysical_state_is_flagged():
+    say("[gpu] non-physical flag")
+    from paper_2007_14933_amd.solver import Solver
+    from paper_2007_14933_amd import binding as B
+    prob = I.sod(64)
+    s = Solver(prob)
+    s.apply_bc()
+    s.check()
+    s.U[0, 0, 0, 20] = -1.0
+    s.residual()
+    with pytest.raises(B.OsbliError) as ei:
+        s.check()
+    assert ei.value.code == B.OSBLI_ENONPHYS
+    s.check()  # flag cleared
+
+
+@pytest.mark.parametrize("n", [5, 6, 7, 13])
+def test_minimum_sizes(n):
+    """Smallest legal grids (5 nodes non-periodic, 6 periodic) and ragged ones."""
+    say("[gpu parity] minimum size", n)
+    per = n >= 6
+    bc = ((I.PERIODIC, I.PERIODIC) if per else (I.EXTRAPOLATE, I.EXTRAPOLATE), (I.PERIODIC, I.PERIODIC),
+          (I.PERIODIC, I.PERIODIC))
+    prob = I.smooth_random(2, (n, 6), seed=n, amp=0.1)
+    prob = prob.with_(bc=(bc[0], (I.PERIODIC, I.PERIODIC), bc[2]))
+    Ug, _, _ = gpu_run(prob, 20)
+    Uo, _ = oracle_run(prob, 20)
+    assert normwise_rel(O.interior(prob, Ug), O.interior(prob, Uo)).max() <= TOL_RUN
