@@ -66,10 +66,15 @@ K_NAMES = ["sweep_x", "sweep_y", "sweep_z", "visc_flux", "finish", "bc", "dt"]
 
 
 def load():
-    """Load libosbli.so (raises if it has not been built)."""
+    """Load libosbli.so (raises if it has not been built).
+
+    torch is imported first so that its HIP runtime is the one in the process:
+    the library and torch then share one runtime (same SONAME), hence one set
+    of streams and allocations."""
     global _lib
     with _lock:
         if _lib is None:
+            import torch  # noqa: F401  (loads the process's HIP runtime first)
             if not os.path.exists(LIB_PATH):
                 raise ImportError("libosbli.so not built: run `python -m paper_2007_14933_amd.build`")
             lib = C.CDLL(LIB_PATH)

@@ -84,7 +84,9 @@ int make_grid(const osbli_params *p, Grid &g, char *buf, size_t nb) {
         g.periodic[d] = k0 == OSBLI_PERIODIC;
         const int64_t nmin = g.periodic[d] ? 6 : 5;
         if (p->n[d] < nmin) { snprintf(buf, nb, "n[%d] = %lld below %lld", d, (long long)p->n[d], (long long)nmin); return -1; }
-        if (p->n[d] > (int64_t(1) << 24)) { snprintf(buf, nb, "n[%d] too large", d); return -1; }
+        // grid limits of the pointwise launches (y blocks of 4, z one block per plane)
+        const int64_t nmax = d == 0 ? (int64_t(1) << 26) : (d == 1 ? int64_t(4) * 65535 : 65535);
+        if (p->n[d] > nmax) { snprintf(buf, nb, "n[%d] too large", d); return -1; }
     }
     g.es[0] = 1;
     g.es[1] = g.e[0];

@@ -31,11 +31,9 @@ struct Loc {
     double r, mn, mt[2], E, p, a, ri;
 };
 
+// derived quantities of a point whose conserved state is in w.U
 template <int ND>
-__device__ __forceinline__ void load_point(const double *__restrict__ U, int64_t e, int64_t cs,
-                                           const Phys &ph, Pt<ND> &w, bool &bad) {
-#pragma unroll
-    for (int c = 0; c < ND + 2; ++c) w.U[c] = U[e + c * cs];
+__device__ __forceinline__ void finish_point(const Phys &ph, Pt<ND> &w, bool &bad) {
     const double ri = 1.0 / w.U[0];
     double ke = 0.0;
 #pragma unroll
@@ -52,7 +50,10 @@ __device__ __forceinline__ void load_point(const double *__restrict__ U, int64_t
 // tau_5 = |beta_0 - beta_2|; WENO-Z alpha_r = d_r (1 + (tau/(beta_r+eps))^2);
 // TENO gamma_r = (1 + tau/(beta_r+eps))^6, stencil r cut when
 // gamma_r / sum(gamma) < C_T (evaluated as gamma_r < C_T * sum), weights
-// d_r delta_r / sum(d delta).
+// d_r delta_r / sum(d delta).  The three ratios tau/(beta_r+eps) share one
+// reciprocal of the product of the denominators; TENO's normalisation is a
+// reciprocal of one of seven sums of optimal weights, skipped when no
+// stencil is cut (sum = 1).
 template <int SCHEME>
 __device__ __forceinline__ double recon5(double fm2, double fm1, double f0, double fp1, double fp2,
                                          double CT, double eps) {
@@ -70,23 +71,29 @@ __device__ __forceinline__ double recon5(double fm2, double fm1, double f0, doub
     t = fm2 - 4.0 * fm1 + 3.0 * f0;
     const double b2 = (13.0 / 12.0) * s * s + 0.25 * t * t;
     const double tau = fabs(b0 - b2);
+    const double e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
+    const double e01 = e0 * e1;
+    const double tinv = tau / (e01 * e2);
+    const double x0 = (e1 * e2) * tinv, x1 = (e0 * e2) * tinv, x2 = e01 * tinv;
     if (SCHEME == OSBLI_WENOZ5) {
-        const double x0 = tau / (b0 + eps), x1 = tau / (b1 + eps), x2 = tau / (b2 + eps);
         const double a0 = 0.3 * (1.0 + x0 * x0);
         const double a1 = 0.6 * (1.0 + x1 * x1);
         const double a2 = 0.1 * (1.0 + x2 * x2);
         return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
     } else {
-        double c0 = 1.0 + tau / (b0 + eps), c1 = 1.0 + tau / (b1 + eps), c2 = 1.0 + tau / (b2 + eps);
+        double c0 = 1.0 + x0, c1 = 1.0 + x1, c2 = 1.0 + x2;
         c0 = c0 * c0 * c0;
         c1 = c1 * c1 * c1;
         c2 = c2 * c2 * c2;
         const double g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2;
         const double lim = CT * (g0 + g1 + g2);
-        const double w0 = g0 < lim ? 0.0 : 0.3;
-        const double w1 = g1 < lim ? 0.0 : 0.6;
-        const double w2 = g2 < lim ? 0.0 : 0.1;
-        return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+        const bool k0 = !(g0 < lim), k1 = !(g1 < lim), k2 = !(g2 < lim);
+        const double w0 = k0 ? 0.3 : 0.0;
+        const double w1 = k1 ? 0.6 : 0.0;
+        const double w2 = k2 ? 0.1 : 0.0;
+        const double num = w0 * q0 + w1 * q1 + w2 * q2;
+        if (k0 && k1 && k2) return num;
+        return num / (w0 + w1 + w2);
     }
 }
 
@@ -202,7 +209,15 @@ struct Axes {
     static constexpr int T2 = (DIR + 2) % ND;
 };
 
+constexpr int kChunk = 8;   // x-points staged per cooperative load (x sweep)
+constexpr int kWaves = 4;   // waves per block
+
 // One convective sweep along DIR.  first != 0: R = contribution, else R +=.
+// Thread mapping: every wave owns 64 consecutive lines and one segment
+// [p0, p1) along DIR (wave-uniform), lane l owns line line0 + l.  Along y and
+// z the lanes' loads are contiguous in x.  Along x the lines are strided, so
+// the wave stages chunks of kChunk points of its 64 rows through LDS with
+// contiguous loads and each lane reads its own row back.
 template <int ND, int DIR, int SCHEME, bool GEN>
 __global__ void __launch_bounds__(256)
 k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t seg,
@@ -212,18 +227,22 @@ k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, M
     constexpr int O1 = DIR == 0 ? 1 : 0;
     constexpr int O2 = DIR == 2 ? 1 : 2;
     const int64_t n1 = g.n[O1], n2 = g.n[O2], N = g.n[DIR];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t a = t % n1;
-    const int64_t rr = t / n1;
-    const int64_t bb = rr % n2;
-    const int64_t sg = rr / n2;
-    if (sg >= nseg) return;
+    const int64_t lines = n1 * n2;
+    const int64_t wpl = (lines + 63) >> 6;  // waves per segment
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t sg = gw / wpl;
+    if (sg >= nseg) return;  // wave-uniform
+    const int64_t line0 = (gw - sg * wpl) << 6;
+    const int64_t line = line0 + lane;
+    const bool active = line < lines;
+    const int64_t lc = active ? line : lines - 1;
     const int64_t p0 = sg * seg;
     const int64_t p1 = p0 + seg < N ? p0 + seg : N;
     int64_t q[3];
     q[DIR] = 0;
-    q[O1] = a;
-    q[O2] = bb;
+    q[O1] = lc % n1;
+    q[O2] = lc / n1;
     const int64_t base = ext_index(g, q[0], q[1], q[2]);
     const int64_t st = g.es[DIR];
     const int64_t cs = g.enpts;
@@ -231,9 +250,45 @@ k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, M
     const int64_t ist = g.is[DIR];
     bool bad = false;
 
+    // x sweep staging buffer: [wave][component][chunk point][row]
+    __shared__ double sbuf[DIR == 0 ? kWaves : 1][DIR == 0 ? NC : 1][DIR == 0 ? kChunk : 1][64];
+    const int wv = DIR == 0 ? (threadIdx.x >> 6) : 0;
+    int64_t cbase = p0 - 3 - kChunk;  // first point held in the chunk buffer
+    // point q's conserved state into w (from LDS along x, directly otherwise)
+    auto fetch = [&](int64_t qp, Pt<ND> &w) {
+        if (DIR == 0) {
+            if (qp >= cbase + kChunk) {
+                cbase = qp;
+                const int64_t last = N + kGhost - 1;
+#pragma unroll
+                for (int s2 = 0; s2 < kChunk; ++s2) {
+                    const int e = lane + 64 * s2;
+                    const int r = e / kChunk, x = e % kChunk;
+                    int64_t rl = line0 + r;
+                    if (rl >= lines) rl = lines - 1;
+                    const int64_t rb = ext_index(g, 0, rl % n1, rl / n1);
+                    int64_t xp = qp + x;
+                    if (xp > last) xp = last;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) sbuf[wv][c][x][r] = U[rb + xp + c * cs];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            const int xi = (int)(qp - cbase);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) w.U[c] = sbuf[wv][c][xi][lane];
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) w.U[c] = U[base + qp * st + c * cs];
+        }
+        finish_point<ND>(ph, w, bad);
+    };
+
     Pt<ND> w[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) load_point<ND>(U, base + (p0 - 3 + k) * st, cs, ph, w[k], bad);
+    for (int k = 0; k < 6; ++k) fetch(p0 - 3 + k, w[k]);
 
     // general meshes: node area vectors S_DIR at f-1 .. f+2 for interface f+1/2
     double Sw[4][3];
@@ -250,7 +305,7 @@ k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, M
         if (f >= p0) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) w[k] = w[k + 1];
-            load_point<ND>(U, base + (f + 3) * st, cs, ph, w[5], bad);
+            fetch(f + 3, w[5]);
             if (GEN) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
@@ -342,7 +397,7 @@ k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, M
                 F[1 + c] = v * Smag;
             }
         }
-        if (f >= p0) {
+        if (f >= p0 && active) {
             const double sc = GEN ? m.J[base + f * st] : m.invh[DIR][f];
             const int64_t oi = ibase + f * ist;
 #pragma unroll
@@ -371,9 +426,9 @@ hipError_t launch_one(const Grid &g, const Phys &ph, const Metrics &m, const dou
     if (seg < 8) seg = 8;
     if (seg > N) seg = N;
     const int64_t nseg = (N + seg - 1) / seg;
-    const int64_t threads = lines * nseg;
-    const int bs = 256;
-    const int64_t nb = (threads + bs - 1) / bs;
+    const int64_t waves = ((lines + 63) / 64) * nseg;
+    const int bs = 64 * kWaves;
+    const int64_t nb = (waves + kWaves - 1) / kWaves;
     hipLaunchKernelGGL((k_sweep<ND, DIR, SCHEME, GEN>), dim3((unsigned)nb), dim3(bs), 0, s, U, R, g, ph, m,
                        seg, nseg, first, flags);
     return hipGetLastError();

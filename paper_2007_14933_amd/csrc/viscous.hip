@@ -30,6 +30,20 @@ __device__ __forceinline__ double dline(const At &at, int64_t p, int64_t N, bool
     return (3.0 * at(N - 5) - 16.0 * at(N - 4) + 36.0 * at(N - 3) - 48.0 * at(N - 2) + 25.0 * at(N - 1)) / 12.0;
 }
 
+// pointwise kernels: blocks of 64 x 4 threads over (i, j), grid.z over k
+constexpr int kBX = 64, kBY = 4;
+
+__device__ __forceinline__ bool node_of_thread(const Grid &g, int64_t (&idx)[3]) {
+    idx[0] = (int64_t)blockIdx.x * kBX + threadIdx.x;
+    idx[1] = (int64_t)blockIdx.y * kBY + threadIdx.y;
+    idx[2] = blockIdx.z;
+    return idx[0] < g.n[0] && idx[1] < g.n[1];
+}
+
+inline dim3 node_grid(const Grid &g) {
+    return dim3((unsigned)((g.n[0] + kBX - 1) / kBX), (unsigned)((g.n[1] + kBY - 1) / kBY), (unsigned)g.n[2]);
+}
+
 template <int ND>
 __device__ __forceinline__ void phi_at(const double *__restrict__ U, int64_t e, int64_t cs, const Phys &ph,
                                        double (&phi)[ND + 1]) {
@@ -55,12 +69,9 @@ template <int ND, bool GEN>
 __global__ void __launch_bounds__(256)
 k_visc_flux(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys ph, Metrics m) {
     constexpr int NV = ND + 1;
-    const int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (ci >= g.nint) return;
     int64_t idx[3];
-    idx[0] = ci % g.n[0];
-    idx[1] = (ci / g.n[0]) % g.n[1];
-    idx[2] = ci / (g.n[0] * g.n[1]);
+    if (!node_of_thread(g, idx)) return;
+    const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
     const int64_t e0 = ext_index(g, idx[0], idx[1], idx[2]);
     const int64_t cs = g.enpts;
 
@@ -154,12 +165,9 @@ k_finish(const double *Racc, const double *__restrict__ G, double *Rout, Grid g,
          Phys ph, Metrics m, int stage, double dt, double *__restrict__ U, double *__restrict__ dU) {
     constexpr int NC = ND + 2;
     constexpr int NV = ND + 1;
-    const int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (ci >= g.nint) return;
     int64_t idx[3];
-    idx[0] = ci % g.n[0];
-    idx[1] = (ci / g.n[0]) % g.n[1];
-    idx[2] = ci / (g.n[0] * g.n[1]);
+    if (!node_of_thread(g, idx)) return;
+    const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
     double R[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) R[c] = Racc[c * g.nint + ci];
@@ -214,13 +222,9 @@ template <int ND, bool GEN>
 __global__ void __launch_bounds__(256)
 k_dt(const double *__restrict__ U, Grid g, Phys ph, Metrics m, unsigned long long *slot) {
     __shared__ double part[4];
-    const int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0.0;
-    if (ci < g.nint) {
-        int64_t idx[3];
-        idx[0] = ci % g.n[0];
-        idx[1] = (ci / g.n[0]) % g.n[1];
-        idx[2] = ci / (g.n[0] * g.n[1]);
+    int64_t idx[3];
+    if (node_of_thread(g, idx)) {
         const int64_t e = ext_index(g, idx[0], idx[1], idx[2]);
         const int64_t cs = g.enpts;
         const double r = U[e], ri = 1.0 / r;
@@ -263,12 +267,12 @@ k_dt(const double *__restrict__ U, Grid g, Phys ph, Metrics m, unsigned long lon
         if (!(s >= 0.0)) s = __builtin_inf();  // NaN state: force dt -> 0
     }
     s = wave_max(s);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.y;
     if (lane == 0) part[wv] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
         double b = part[0];
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = fmax(b, part[k]);
+        for (int k = 1; k < (int)blockDim.y; ++k) b = fmax(b, part[k]);
         atomicMax(slot, (unsigned long long)__double_as_longlong(b));
     }
 }
@@ -281,21 +285,20 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int n) {
 template <int ND, bool GEN>
 hipError_t finish_nd(const Grid &g, const Phys &ph, const Metrics &m, const double *Racc, const double *G,
                      double *Rout, int stage, double dt, double *U, double *dU, int mode, hipStream_t s) {
-    const int bs = 256;
-    const unsigned nb = (unsigned)((g.nint + bs - 1) / bs);
+    const dim3 nb = node_grid(g), bs(kBX, kBY);
     if (ph.viscous) {
         if (mode == 0)
-            hipLaunchKernelGGL((k_finish<ND, GEN, true, 0>), dim3(nb), dim3(bs), 0, s, Racc, G, Rout, g, ph, m,
+            hipLaunchKernelGGL((k_finish<ND, GEN, true, 0>), nb, bs, 0, s, Racc, G, Rout, g, ph, m,
                                stage, dt, U, dU);
         else
-            hipLaunchKernelGGL((k_finish<ND, GEN, true, 1>), dim3(nb), dim3(bs), 0, s, Racc, G, Rout, g, ph, m,
+            hipLaunchKernelGGL((k_finish<ND, GEN, true, 1>), nb, bs, 0, s, Racc, G, Rout, g, ph, m,
                                stage, dt, U, dU);
     } else {
         if (mode == 0)
-            hipLaunchKernelGGL((k_finish<ND, GEN, false, 0>), dim3(nb), dim3(bs), 0, s, Racc, G, Rout, g, ph,
+            hipLaunchKernelGGL((k_finish<ND, GEN, false, 0>), nb, bs, 0, s, Racc, G, Rout, g, ph,
                                m, stage, dt, U, dU);
         else
-            hipLaunchKernelGGL((k_finish<ND, GEN, false, 1>), dim3(nb), dim3(bs), 0, s, Racc, G, Rout, g, ph,
+            hipLaunchKernelGGL((k_finish<ND, GEN, false, 1>), nb, bs, 0, s, Racc, G, Rout, g, ph,
                                m, stage, dt, U, dU);
     }
     return hipGetLastError();
@@ -305,18 +308,17 @@ hipError_t finish_nd(const Grid &g, const Phys &ph, const Metrics &m, const doub
 
 hipError_t launch_viscous_fluxes(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *G,
                                  hipStream_t s) {
-    const int bs = 256;
-    const unsigned nb = (unsigned)((g.nint + bs - 1) / bs);
+    const dim3 nb = node_grid(g), bs(kBX, kBY);
     const bool gen = m.general != 0;
     switch (g.nd) {
-        case 1: hipLaunchKernelGGL((k_visc_flux<1, false>), dim3(nb), dim3(bs), 0, s, U, G, g, ph, m); break;
+        case 1: hipLaunchKernelGGL((k_visc_flux<1, false>), nb, bs, 0, s, U, G, g, ph, m); break;
         case 2:
-            if (gen) hipLaunchKernelGGL((k_visc_flux<2, true>), dim3(nb), dim3(bs), 0, s, U, G, g, ph, m);
-            else hipLaunchKernelGGL((k_visc_flux<2, false>), dim3(nb), dim3(bs), 0, s, U, G, g, ph, m);
+            if (gen) hipLaunchKernelGGL((k_visc_flux<2, true>), nb, bs, 0, s, U, G, g, ph, m);
+            else hipLaunchKernelGGL((k_visc_flux<2, false>), nb, bs, 0, s, U, G, g, ph, m);
             break;
         default:
-            if (gen) hipLaunchKernelGGL((k_visc_flux<3, true>), dim3(nb), dim3(bs), 0, s, U, G, g, ph, m);
-            else hipLaunchKernelGGL((k_visc_flux<3, false>), dim3(nb), dim3(bs), 0, s, U, G, g, ph, m);
+            if (gen) hipLaunchKernelGGL((k_visc_flux<3, true>), nb, bs, 0, s, U, G, g, ph, m);
+            else hipLaunchKernelGGL((k_visc_flux<3, false>), nb, bs, 0, s, U, G, g, ph, m);
     }
     return hipGetLastError();
 }
@@ -337,18 +339,17 @@ hipError_t launch_finish(const Grid &g, const Phys &ph, const Metrics &m, const 
 
 hipError_t launch_dt(const Grid &g, const Phys &ph, const Metrics &m, const double *U, unsigned long long *slot,
                      hipStream_t s) {
-    const int bs = 256;
-    const unsigned nb = (unsigned)((g.nint + bs - 1) / bs);
+    const dim3 nb = node_grid(g), bs(kBX, kBY);
     const bool gen = m.general != 0;
     switch (g.nd) {
-        case 1: hipLaunchKernelGGL((k_dt<1, false>), dim3(nb), dim3(bs), 0, s, U, g, ph, m, slot); break;
+        case 1: hipLaunchKernelGGL((k_dt<1, false>), nb, bs, 0, s, U, g, ph, m, slot); break;
         case 2:
-            if (gen) hipLaunchKernelGGL((k_dt<2, true>), dim3(nb), dim3(bs), 0, s, U, g, ph, m, slot);
-            else hipLaunchKernelGGL((k_dt<2, false>), dim3(nb), dim3(bs), 0, s, U, g, ph, m, slot);
+            if (gen) hipLaunchKernelGGL((k_dt<2, true>), nb, bs, 0, s, U, g, ph, m, slot);
+            else hipLaunchKernelGGL((k_dt<2, false>), nb, bs, 0, s, U, g, ph, m, slot);
             break;
         default:
-            if (gen) hipLaunchKernelGGL((k_dt<3, true>), dim3(nb), dim3(bs), 0, s, U, g, ph, m, slot);
-            else hipLaunchKernelGGL((k_dt<3, false>), dim3(nb), dim3(bs), 0, s, U, g, ph, m, slot);
+            if (gen) hipLaunchKernelGGL((k_dt<3, true>), nb, bs, 0, s, U, g, ph, m, slot);
+            else hipLaunchKernelGGL((k_dt<3, false>), nb, bs, 0, s, U, g, ph, m, slot);
     }
     return hipGetLastError();
 }
