@@ -218,13 +218,18 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // dt denominator, max over nodes; positive doubles compare as unsigned 64-bit.
+// Blocks stride over z planes so that only a few hundred blocks issue the
+// final atomic (a max is order independent, so the result is deterministic).
 template <int ND, bool GEN>
 __global__ void __launch_bounds__(256)
 k_dt(const double *__restrict__ U, Grid g, Phys ph, Metrics m, unsigned long long *slot) {
     __shared__ double part[4];
     double s = 0.0;
     int64_t idx[3];
-    if (node_of_thread(g, idx)) {
+    idx[0] = (int64_t)blockIdx.x * kBX + threadIdx.x;
+    idx[1] = (int64_t)blockIdx.y * kBY + threadIdx.y;
+    const bool inplane = idx[0] < g.n[0] && idx[1] < g.n[1];
+    for (idx[2] = blockIdx.z; inplane && idx[2] < g.n[2]; idx[2] += gridDim.z) {
         const int64_t e = ext_index(g, idx[0], idx[1], idx[2]);
         const int64_t cs = g.enpts;
         const double r = U[e], ri = 1.0 / r;
@@ -263,8 +268,9 @@ k_dt(const double *__restrict__ U, Grid g, Phys ph, Metrics m, unsigned long lon
             conv += js * (fabs(un) + a);
             diff += js * js;
         }
-        s = conv + 2.0 * nu * diff;
-        if (!(s >= 0.0)) s = __builtin_inf();  // NaN state: force dt -> 0
+        double sn = conv + 2.0 * nu * diff;
+        if (!(sn >= 0.0)) sn = __builtin_inf();  // NaN state: force dt -> 0
+        s = fmax(s, sn);
     }
     s = wave_max(s);
     const int lane = threadIdx.x & 63, wv = threadIdx.y;
@@ -339,7 +345,13 @@ hipError_t launch_finish(const Grid &g, const Phys &ph, const Metrics &m, const 
 
 hipError_t launch_dt(const Grid &g, const Phys &ph, const Metrics &m, const double *U, unsigned long long *slot,
                      hipStream_t s) {
-    const dim3 nb = node_grid(g), bs(kBX, kBY);
+    dim3 nb = node_grid(g);
+    const dim3 bs(kBX, kBY);
+    const unsigned plane_blocks = nb.x * nb.y;
+    unsigned gz = (1024 + plane_blocks - 1) / plane_blocks;
+    if (gz < 1) gz = 1;
+    if (gz > nb.z) gz = nb.z;
+    nb.z = gz;
     const bool gen = m.general != 0;
     switch (g.nd) {
         case 1: hipLaunchKernelGGL((k_dt<1, false>), nb, bs, 0, s, U, g, ph, m, slot); break;
