@@ -29,18 +29,20 @@ sys.path.insert(0, ROOT)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256, help="TGV grid points per direction")
     ap.add_argument("--cfl", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision / sensor forms")
     ap.add_argument("--cpu-n", type=int, default=0, help="oracle sample grid (default: same as --n)")
     return ap.parse_args()
 
 
 def cpu_baseline(n):
     """The oracle as it stands: one RK substage (residual + update) of the
-    same TGV problem, timed on the host cores it uses."""
+    same TGV problem, timed on the host cores it uses (metrics and set-up
+    excluded)."""
     import numpy as np
     from oracle import oracle as O
     from paper_2007_14933_amd import inputs
@@ -59,23 +61,16 @@ def cpu_baseline(n):
             "sample": "one RK substage (residual + low-storage update) of TGV %d^3, FP64, %.1f s" % (n, el)}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU halo exchange "
-              "is described in the design notes but not built" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def timed_run(prob, form, steps, warmup, cfl):
+    """W warm-up steps, then K timed steps (dt reduction + 3 substages + BCs
+    each) with the library's per-kernel event timing on."""
     import torch
-    from paper_2007_14933_amd import cost, inputs
     from paper_2007_14933_amd.solver import Solver
-
-    n = args.n
-    prob = inputs.tgv(n)
-    s = Solver(prob)
+    s = Solver(prob, form=form)
     stream = s.stream
     s.apply_bc()
-    for _ in range(args.warmup):
-        s.step(s.compute_dt(args.cfl))
+    for _ in range(warmup):
+        s.step(s.compute_dt(cfl))
     s.check()
     torch.cuda.synchronize()
     s.profile(True)
@@ -83,8 +78,8 @@ def main():
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
-        s.step(s.compute_dt(args.cfl))
+    for _ in range(steps):
+        s.step(s.compute_dt(cfl))
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -92,7 +87,52 @@ def main():
     prof = s.profile_read()
     s.profile(False)
     gpu_ms = ev0.elapsed_time(ev1)
+    del s
+    torch.cuda.empty_cache()
+    return wall, gpu_ms, prof
+
+
+def form_error(prob, form, steps, cfl):
+    """Relative L1 / Linf of rho and rho E of a form against plain FP64 after
+    `steps` steps with the same fixed dt (from the initial state)."""
+    import numpy as np
+    import torch
+    from paper_2007_14933_amd.solver import Solver
+    outs = []
+    dt = None
+    for f in (0, form):
+        s = Solver(prob, form=f)
+        s.apply_bc()
+        if dt is None:
+            dt = s.compute_dt(cfl)
+        for _ in range(steps):
+            s.step(dt)
+        s.check()
+        outs.append(s.interior())
+        del s
+        torch.cuda.empty_cache()
+    a, b = outs[1], outs[0]
+    res = {}
+    for name, c in (("rho", 0), ("rhoE", prob.nc - 1)):
+        d = np.abs(a[c] - b[c])
+        res["rel_L1_" + name] = float("%.3e" % (d.mean() / np.abs(b[c]).mean()))
+        res["rel_Linf_" + name] = float("%.3e" % (d.max() / np.abs(b[c]).max()))
+    res["steps"] = steps
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU halo exchange "
+              "is described in the design notes but not built" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    from paper_2007_14933_amd import cost, inputs
+
+    n = args.n
+    prob = inputs.tgv(n)
     npts = n ** 3
+    wall, gpu_ms, prof = timed_run(prob, 0, args.steps, args.warmup, args.cfl)
     value = npts * 3 * args.steps / wall / 1e6
 
     # dominant kernel: the convective sweeps (one launch per direction and substage)
@@ -131,6 +171,14 @@ def main():
         "roofline": roofline,
         "kernels": breakdown,
     }
+    if not args.no_forms:
+        wm, _, pm = timed_run(prob, 1, args.steps, args.warmup, args.cfl)
+        vm = npts * 3 * args.steps / wm / 1e6
+        sm = sum(pm["sweep_%s" % a][1] for a in "xyz") / max(1, sum(pm["sweep_%s" % a][0] for a in "xyz"))
+        out["forms"] = {"mixed_fp32": {
+            "value": round(vm, 3), "speedup_vs_fp64": round(vm / value, 3),
+            "sweep_avg_ms": round(sm, 4),
+            "error_vs_fp64": form_error(prob, 1, 10, args.cfl)}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n or n)
     print(json.dumps(out), flush=True)

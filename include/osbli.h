@@ -62,8 +62,13 @@ enum osbli_bc {
 
 enum osbli_scheme { OSBLI_WENOZ5 = 0, OSBLI_TENO5 = 1 };
 
-/* arithmetic of the reconstruction and flux evaluation (state, RK
- * accumulation, metrics and dt reduction are FP64 in every form) */
+/* Arithmetic of the characteristic reconstruction and flux evaluation.
+ * OSBLI_FORM_MIXED: per interface, the FP64 flux of node i is the
+ * reference; deviations of the six stencil states and fluxes from it are
+ * formed in FP64, rounded to FP32, projected, split, reconstructed and
+ * back-projected in FP32 (the reconstructions are shift-equivariant), and
+ * added to the reference in FP64.  State, RK accumulation, viscous terms,
+ * metrics and the dt reduction are FP64 in every form. */
 enum osbli_form { OSBLI_FORM_FP64 = 0, OSBLI_FORM_MIXED = 1 };
 
 /* coordinate input of osbli_init_grid */

@@ -98,7 +98,7 @@ int make_grid(const osbli_params *p, Grid &g, char *buf, size_t nb) {
     g.nint = g.n[0] * g.n[1] * g.n[2];
     if (!(p->gamma > 1.0)) { snprintf(buf, nb, "gamma must exceed 1"); return -1; }
     if (p->scheme != OSBLI_WENOZ5 && p->scheme != OSBLI_TENO5) { snprintf(buf, nb, "bad scheme"); return -1; }
-    if (p->form != OSBLI_FORM_FP64) { snprintf(buf, nb, "form %d not available", p->form); return -1; }
+    if (p->form != OSBLI_FORM_FP64 && p->form != OSBLI_FORM_MIXED) { snprintf(buf, nb, "bad form %d", p->form); return -1; }
     if (p->sensor != 0) { snprintf(buf, nb, "sensor routing not available"); return -1; }
     if (p->mesh != OSBLI_MESH_SEPARABLE && p->mesh != OSBLI_MESH_GENERAL) { snprintf(buf, nb, "bad mesh kind"); return -1; }
     bool walls = false;
@@ -167,6 +167,7 @@ Phys make_phys(const osbli_params *p) {
     ph.sutherland = p->sutherland;
     ph.scheme = p->scheme;
     ph.roe = p->roe_avg;
+    ph.mixed = p->form == OSBLI_FORM_MIXED;
     return ph;
 }
 

@@ -203,6 +203,198 @@ __device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph,
     }
 }
 
+// ---------------------------------------------------------------- mixed form
+// Reconstruction and flux evaluation in FP32 on deviations from an FP64
+// reference: with U_ref = U_i, f_ref = f(U_i) (local frame, FP64), the split
+// fluxes are g+- = (L f_ref +- alpha L U_ref)/2 + (L df +- alpha L dU)/2, and
+// both reconstructions are exactly shift-equivariant (sum of weights 1,
+// smoothness indicators use differences only), so
+//   F = f_ref + R (recon+(dg+) + recon-(dg-)).
+// f_ref and the final sum are FP64; everything between runs on the FP32
+// deviations, whose rounding is relative to |df|, not to |f|.
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// FP32 WENO-Z / TENO with overflow-safe weights: the TENO cut-off is
+// evaluated on c_r / max(c) (gamma_r = (1 + tau/(beta_r+eps))^6 exceeds the
+// FP32 range at nearly every jump), WENO-Z's alpha on x_r / max(x) once
+// max(x) >= 1.  Both are algebraically the FP64 test.
+template <int SCHEME>
+__device__ __forceinline__ float recon5f(float fm2, float fm1, float f0, float fp1, float fp2, float CT, float eps) {
+    const float q0 = (1.0f / 3.0f) * f0 + (5.0f / 6.0f) * fp1 - (1.0f / 6.0f) * fp2;
+    const float q1 = -(1.0f / 6.0f) * fm1 + (5.0f / 6.0f) * f0 + (1.0f / 3.0f) * fp1;
+    const float q2 = (1.0f / 3.0f) * fm2 - (7.0f / 6.0f) * fm1 + (11.0f / 6.0f) * f0;
+    float s, t;
+    s = f0 - 2.0f * fp1 + fp2;
+    t = 3.0f * f0 - 4.0f * fp1 + fp2;
+    const float b0 = (13.0f / 12.0f) * s * s + 0.25f * t * t;
+    s = fm1 - 2.0f * f0 + fp1;
+    t = fm1 - fp1;
+    const float b1 = (13.0f / 12.0f) * s * s + 0.25f * t * t;
+    s = fm2 - 2.0f * fm1 + f0;
+    t = fm2 - 4.0f * fm1 + 3.0f * f0;
+    const float b2 = (13.0f / 12.0f) * s * s + 0.25f * t * t;
+    const float tau = fabsf(b0 - b2);
+    const float x0 = tau * rcpf(b0 + eps), x1 = tau * rcpf(b1 + eps), x2 = tau * rcpf(b2 + eps);
+    if (SCHEME == OSBLI_WENOZ5) {
+        const float xm = fmaxf(x0, fmaxf(x1, x2));
+        float a0, a1, a2;
+        if (xm < 1.0f) {
+            a0 = 0.3f * (1.0f + x0 * x0);
+            a1 = 0.6f * (1.0f + x1 * x1);
+            a2 = 0.1f * (1.0f + x2 * x2);
+        } else {
+            const float h = rcpf(xm);
+            const float w0 = x0 * h, w1 = x1 * h, w2 = x2 * h, h2 = h * h;
+            a0 = 0.3f * (h2 + w0 * w0);
+            a1 = 0.6f * (h2 + w1 * w1);
+            a2 = 0.1f * (h2 + w2 * w2);
+        }
+        return (a0 * q0 + a1 * q1 + a2 * q2) * rcpf(a0 + a1 + a2);
+    } else {
+        const float c0 = 1.0f + x0, c1 = 1.0f + x1, c2 = 1.0f + x2;
+        const float ic = rcpf(fmaxf(c0, fmaxf(c1, c2)));
+        float r0 = c0 * ic, r1 = c1 * ic, r2 = c2 * ic;
+        r0 = r0 * r0 * r0;
+        r1 = r1 * r1 * r1;
+        r2 = r2 * r2 * r2;
+        const float g0 = r0 * r0, g1 = r1 * r1, g2 = r2 * r2;
+        const float lim = CT * (g0 + g1 + g2);
+        const bool k0 = !(g0 < lim), k1 = !(g1 < lim), k2 = !(g2 < lim);
+        const float w0 = k0 ? 0.3f : 0.0f, w1 = k1 ? 0.6f : 0.0f, w2 = k2 ? 0.1f : 0.0f;
+        const float num = w0 * q0 + w1 * q1 + w2 * q2;
+        if (k0 && k1 && k2) return num;
+        return num * rcpf(w0 + w1 + w2);
+    }
+}
+
+template <int SCHEME>
+__device__ __forceinline__ float split_reconf(const float (&V)[6], const float (&G)[6], float alpha, float CT,
+                                              float eps) {
+    float gp[6], gm[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        gp[k] = 0.5f * (G[k] + alpha * V[k]);
+        gm[k] = 0.5f * (G[k] - alpha * V[k]);
+    }
+    return recon5f<SCHEME>(gp[0], gp[1], gp[2], gp[3], gp[4], CT, eps) +
+           recon5f<SCHEME>(gm[5], gm[4], gm[3], gm[2], gm[1], CT, eps);
+}
+
+template <int ND, int SCHEME>
+__device__ __forceinline__ void char_flux_mixed(const Loc<ND> (&P)[6], const Phys &ph, double &Fr, double &Fn,
+                                                double (&Ft)[2], double &FE) {
+    constexpr int NT = ND - 1;
+    // FP64 reference flux of node i in the local frame:
+    // f = u_n (rho, m_n, m_t, E) + p (0, 1, 0, u_n)
+    double un64[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) un64[k] = P[k].mn * P[k].ri;
+    const double fr0 = P[2].mn;
+    const double fn0 = P[2].mn * un64[2] + P[2].p;
+    double ft0[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NT; ++s) ft0[s] = P[2].mt[s] * un64[2];
+    const double fE0 = (P[2].E + P[2].p) * un64[2];
+
+    float dr[6], dmn[6], dmt[2][6], dE[6], gr[6], gmn[6], gmt[2][6], gE[6], unf[6], af[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        dr[k] = (float)(P[k].r - P[2].r);
+        dmn[k] = (float)(P[k].mn - P[2].mn);
+        dE[k] = (float)(P[k].E - P[2].E);
+        gr[k] = (float)(P[k].mn - fr0);
+        gmn[k] = (float)(P[k].mn * un64[k] + P[k].p - fn0);
+        gE[k] = (float)((P[k].E + P[k].p) * un64[k] - fE0);
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            dmt[s][k] = (float)(P[k].mt[s] - P[2].mt[s]);
+            gmt[s][k] = (float)(P[k].mt[s] * un64[k] - ft0[s]);
+        }
+        unf[k] = (float)un64[k];
+        af[k] = (float)P[k].a;
+    }
+    // averaged state of nodes i, i+1 in FP32
+    float sl = 1.0f, sr = 1.0f;
+    if (ph.roe) {
+        sl = sqrtf((float)P[2].r);
+        sr = sqrtf((float)P[3].r);
+    }
+    const float iw = rcpf(sl + sr);
+    const float un = (sl * unf[2] + sr * unf[3]) * iw;
+    float ut[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < NT; ++s)
+        ut[s] = (sl * (float)(P[2].mt[s] * P[2].ri) + sr * (float)(P[3].mt[s] * P[3].ri)) * iw;
+    const float Hl = (float)((P[2].E + P[2].p) * P[2].ri), Hr = (float)((P[3].E + P[3].p) * P[3].ri);
+    const float Hh = (sl * Hl + sr * Hr) * iw;
+    float K = un * un;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) K += ut[s] * ut[s];
+    K *= 0.5f;
+    const float gm1 = (float)ph.gm1;
+    const float ah = sqrtf(gm1 * (Hh - K));
+    const float ia = rcpf(ah);
+    const float b = gm1 * ia * ia;
+    const float CT = (float)ph.CT, eps = (float)ph.eps;
+
+    float A[6], B[6], Ag[6], Bg[6], aminus = 0.0f, aplus = 0.0f, a0 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float um = un * dmn[k], ug = un * gmn[k];
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            um += ut[s] * dmt[s][k];
+            ug += ut[s] * gmt[s][k];
+        }
+        A[k] = b * (K * dr[k] - um + dE[k]);
+        B[k] = (un * dr[k] - dmn[k]) * ia;
+        Ag[k] = b * (K * gr[k] - ug + gE[k]);
+        Bg[k] = (un * gr[k] - gmn[k]) * ia;
+        aminus = fmaxf(aminus, fabsf(unf[k] - af[k]));
+        aplus = fmaxf(aplus, fabsf(unf[k] + af[k]));
+        a0 = fmaxf(a0, fabsf(unf[k]));
+    }
+    float V[6], G[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = 0.5f * (A[k] + B[k]);
+        G[k] = 0.5f * (Ag[k] + Bg[k]);
+    }
+    const float h0 = split_reconf<SCHEME>(V, G, aminus, CT, eps);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = 0.5f * (A[k] - B[k]);
+        G[k] = 0.5f * (Ag[k] - Bg[k]);
+    }
+    const float h4 = split_reconf<SCHEME>(V, G, aplus, CT, eps);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = dr[k] - A[k];
+        G[k] = gr[k] - Ag[k];
+    }
+    const float h1 = split_reconf<SCHEME>(V, G, a0, CT, eps);
+    float ht[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            V[k] = dmt[s][k] - ut[s] * dr[k];
+            G[k] = gmt[s][k] - ut[s] * gr[k];
+        }
+        ht[s] = split_reconf<SCHEME>(V, G, a0, CT, eps);
+    }
+    const float hs = h0 + h1 + h4, hd = h4 - h0;
+    float dFE = Hh * (h0 + h4) + ah * un * hd + K * h1;
+    Fr = fr0 + (double)hs;
+    Fn = fn0 + (double)(un * hs + ah * hd);
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        Ft[s] = ft0[s] + (double)(ut[s] * hs + ht[s]);
+        dFE += ut[s] * ht[s];
+    }
+    FE = fE0 + (double)dFE;
+}
+
 template <int ND, int DIR>
 struct Axes {
     static constexpr int T1 = (DIR + 1) % ND;
@@ -218,7 +410,7 @@ constexpr int kWaves = 4;   // waves per block
 // z the lanes' loads are contiguous in x.  Along x the lines are strided, so
 // the wave stages chunks of kChunk points of its 64 rows through LDS with
 // contiguous loads and each lane reads its own row back.
-template <int ND, int DIR, int SCHEME, bool GEN>
+template <int ND, int DIR, int SCHEME, bool GEN, bool MIX>
 __global__ void __launch_bounds__(256)
 k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t seg,
         int64_t nseg, int first, unsigned *flags) {
@@ -381,7 +573,8 @@ k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, M
             }
         }
         double Fr, Fn, Ft[2], FE;
-        char_flux<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
+        if (MIX) char_flux_mixed<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
+        else char_flux<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
         F[0] = Fr * Smag;
         F[NC - 1] = FE * Smag;
         if (!GEN) {
@@ -414,7 +607,7 @@ k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, M
     if (bad) atomicOr(flags, kFlagNonPhys);
 }
 
-template <int ND, int DIR, int SCHEME, bool GEN>
+template <int ND, int DIR, int SCHEME, bool GEN, bool MIX>
 hipError_t launch_one(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
                       unsigned *flags, int first, hipStream_t s) {
     constexpr int O1 = DIR == 0 ? 1 : 0;
@@ -429,17 +622,24 @@ hipError_t launch_one(const Grid &g, const Phys &ph, const Metrics &m, const dou
     const int64_t waves = ((lines + 63) / 64) * nseg;
     const int bs = 64 * kWaves;
     const int64_t nb = (waves + kWaves - 1) / kWaves;
-    hipLaunchKernelGGL((k_sweep<ND, DIR, SCHEME, GEN>), dim3((unsigned)nb), dim3(bs), 0, s, U, R, g, ph, m,
+    hipLaunchKernelGGL((k_sweep<ND, DIR, SCHEME, GEN, MIX>), dim3((unsigned)nb), dim3(bs), 0, s, U, R, g, ph, m,
                        seg, nseg, first, flags);
     return hipGetLastError();
+}
+
+template <int ND, int SCHEME, bool GEN, bool MIX>
+hipError_t launch_dir_f(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
+                        unsigned *flags, int dir, int first, hipStream_t s) {
+    if (dir == 0) return launch_one<ND, 0, SCHEME, GEN, MIX>(g, ph, m, U, R, flags, first, s);
+    if (dir == 1) return launch_one<ND, (ND >= 2 ? 1 : 0), SCHEME, GEN, MIX>(g, ph, m, U, R, flags, first, s);
+    return launch_one<ND, (ND >= 3 ? 2 : 0), SCHEME, GEN, MIX>(g, ph, m, U, R, flags, first, s);
 }
 
 template <int ND, int SCHEME, bool GEN>
 hipError_t launch_dir(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
                       unsigned *flags, int dir, int first, hipStream_t s) {
-    if (dir == 0) return launch_one<ND, 0, SCHEME, GEN>(g, ph, m, U, R, flags, first, s);
-    if (dir == 1) return launch_one<ND, (ND >= 2 ? 1 : 0), SCHEME, GEN>(g, ph, m, U, R, flags, first, s);
-    return launch_one<ND, (ND >= 3 ? 2 : 0), SCHEME, GEN>(g, ph, m, U, R, flags, first, s);
+    if (ph.mixed) return launch_dir_f<ND, SCHEME, GEN, true>(g, ph, m, U, R, flags, dir, first, s);
+    return launch_dir_f<ND, SCHEME, GEN, false>(g, ph, m, U, R, flags, dir, first, s);
 }
 
 template <int ND, int SCHEME>

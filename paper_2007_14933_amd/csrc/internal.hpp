@@ -32,6 +32,7 @@ struct Phys {
     double kheat;      // 1/((gamma-1) M^2 Pr Re)
     double nu_fac;     // max(4/3, gamma/Pr)
     int sutherland, scheme, roe, viscous;
+    int mixed;         // FP32 reconstruction / flux evaluation on FP64 deviations
 };
 
 // Metric terms.  Separable meshes keep 1/h_d per direction (h_d = D_d x_d);
