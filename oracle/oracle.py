@@ -83,6 +83,8 @@ def _load():
                 "orc_deriv_field": (None, [P, _D, C.c_int, _D]),
                 "orc_viscosity": (C.c_double, [P, C.c_double]),
                 "orc_num_threads": (C.c_int, []),
+                "orc_cheap_flux": (None, [P, C.c_int, _D, _D, _D]),
+                "orc_features": (None, [P, C.c_int, _D, _D, _D, _I]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(lib, name)
@@ -265,3 +267,46 @@ def viscosity(prob, T):
 
 def num_threads():
     return int(_load().orc_num_threads())
+
+
+def cheap_flux(prob, d, Uk, S):
+    """Exact all-stencils-kept limit of the characteristic flux."""
+    nc = prob.ndim + 2
+    Uk = np.ascontiguousarray(Uk, dtype=np.float64).reshape(6 * nc)
+    S3 = np.zeros(3)
+    S3[: prob.ndim] = np.asarray(S, dtype=np.float64)[: prob.ndim]
+    F = np.zeros(nc)
+    _load().orc_cheap_flux(C.byref(params(prob)), int(d), _dp(Uk), _dp(S3), _dp(F))
+    return F
+
+
+def features(prob, d, Uk, S):
+    """Ten sensor features and the TENO all-kept label of one interface."""
+    nc = prob.ndim + 2
+    Uk = np.ascontiguousarray(Uk, dtype=np.float64).reshape(6 * nc)
+    S3 = np.zeros(3)
+    S3[: prob.ndim] = np.asarray(S, dtype=np.float64)[: prob.ndim]
+    f = np.zeros(10)
+    lab = np.zeros(1, dtype=np.intc)
+    _load().orc_features(C.byref(params(prob)), int(d), _dp(Uk), _dp(S3), _dp(f), _ip(lab))
+    return f, int(lab[0])
+
+
+def stencils(prob, U, d):
+    """All interface stencils of direction d of a ghosted state: array
+    (n_interfaces, 6, nc) ordered [other dims..., i = -1 .. N-1] with the
+    sweep direction fastest, plus the half-node area vectors (from the
+    oracle's metrics of prob)."""
+    nd = prob.ndim
+    Ui = np.moveaxis(U, 0, -1)               # (ez, ey, ex, nc)
+    ax = 2 - d                               # array axis of direction d
+    N = int(prob.n[d])
+    core = [slice(3, -3) if e < nd else slice(None) for e in (2, 1, 0)]
+    out = []
+    for k in range(6):
+        sl = list(core)
+        sl[ax] = slice(1 + k, 1 + k + N + 1)   # node p-2+k for p = -1..N-1
+        out.append(Ui[tuple(sl)])
+    st = np.stack(out, axis=-2)              # (..., N+1, 6, nc) with d axis in place
+    st = np.moveaxis(st, ax, -3)             # direction d next to the stencil axis
+    return st.reshape(-1, 6, nd + 2)

@@ -1036,3 +1036,123 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ---------------------------------------------- learned-sensor support --
+ * Not in the paper: the paper names sensor-switched hybrids of central and
+ * shock-capturing fluxes (section 2, introduction) as hard to design by
+ * hand.  The routed form replaces the characteristic TENO flux at an
+ * interface the sensor calls smooth by the exact all-stencils-kept limit of
+ * the same flux (cheap flux), and keeps the full flux elsewhere.
+ *
+ * Cheap flux: summing the split upwind-5 reconstructions of g+ and g- gives
+ *   F = |S| [ C6 f + R diag(alpha) L D6 U ],
+ *   C6 = (1, -8, 37, 37, -8, 1)/60,  D6 = (1, -5, 10, -10, 5, -1)/60 on
+ *   i-2..i+3, with the averaged state, L, R and alpha of the full flux.
+ */
+void orc_cheap_flux(const orc_params *P, int d, const double *Uk, const double *S, double *F)
+{
+    const int nd = P->ndim, nc = nd + 2;
+    double Smag = 0.0, nv[3] = {0.0, 0.0, 0.0};
+    for (int m = 0; m < nd; m++) Smag += S[m] * S[m];
+    Smag = sqrt(Smag);
+    for (int m = 0; m < nd; m++) nv[m] = S[m] / Smag;
+    prim_t w[6];
+    double fk[6][NCMAX], lam[6][NCMAX];
+    for (int k = 0; k < 6; k++) {
+        to_prim(P, nd, Uk + k * nc, &w[k]);
+        phys_flux(nd, Uk + k * nc, &w[k], nv, fk[k]);
+        double un = 0.0;
+        for (int m = 0; m < nd; m++) un += w[k].u[m] * nv[m];
+        lam[k][0] = un - w[k].a;
+        for (int j = 1; j <= nd; j++) lam[k][j] = un;
+        lam[k][nd + 1] = un + w[k].a;
+    }
+    double uh[3], Hh;
+    double ah = sqrt(half_state(P, nd, &w[2], &w[3], uh, &Hh));
+    double Lm[NCMAX][NCMAX], Rm[NCMAX][NCMAX];
+    eigvecs(P, nd, d, uh, Hh, ah, nv, Lm, Rm);
+    const double C6[6] = {1.0 / 60.0, -8.0 / 60.0, 37.0 / 60.0, 37.0 / 60.0, -8.0 / 60.0, 1.0 / 60.0};
+    const double D6[6] = {1.0 / 60.0, -5.0 / 60.0, 10.0 / 60.0, -10.0 / 60.0, 5.0 / 60.0, -1.0 / 60.0};
+    double cf[NCMAX], du[NCMAX], v[NCMAX];
+    for (int c = 0; c < nc; c++) {
+        cf[c] = 0.0;
+        du[c] = 0.0;
+        for (int k = 0; k < 6; k++) {
+            cf[c] += C6[k] * fk[k][c];
+            du[c] += D6[k] * Uk[k * nc + c];
+        }
+    }
+    for (int j = 0; j < nc; j++) {
+        double alpha = 0.0, s = 0.0;
+        for (int k = 0; k < 6; k++) alpha = fmax(alpha, fabs(lam[k][j]));
+        for (int c = 0; c < nc; c++) s += Lm[j][c] * du[c];
+        v[j] = alpha * s;
+    }
+    for (int c = 0; c < nc; c++) {
+        double s = 0.0;
+        for (int j = 0; j < nc; j++) s += Rm[c][j] * v[j];
+        F[c] = Smag * (cf[c] + s);
+    }
+}
+
+/* Sensor features of interface i+1/2 (ten values; reading of the sensor
+ * inputs "smoothness indicators + normalised rho/p jumps"):
+ *   f0..f3: Jiang-Shu three-point indicators B(a,b,c) = 13/12 (a-2b+c)^2 +
+ *     1/4 (a-c)^2 of rho/rho_bar + p/p_bar + (u.t_s)/a_bar summed over the
+ *     tangents, on the substencils {i-2..i}, {i-1..i+1}, {i..i+2},
+ *     {i+1..i+3}, divided by their sum (+1e-30);
+ *   f4..f6: |rho_{k+1} - rho_k| / (rho_{k+1} + rho_k) over (i-1,i), (i,i+1),
+ *     (i+1,i+2);  f7..f9: the same for p.
+ * rho_bar, p_bar: means of nodes i, i+1; a_bar = sqrt(gamma p_bar / rho_bar).
+ * Label: 1 iff every TENO stencil of every field and both splits is kept. */
+void orc_features(const orc_params *P, int d, const double *Uk, const double *S, double *feat, int *label)
+{
+    const int nd = P->ndim, nc = nd + 2;
+    double Smag = 0.0, nv[3] = {0.0, 0.0, 0.0};
+    for (int m = 0; m < nd; m++) Smag += S[m] * S[m];
+    Smag = sqrt(Smag);
+    for (int m = 0; m < nd; m++) nv[m] = S[m] / Smag;
+    double t[2][3];
+    tangents(nd, d, nv, t);
+    prim_t w[6];
+    for (int k = 0; k < 6; k++) to_prim(P, nd, Uk + k * nc, &w[k]);
+    const double rb = 0.5 * (w[2].rho + w[3].rho), pb = 0.5 * (w[2].p + w[3].p);
+    const double ab = sqrt(P->gamma * pb / rb);
+    double r[6], q[6], vt[2][6];
+    for (int k = 0; k < 6; k++) {
+        r[k] = w[k].rho / rb;
+        q[k] = w[k].p / pb;
+        for (int s = 0; s < nd - 1; s++) {
+            double ut = 0.0;
+            for (int m = 0; m < nd; m++) ut += w[k].u[m] * t[s][m];
+            vt[s][k] = ut / ab;
+        }
+    }
+    double beta[4], sum = 0.0;
+    for (int m = 0; m < 4; m++) {
+        double a1, a2, b;
+        a1 = r[m] - 2.0 * r[m + 1] + r[m + 2]; a2 = r[m] - r[m + 2];
+        b = (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
+        a1 = q[m] - 2.0 * q[m + 1] + q[m + 2]; a2 = q[m] - q[m + 2];
+        b += (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
+        for (int s = 0; s < nd - 1; s++) {
+            a1 = vt[s][m] - 2.0 * vt[s][m + 1] + vt[s][m + 2]; a2 = vt[s][m] - vt[s][m + 2];
+            b += (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
+        }
+        beta[m] = b;
+        sum += b;
+    }
+    for (int m = 0; m < 4; m++) feat[m] = beta[m] / (sum + 1e-30);
+    for (int m = 0; m < 3; m++) {
+        feat[4 + m] = fabs(w[m + 2].rho - w[m + 1].rho) / (w[m + 2].rho + w[m + 1].rho);
+        feat[7 + m] = fabs(w[m + 2].p - w[m + 1].p) / (w[m + 2].p + w[m + 1].p);
+    }
+    if (label) {
+        int dl[NCMAX * 2 * 3];
+        double F[NCMAX];
+        iface_flux(P, d, Uk, S, F, dl);
+        int all = 1;
+        for (int i = 0; i < nc * 2 * 3; i++) all &= dl[i];
+        *label = all;
+    }
+}
