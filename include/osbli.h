@@ -92,7 +92,7 @@ typedef struct osbli_params {
     double eps;                /* epsilon of the nonlinear weights (1e-16) */
     int32_t roe_avg;           /* 1: Roe average, 0: arithmetic mean of u, H */
     int32_t form;              /* enum osbli_form */
-    int32_t sensor;            /* 0: off (learned routing is a later form) */
+    int32_t sensor;            /* 1: learned-sensor routing (TENO5, separable mesh) */
     int32_t reserved;
     int32_t bc_kind[3][2];     /* enum osbli_bc per (direction, side) */
     double wall_T[3][2];       /* isothermal wall temperature per face */
@@ -154,6 +154,71 @@ const char *osbli_last_error(const osbli_ctx *ctx);
 /* Release the host-side context (the workspace stays with its owner). */
 void osbli_destroy(osbli_ctx *ctx);
 
+/* ---------------------------------------------------------------------
+ * Learned shock sensor (not in the paper, which names sensor-switched
+ * hybrid central/shock-capturing fluxes as hard to design for every flow).
+ * With params.sensor = 1 each interface is routed either to the full
+ * characteristic TENO5 flux or to its exact all-stencils-kept limit
+ *   F = |S| [C6 f + R diag(alpha) L D6 U],
+ *   C6 = (1,-8,37,37,-8,1)/60, D6 = (1,-5,10,-10,5,-1)/60 on i-2..i+3,
+ * by a 10 -> 32 -> 32 -> 1 network (ReLU, ReLU, sigmoid) evaluated on the
+ * matrix cores (bfloat16 operands, FP32 accumulation).  A misrouted
+ * interface is the form's only approximation.
+ *
+ * Features of interface i+1/2 (float32, ten per interface): Jiang-Shu
+ * three-point indicators of rho/rho_bar + p/p_bar + (u.t)/a_bar on the four
+ * substencils of i-2..i+3, normalised by their sum; |jump|/sum of rho and
+ * of p over (i-1,i), (i,i+1), (i+1,i+2).  Label: 1 iff every TENO5 stencil
+ * of every characteristic field and both splits is kept.
+ * Weights: 1441 bfloat16 values in the order W1[10][32] (input-major), b1[32],
+ * W2[32][32] (input-major), b2[32], w3[32], b3.
+ * --------------------------------------------------------------------- */
+
+/* Copy the routing network's weights (host array) into the context; route
+ * an interface to the cheap flux when P(smooth) >= threshold (and, with
+ * dilate, also at its two neighbours along the sweep).  Masks are refreshed
+ * at stage 0 of each RK step (every substage with every_substage) and by
+ * osbli_residual.  Synchronising. */
+int osbli_sensor_set_weights(osbli_ctx *ctx, const uint16_t *w_bf16_host, int n, double threshold, int dilate,
+                             int every_substage, void *stream);
+
+/* Recompute the routing masks of every direction from U. */
+int osbli_sensor_update(osbli_ctx *ctx, const double *U, void *stream);
+
+/* Number of interfaces routed to the cheap flux by the last mask refresh,
+ * and the total number of interfaces.  Synchronising. */
+int osbli_sensor_stats(osbli_ctx *ctx, int64_t *smooth, int64_t *total);
+
+/* Interfaces of all directions: sum_d (n_d + 1) prod_{e != d} n_e. */
+int osbli_interface_count(osbli_ctx *ctx, int64_t *count);
+
+/* Training data made by the method: features (device, count x 10 float32)
+ * and TENO5 all-kept labels (device, count bytes) of every interface of U,
+ * direction by direction, each direction in x-fastest order of its interface
+ * grid (extent n_d + 1 along d).  OSBLI_ENOSPACE if cap < count (count is
+ * still returned).  Needs TENO5 and a separable mesh. */
+int osbli_collect_labels(osbli_ctx *ctx, const double *U, float *feat, uint8_t *label, int64_t cap,
+                         int64_t *count, void *stream);
+
+/* Training of the network (context-free; all pointers device, stream-ordered).
+ * osbli_mlp_grad: mean class-weighted binary cross-entropy of sigmoid(z)
+ * against y over n samples (label-0 samples weigh w_neg), its gradient
+ * (1441 float32, with respect to the bfloat16 weights w) and the loss; FP32
+ * forward / backward; per-block partial sums in the workspace reduced in a
+ * fixed order (deterministic). */
+size_t osbli_mlp_workspace_bytes(int64_t n);
+int osbli_mlp_grad(const float *X, const uint8_t *y, int64_t n, const uint16_t *w, float w_neg, float *grad,
+                   float *loss, void *workspace, size_t ws_bytes, void *stream);
+
+/* Adam step t >= 1 on the FP32 master weights; writes their bfloat16 copy
+ * (round to nearest even) to w.  m, v: FP32 moment buffers (1441 each). */
+int osbli_mlp_adam(float *master, uint16_t *w, const float *grad, float *m, float *v, int64_t t, float lr,
+                   float b1, float b2, float eps, void *stream);
+
+/* Logits of n samples: inference = 0 FP32 VALU (training forward),
+ * inference = 1 the bfloat16 MFMA path used for routing. */
+int osbli_mlp_forward(const float *X, int64_t n, const uint16_t *w, float *z, int inference, void *stream);
+
 /* Kernel classes timed by the optional profiler. */
 enum osbli_kernel_class {
     OSBLI_K_SWEEP_X = 0,   /* convective sweep along x (y = 1, z = 2 follow) */
@@ -163,7 +228,8 @@ enum osbli_kernel_class {
     OSBLI_K_FINISH = 4,    /* viscous divergence + RK update (or residual store) */
     OSBLI_K_BC = 5,        /* boundary-condition launches of one osbli_apply_bc */
     OSBLI_K_DT = 6,        /* time-step reduction */
-    OSBLI_K_COUNT = 7
+    OSBLI_K_SENSOR = 7,    /* learned-sensor routing masks */
+    OSBLI_K_COUNT = 8
 };
 
 /* Instrumentation (not part of the method): when enabled, each launch group

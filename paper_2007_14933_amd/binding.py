@@ -59,10 +59,19 @@ _SIGS = {
     "osbli_destroy": (None, [_VP]),
     "osbli_profile_enable": (C.c_int, [_VP, C.c_int]),
     "osbli_profile_read": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int64), _DP]),
+    "osbli_sensor_set_weights": (C.c_int, [_VP, _VP, C.c_int, C.c_double, C.c_int, C.c_int, _VP]),
+    "osbli_sensor_update": (C.c_int, [_VP, _VP, _VP]),
+    "osbli_sensor_stats": (C.c_int, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "osbli_interface_count": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
+    "osbli_collect_labels": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int64, C.POINTER(C.c_int64), _VP]),
+    "osbli_mlp_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "osbli_mlp_grad": (C.c_int, [_VP, _VP, C.c_int64, _VP, C.c_float, _VP, _VP, _VP, C.c_size_t, _VP]),
+    "osbli_mlp_adam": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _VP]),
+    "osbli_mlp_forward": (C.c_int, [_VP, C.c_int64, _VP, _VP, C.c_int, _VP]),
 }
 
-K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_VISC_FLUX, K_FINISH, K_BC, K_DT = range(7)
-K_NAMES = ["sweep_x", "sweep_y", "sweep_z", "visc_flux", "finish", "bc", "dt"]
+K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_VISC_FLUX, K_FINISH, K_BC, K_DT, K_SENSOR = range(8)
+K_NAMES = ["sweep_x", "sweep_y", "sweep_z", "visc_flux", "finish", "bc", "dt", "sensor"]
 
 
 def load():

@@ -33,6 +33,11 @@ struct osbli_ctx {
     unsigned *flags;
     unsigned long long *red;
     double *Racc, *G;
+    uint8_t *mask[3];
+    uint16_t *wts;
+    int sensor_ready;      // weights set
+    int sensor_every;      // refresh the routing masks at every substage (else at stage 0)
+    float zcut;            // logit of the routing threshold
     hipStream_t last;
     int device;
     char err[320];
@@ -99,7 +104,11 @@ int make_grid(const osbli_params *p, Grid &g, char *buf, size_t nb) {
     if (!(p->gamma > 1.0)) { snprintf(buf, nb, "gamma must exceed 1"); return -1; }
     if (p->scheme != OSBLI_WENOZ5 && p->scheme != OSBLI_TENO5) { snprintf(buf, nb, "bad scheme"); return -1; }
     if (p->form != OSBLI_FORM_FP64 && p->form != OSBLI_FORM_MIXED) { snprintf(buf, nb, "bad form %d", p->form); return -1; }
-    if (p->sensor != 0) { snprintf(buf, nb, "sensor routing not available"); return -1; }
+    if (p->sensor != 0 && p->sensor != 1) { snprintf(buf, nb, "bad sensor flag"); return -1; }
+    if (p->sensor && (p->scheme != OSBLI_TENO5 || (p->mesh == OSBLI_MESH_GENERAL && p->ndim > 1))) {
+        snprintf(buf, nb, "sensor routing needs TENO5 on a separable mesh");
+        return -1;
+    }
     if (p->mesh != OSBLI_MESH_SEPARABLE && p->mesh != OSBLI_MESH_GENERAL) { snprintf(buf, nb, "bad mesh kind"); return -1; }
     bool walls = false;
     for (int d = 0; d < p->ndim; ++d)
@@ -144,6 +153,12 @@ Layout make_layout(const osbli_params *p, const Grid &g) {
     L.stage = off;
     size_t region = racc + gsz > stage ? racc + gsz : stage;
     off += region;
+    for (int d = 0; d < 3; ++d) {
+        L.mask[d] = off;
+        if (p->sensor && d < g.nd) off += align256((size_t)iface_count(g, d));
+    }
+    L.wts = off;
+    if (p->sensor) off += align256(2 * 1441);
     L.total = off;
     return L;
 }
@@ -168,6 +183,7 @@ Phys make_phys(const osbli_params *p) {
     ph.scheme = p->scheme;
     ph.roe = p->roe_avg;
     ph.mixed = p->form == OSBLI_FORM_MIXED;
+    ph.dilate = 1;
     return ph;
 }
 
@@ -218,9 +234,19 @@ int resolve_profile(osbli_ctx *c) {
 
 // convective sweeps of every direction into R (first stores, later accumulate)
 hipError_t convective_all(osbli_ctx *c, const double *U, double *R, hipStream_t s) {
+    const bool route = c->p.sensor && c->sensor_ready;
     for (int d = 0; d < c->g.nd; ++d) {
         Timed t(c, OSBLI_K_SWEEP_X + d, s);
-        hipError_t e = launch_convective(c->g, c->ph, c->m, U, R, c->flags, d, d == 0, s);
+        hipError_t e = launch_convective(c->g, c->ph, c->m, U, R, c->flags, d, d == 0, route ? c->mask[d] : nullptr, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t sensor_all(osbli_ctx *c, const double *U, hipStream_t s) {
+    Timed t(c, OSBLI_K_SENSOR, s);
+    for (int d = 0; d < c->g.nd; ++d) {
+        hipError_t e = launch_sensor(c->g, c->ph, U, d, c->wts, c->zcut, c->mask[d], s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -268,6 +294,11 @@ int osbli_init_grid(osbli_ctx **out, const osbli_params *p, const double *x, con
     c->red = reinterpret_cast<unsigned long long *>(c->ws + c->L.red);
     c->Racc = reinterpret_cast<double *>(c->ws + c->L.Racc);
     c->G = reinterpret_cast<double *>(c->ws + c->L.G);
+    for (int d = 0; d < 3; ++d) c->mask[d] = reinterpret_cast<uint8_t *>(c->ws + c->L.mask[d]);
+    c->wts = reinterpret_cast<uint16_t *>(c->ws + c->L.wts);
+    c->sensor_ready = 0;
+    c->sensor_every = 0;
+    c->zcut = 0.0f;
     HIP_TRY(c, launch_fill_u64(reinterpret_cast<unsigned long long *>(c->ws), 0ull, 64, s));
 
     const bool gen = general_mesh(p);
@@ -323,6 +354,7 @@ int osbli_residual(osbli_ctx *c, const double *U, double *R, void *stream) {
     if ((const void *)U == (const void *)R) return set_err(c, OSBLI_EINVAL, "R aliases U");
     hipStream_t s = as_stream(stream);
     c->last = s;
+    if (c->p.sensor && c->sensor_ready) HIP_TRY(c, sensor_all(c, U, s));
     if (c->ph.viscous) {
         Timed t(c, OSBLI_K_VISC_FLUX, s);
         HIP_TRY(c, launch_viscous_fluxes(c->g, c->ph, c->m, U, c->G, s));
@@ -341,6 +373,7 @@ int osbli_rk_substep(osbli_ctx *c, int stage, double dt, double *U, double *dU, 
     if ((void *)U == (void *)dU) return set_err(c, OSBLI_EINVAL, "dU aliases U");
     hipStream_t s = as_stream(stream);
     c->last = s;
+    if (c->p.sensor && c->sensor_ready && (stage == 0 || c->sensor_every)) HIP_TRY(c, sensor_all(c, U, s));
     if (c->ph.viscous) {
         Timed t(c, OSBLI_K_VISC_FLUX, s);
         HIP_TRY(c, launch_viscous_fluxes(c->g, c->ph, c->m, U, c->G, s));
@@ -386,6 +419,102 @@ int osbli_check(osbli_ctx *c) {
 }
 
 const char *osbli_last_error(const osbli_ctx *c) { return c ? c->err : "null context"; }
+
+int osbli_sensor_set_weights(osbli_ctx *c, const uint16_t *w, int n, double threshold, int dilate, int every_substage,
+                             void *stream) {
+    if (!c || !w) return set_err(c, OSBLI_EINVAL, "null argument");
+    if (!c->p.sensor) return set_err(c, OSBLI_EINVAL, "context created without sensor routing");
+    if (n != 1441) return set_err(c, OSBLI_EINVAL, "expected 1441 bfloat16 weights, got %d", n);
+    if (!(threshold > 0.0 && threshold < 1.0)) return set_err(c, OSBLI_EINVAL, "threshold must lie in (0, 1)");
+    hipStream_t s = as_stream(stream);
+    c->last = s;
+    HIP_TRY(c, hipMemcpyAsync(c->wts, w, sizeof(uint16_t) * 1441, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->zcut = (float)log(threshold / (1.0 - threshold));
+    c->ph.dilate = dilate != 0;
+    c->sensor_every = every_substage != 0;
+    c->sensor_ready = 1;
+    return OSBLI_OK;
+}
+
+int osbli_sensor_update(osbli_ctx *c, const double *U, void *stream) {
+    if (!c || !U) return set_err(c, OSBLI_EINVAL, "null argument");
+    if (!c->p.sensor || !c->sensor_ready) return set_err(c, OSBLI_EINVAL, "sensor weights not set");
+    hipStream_t s = as_stream(stream);
+    c->last = s;
+    HIP_TRY(c, sensor_all(c, U, s));
+    return OSBLI_OK;
+}
+
+int osbli_sensor_stats(osbli_ctx *c, int64_t *smooth, int64_t *total) {
+    if (!c || !smooth || !total) return set_err(c, OSBLI_EINVAL, "null argument");
+    if (!c->p.sensor || !c->sensor_ready) return set_err(c, OSBLI_EINVAL, "sensor weights not set");
+    hipStream_t s = c->last;
+    HIP_TRY(c, launch_fill_u64(c->red + 1, 0ull, 1, s));
+    int64_t tot = 0;
+    for (int d = 0; d < c->g.nd; ++d) {
+        HIP_TRY(c, launch_count_u8(c->mask[d], iface_count(c->g, d), c->red + 1, s));
+        tot += iface_count(c->g, d);
+    }
+    unsigned long long cnt = 0;
+    HIP_TRY(c, hipMemcpyAsync(&cnt, c->red + 1, sizeof cnt, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    *smooth = (int64_t)cnt;
+    *total = tot;
+    return OSBLI_OK;
+}
+
+int osbli_interface_count(osbli_ctx *c, int64_t *count) {
+    if (!c || !count) return set_err(c, OSBLI_EINVAL, "null argument");
+    int64_t tot = 0;
+    for (int d = 0; d < c->g.nd; ++d) tot += iface_count(c->g, d);
+    *count = tot;
+    return OSBLI_OK;
+}
+
+int osbli_collect_labels(osbli_ctx *c, const double *U, float *feat, uint8_t *label, int64_t cap, int64_t *count,
+                         void *stream) {
+    if (!c || !U || !feat || !label || !count) return set_err(c, OSBLI_EINVAL, "null argument");
+    if (c->p.scheme != OSBLI_TENO5) return set_err(c, OSBLI_EINVAL, "labels are TENO5 cut-off decisions");
+    if (c->m.general) return set_err(c, OSBLI_EINVAL, "labels need a separable mesh");
+    int64_t tot = 0;
+    for (int d = 0; d < c->g.nd; ++d) tot += iface_count(c->g, d);
+    *count = tot;
+    if (cap < tot) return set_err(c, OSBLI_ENOSPACE, "label buffers hold %lld, need %lld", (long long)cap, (long long)tot);
+    hipStream_t s = as_stream(stream);
+    c->last = s;
+    int64_t off = 0;
+    for (int d = 0; d < c->g.nd; ++d) {
+        HIP_TRY(c, launch_labels(c->g, c->ph, U, d, feat + off * 10, label + off, s));
+        off += iface_count(c->g, d);
+    }
+    return OSBLI_OK;
+}
+
+size_t osbli_mlp_workspace_bytes(int64_t n) { return n > 0 ? mlp_workspace_bytes(n) : 0; }
+
+int osbli_mlp_grad(const float *X, const uint8_t *y, int64_t n, const uint16_t *w, float w_neg, float *grad,
+                   float *loss, void *workspace, size_t ws_bytes, void *stream) {
+    if (!X || !y || !w || !grad || !workspace || n <= 0) return OSBLI_EINVAL;
+    if (ws_bytes < mlp_workspace_bytes(n)) return OSBLI_ENOSPACE;
+    return launch_mlp_grad(X, y, n, w, w_neg, grad, loss, static_cast<float *>(workspace), as_stream(stream)) ==
+                   hipSuccess
+               ? OSBLI_OK
+               : OSBLI_EDEVICE;
+}
+
+int osbli_mlp_adam(float *master, uint16_t *w, const float *grad, float *m, float *v, int64_t t, float lr, float b1,
+                   float b2, float eps, void *stream) {
+    if (!master || !w || !grad || !m || !v || t < 1) return OSBLI_EINVAL;
+    return launch_mlp_adam(master, w, grad, m, v, t, lr, b1, b2, eps, as_stream(stream)) == hipSuccess
+               ? OSBLI_OK
+               : OSBLI_EDEVICE;
+}
+
+int osbli_mlp_forward(const float *X, int64_t n, const uint16_t *w, float *z, int inference, void *stream) {
+    if (!X || !w || !z || n <= 0) return OSBLI_EINVAL;
+    return launch_mlp_forward(X, n, w, z, inference, as_stream(stream)) == hipSuccess ? OSBLI_OK : OSBLI_EDEVICE;
+}
 
 int osbli_profile_enable(osbli_ctx *c, int enable) {
     if (!c) return OSBLI_EINVAL;

@@ -1,0 +1,543 @@
+// Device building blocks of the characteristic interface flux (section 2.2,
+// enumerated algorithm; reconstructions of sections 2.3-2.5), shared by the
+// convective sweeps and the sensor kernels.  Local frame (n, t1, t2): with
+// f_k = u_n U_k + p_k (0, n, u_n) the projected flux is
+// g_kj = u_n,k V_kj + p_k (l_j,m . n + l_j,E u_n,k), so only V = L U is
+// formed per point and L, R are never stored as matrices.
+#pragma once
+
+#include "internal.hpp"
+
+namespace osbli {
+namespace cf {
+
+
+template <int ND>
+struct Pt {
+    double U[ND + 2];
+    double ri, p, a;
+};
+
+// Local-frame view of one stencil point: normal / tangential momentum.
+template <int ND>
+struct Loc {
+    double r, mn, mt[2], E, p, a, ri;
+};
+
+// derived quantities of a point whose conserved state is in w.U
+template <int ND>
+__device__ __forceinline__ void finish_point(const Phys &ph, Pt<ND> &w, bool &bad) {
+    const double ri = 1.0 / w.U[0];
+    double ke = 0.0;
+#pragma unroll
+    for (int m = 0; m < ND; ++m) ke += w.U[1 + m] * w.U[1 + m];
+    const double p = ph.gm1 * (w.U[ND + 1] - 0.5 * ke * ri);
+    w.ri = ri;
+    w.p = p;
+    w.a = sqrt(ph.gamma * p * ri);
+    bad |= !(w.U[0] > 0.0 && p > 0.0);
+}
+
+// Fifth-order WENO-Z / TENO reconstruction at x_{i+1/2} from f_{i-2..i+2}.
+// Candidate stencils S_r = {i-r .. i-r+2}, Jiang-Shu indicators,
+// tau_5 = |beta_0 - beta_2|; WENO-Z alpha_r = d_r (1 + (tau/(beta_r+eps))^2);
+// TENO gamma_r = (1 + tau/(beta_r+eps))^6, stencil r cut when
+// gamma_r / sum(gamma) < C_T (evaluated as gamma_r < C_T * sum), weights
+// d_r delta_r / sum(d delta).  The three ratios tau/(beta_r+eps) share one
+// reciprocal of the product of the denominators; TENO's normalisation is a
+// reciprocal of one of seven sums of optimal weights, skipped when no
+// stencil is cut (sum = 1).
+template <int SCHEME>
+__device__ __forceinline__ double recon5(double fm2, double fm1, double f0, double fp1, double fp2,
+                                         double CT, double eps, bool *kept = nullptr) {
+    const double q0 = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
+    const double q1 = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
+    const double q2 = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
+    double s, t;
+    s = f0 - 2.0 * fp1 + fp2;
+    t = 3.0 * f0 - 4.0 * fp1 + fp2;
+    const double b0 = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    s = fm1 - 2.0 * f0 + fp1;
+    t = fm1 - fp1;
+    const double b1 = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    s = fm2 - 2.0 * fm1 + f0;
+    t = fm2 - 4.0 * fm1 + 3.0 * f0;
+    const double b2 = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    const double tau = fabs(b0 - b2);
+    const double e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
+    const double e01 = e0 * e1;
+    const double tinv = tau / (e01 * e2);
+    const double x0 = (e1 * e2) * tinv, x1 = (e0 * e2) * tinv, x2 = e01 * tinv;
+    if (SCHEME == OSBLI_WENOZ5) {
+        const double a0 = 0.3 * (1.0 + x0 * x0);
+        const double a1 = 0.6 * (1.0 + x1 * x1);
+        const double a2 = 0.1 * (1.0 + x2 * x2);
+        return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+    } else {
+        double c0 = 1.0 + x0, c1 = 1.0 + x1, c2 = 1.0 + x2;
+        c0 = c0 * c0 * c0;
+        c1 = c1 * c1 * c1;
+        c2 = c2 * c2 * c2;
+        const double g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2;
+        const double lim = CT * (g0 + g1 + g2);
+        const bool k0 = !(g0 < lim), k1 = !(g1 < lim), k2 = !(g2 < lim);
+        const double w0 = k0 ? 0.3 : 0.0;
+        const double w1 = k1 ? 0.6 : 0.0;
+        const double w2 = k2 ? 0.1 : 0.0;
+        const double num = w0 * q0 + w1 * q1 + w2 * q2;
+        if (kept) *kept = *kept && k0 && k1 && k2;
+        if (k0 && k1 && k2) return num;
+        return num / (w0 + w1 + w2);
+    }
+}
+
+// LLF split of one characteristic field over the six points and the two
+// reconstructions: ghat = recon+(g+_{i-2..i+2}) + recon-(g-_{i+3..i-1}).
+template <int SCHEME>
+__device__ __forceinline__ double split_recon(const double (&V)[6], const double (&g)[6], double alpha,
+                                              const Phys &ph, bool *kept = nullptr) {
+    double gp[6], gm[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        gp[k] = 0.5 * (g[k] + alpha * V[k]);
+        gm[k] = 0.5 * (g[k] - alpha * V[k]);
+    }
+    return recon5<SCHEME>(gp[0], gp[1], gp[2], gp[3], gp[4], ph.CT, ph.eps, kept) +
+           recon5<SCHEME>(gm[5], gm[4], gm[3], gm[2], gm[1], ph.CT, ph.eps, kept);
+}
+
+// Interface flux in the local frame (unit |S|).  Outputs: mass, normal
+// momentum, tangential momenta, energy.
+template <int ND, int SCHEME>
+__device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph, double &Fr, double &Fn,
+                                          double (&Ft)[2], double &FE, bool *kept = nullptr) {
+    constexpr int NT = ND - 1;  // tangents
+    // averaged state at the half node (Roe, or arithmetic mean with unit weights)
+    double sl = 1.0, sr = 1.0;
+    if (ph.roe) {
+        sl = sqrt(P[2].r);
+        sr = sqrt(P[3].r);
+    }
+    const double iw = 1.0 / (sl + sr);
+    const double un = (sl * (P[2].mn * P[2].ri) + sr * (P[3].mn * P[3].ri)) * iw;
+    double ut[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NT; ++s) ut[s] = (sl * (P[2].mt[s] * P[2].ri) + sr * (P[3].mt[s] * P[3].ri)) * iw;
+    const double Hh = (sl * ((P[2].E + P[2].p) * P[2].ri) + sr * ((P[3].E + P[3].p) * P[3].ri)) * iw;
+    double K = un * un;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) K += ut[s] * ut[s];
+    K *= 0.5;
+    const double ah = sqrt(ph.gm1 * (Hh - K));
+    const double ia = 1.0 / ah;
+    const double b = ph.gm1 * ia * ia;
+
+    double unk[6], A[6], B[6], am[6], ap[6], a0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        unk[k] = P[k].mn * P[k].ri;
+        double um = un * P[k].mn;
+#pragma unroll
+        for (int s = 0; s < NT; ++s) um += ut[s] * P[k].mt[s];
+        A[k] = b * (K * P[k].r - um + P[k].E);
+        B[k] = (un * P[k].r - P[k].mn) * ia;
+        am[k] = fabs(unk[k] - P[k].a);
+        ap[k] = fabs(unk[k] + P[k].a);
+        a0 = fmax(a0, fabs(unk[k]));
+    }
+    double aminus = am[0], aplus = ap[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) {
+        aminus = fmax(aminus, am[k]);
+        aplus = fmax(aplus, ap[k]);
+    }
+    double V[6], g[6];
+    // field u_n - a
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = 0.5 * (A[k] + B[k]);
+        g[k] = unk[k] * V[k] + P[k].p * (0.5 * b * unk[k] - 0.5 * (b * un + ia));
+    }
+    const double h0 = split_recon<SCHEME>(V, g, aminus, ph, kept);
+    // field u_n + a
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = 0.5 * (A[k] - B[k]);
+        g[k] = unk[k] * V[k] + P[k].p * (0.5 * b * unk[k] - 0.5 * (b * un - ia));
+    }
+    const double h4 = split_recon<SCHEME>(V, g, aplus, ph, kept);
+    // entropy field
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = P[k].r - A[k];
+        g[k] = unk[k] * V[k] + P[k].p * (b * (un - unk[k]));
+    }
+    const double h1 = split_recon<SCHEME>(V, g, a0, ph, kept);
+    // shear fields
+    double ht[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            V[k] = P[k].mt[s] - ut[s] * P[k].r;
+            g[k] = unk[k] * V[k];
+        }
+        ht[s] = split_recon<SCHEME>(V, g, a0, ph, kept);
+    }
+    // back to physical space: F = R ghat
+    const double hs = h0 + h1 + h4;
+    const double hd = h4 - h0;
+    Fr = hs;
+    Fn = un * hs + ah * hd;
+    FE = Hh * (h0 + h4) + ah * un * hd + K * h1;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        Ft[s] = ut[s] * hs + ht[s];
+        FE += ut[s] * ht[s];
+    }
+}
+
+// ---------------------------------------------------------------- mixed form
+// Reconstruction and flux evaluation in FP32 on deviations from an FP64
+// reference: with U_ref = U_i, f_ref = f(U_i) (local frame, FP64), the split
+// fluxes are g+- = (L f_ref +- alpha L U_ref)/2 + (L df +- alpha L dU)/2, and
+// both reconstructions are exactly shift-equivariant (sum of weights 1,
+// smoothness indicators use differences only), so
+//   F = f_ref + R (recon+(dg+) + recon-(dg-)).
+// f_ref and the final sum are FP64; everything between runs on the FP32
+// deviations, whose rounding is relative to |df|, not to |f|.
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// FP32 WENO-Z / TENO with overflow-safe weights: the TENO cut-off is
+// evaluated on c_r / max(c) (gamma_r = (1 + tau/(beta_r+eps))^6 exceeds the
+// FP32 range at nearly every jump), WENO-Z's alpha on x_r / max(x) once
+// max(x) >= 1.  Both are algebraically the FP64 test.
+template <int SCHEME>
+__device__ __forceinline__ float recon5f(float fm2, float fm1, float f0, float fp1, float fp2, float CT, float eps) {
+    const float q0 = (1.0f / 3.0f) * f0 + (5.0f / 6.0f) * fp1 - (1.0f / 6.0f) * fp2;
+    const float q1 = -(1.0f / 6.0f) * fm1 + (5.0f / 6.0f) * f0 + (1.0f / 3.0f) * fp1;
+    const float q2 = (1.0f / 3.0f) * fm2 - (7.0f / 6.0f) * fm1 + (11.0f / 6.0f) * f0;
+    float s, t;
+    s = f0 - 2.0f * fp1 + fp2;
+    t = 3.0f * f0 - 4.0f * fp1 + fp2;
+    const float b0 = (13.0f / 12.0f) * s * s + 0.25f * t * t;
+    s = fm1 - 2.0f * f0 + fp1;
+    t = fm1 - fp1;
+    const float b1 = (13.0f / 12.0f) * s * s + 0.25f * t * t;
+    s = fm2 - 2.0f * fm1 + f0;
+    t = fm2 - 4.0f * fm1 + 3.0f * f0;
+    const float b2 = (13.0f / 12.0f) * s * s + 0.25f * t * t;
+    const float tau = fabsf(b0 - b2);
+    const float x0 = tau * rcpf(b0 + eps), x1 = tau * rcpf(b1 + eps), x2 = tau * rcpf(b2 + eps);
+    if (SCHEME == OSBLI_WENOZ5) {
+        const float xm = fmaxf(x0, fmaxf(x1, x2));
+        float a0, a1, a2;
+        if (xm < 1.0f) {
+            a0 = 0.3f * (1.0f + x0 * x0);
+            a1 = 0.6f * (1.0f + x1 * x1);
+            a2 = 0.1f * (1.0f + x2 * x2);
+        } else {
+            const float h = rcpf(xm);
+            const float w0 = x0 * h, w1 = x1 * h, w2 = x2 * h, h2 = h * h;
+            a0 = 0.3f * (h2 + w0 * w0);
+            a1 = 0.6f * (h2 + w1 * w1);
+            a2 = 0.1f * (h2 + w2 * w2);
+        }
+        return (a0 * q0 + a1 * q1 + a2 * q2) * rcpf(a0 + a1 + a2);
+    } else {
+        const float c0 = 1.0f + x0, c1 = 1.0f + x1, c2 = 1.0f + x2;
+        const float ic = rcpf(fmaxf(c0, fmaxf(c1, c2)));
+        float r0 = c0 * ic, r1 = c1 * ic, r2 = c2 * ic;
+        r0 = r0 * r0 * r0;
+        r1 = r1 * r1 * r1;
+        r2 = r2 * r2 * r2;
+        const float g0 = r0 * r0, g1 = r1 * r1, g2 = r2 * r2;
+        const float lim = CT * (g0 + g1 + g2);
+        const bool k0 = !(g0 < lim), k1 = !(g1 < lim), k2 = !(g2 < lim);
+        const float w0 = k0 ? 0.3f : 0.0f, w1 = k1 ? 0.6f : 0.0f, w2 = k2 ? 0.1f : 0.0f;
+        const float num = w0 * q0 + w1 * q1 + w2 * q2;
+        if (k0 && k1 && k2) return num;
+        return num * rcpf(w0 + w1 + w2);
+    }
+}
+
+template <int SCHEME>
+__device__ __forceinline__ float split_reconf(const float (&V)[6], const float (&G)[6], float alpha, float CT,
+                                              float eps) {
+    float gp[6], gm[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        gp[k] = 0.5f * (G[k] + alpha * V[k]);
+        gm[k] = 0.5f * (G[k] - alpha * V[k]);
+    }
+    return recon5f<SCHEME>(gp[0], gp[1], gp[2], gp[3], gp[4], CT, eps) +
+           recon5f<SCHEME>(gm[5], gm[4], gm[3], gm[2], gm[1], CT, eps);
+}
+
+template <int ND, int SCHEME>
+__device__ __forceinline__ void char_flux_mixed(const Loc<ND> (&P)[6], const Phys &ph, double &Fr, double &Fn,
+                                                double (&Ft)[2], double &FE) {
+    constexpr int NT = ND - 1;
+    // FP64 reference flux of node i in the local frame:
+    // f = u_n (rho, m_n, m_t, E) + p (0, 1, 0, u_n)
+    double un64[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) un64[k] = P[k].mn * P[k].ri;
+    const double fr0 = P[2].mn;
+    const double fn0 = P[2].mn * un64[2] + P[2].p;
+    double ft0[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NT; ++s) ft0[s] = P[2].mt[s] * un64[2];
+    const double fE0 = (P[2].E + P[2].p) * un64[2];
+
+    float dr[6], dmn[6], dmt[2][6], dE[6], gr[6], gmn[6], gmt[2][6], gE[6], unf[6], af[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        dr[k] = (float)(P[k].r - P[2].r);
+        dmn[k] = (float)(P[k].mn - P[2].mn);
+        dE[k] = (float)(P[k].E - P[2].E);
+        gr[k] = (float)(P[k].mn - fr0);
+        gmn[k] = (float)(P[k].mn * un64[k] + P[k].p - fn0);
+        gE[k] = (float)((P[k].E + P[k].p) * un64[k] - fE0);
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            dmt[s][k] = (float)(P[k].mt[s] - P[2].mt[s]);
+            gmt[s][k] = (float)(P[k].mt[s] * un64[k] - ft0[s]);
+        }
+        unf[k] = (float)un64[k];
+        af[k] = (float)P[k].a;
+    }
+    // averaged state of nodes i, i+1 in FP32
+    float sl = 1.0f, sr = 1.0f;
+    if (ph.roe) {
+        sl = sqrtf((float)P[2].r);
+        sr = sqrtf((float)P[3].r);
+    }
+    const float iw = rcpf(sl + sr);
+    const float un = (sl * unf[2] + sr * unf[3]) * iw;
+    float ut[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < NT; ++s)
+        ut[s] = (sl * (float)(P[2].mt[s] * P[2].ri) + sr * (float)(P[3].mt[s] * P[3].ri)) * iw;
+    const float Hl = (float)((P[2].E + P[2].p) * P[2].ri), Hr = (float)((P[3].E + P[3].p) * P[3].ri);
+    const float Hh = (sl * Hl + sr * Hr) * iw;
+    float K = un * un;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) K += ut[s] * ut[s];
+    K *= 0.5f;
+    const float gm1 = (float)ph.gm1;
+    const float ah = sqrtf(gm1 * (Hh - K));
+    const float ia = rcpf(ah);
+    const float b = gm1 * ia * ia;
+    const float CT = (float)ph.CT, eps = (float)ph.eps;
+
+    float A[6], B[6], Ag[6], Bg[6], aminus = 0.0f, aplus = 0.0f, a0 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float um = un * dmn[k], ug = un * gmn[k];
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            um += ut[s] * dmt[s][k];
+            ug += ut[s] * gmt[s][k];
+        }
+        A[k] = b * (K * dr[k] - um + dE[k]);
+        B[k] = (un * dr[k] - dmn[k]) * ia;
+        Ag[k] = b * (K * gr[k] - ug + gE[k]);
+        Bg[k] = (un * gr[k] - gmn[k]) * ia;
+        aminus = fmaxf(aminus, fabsf(unf[k] - af[k]));
+        aplus = fmaxf(aplus, fabsf(unf[k] + af[k]));
+        a0 = fmaxf(a0, fabsf(unf[k]));
+    }
+    float V[6], G[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = 0.5f * (A[k] + B[k]);
+        G[k] = 0.5f * (Ag[k] + Bg[k]);
+    }
+    const float h0 = split_reconf<SCHEME>(V, G, aminus, CT, eps);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = 0.5f * (A[k] - B[k]);
+        G[k] = 0.5f * (Ag[k] - Bg[k]);
+    }
+    const float h4 = split_reconf<SCHEME>(V, G, aplus, CT, eps);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        V[k] = dr[k] - A[k];
+        G[k] = gr[k] - Ag[k];
+    }
+    const float h1 = split_reconf<SCHEME>(V, G, a0, CT, eps);
+    float ht[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            V[k] = dmt[s][k] - ut[s] * dr[k];
+            G[k] = gmt[s][k] - ut[s] * gr[k];
+        }
+        ht[s] = split_reconf<SCHEME>(V, G, a0, CT, eps);
+    }
+    const float hs = h0 + h1 + h4, hd = h4 - h0;
+    float dFE = Hh * (h0 + h4) + ah * un * hd + K * h1;
+    Fr = fr0 + (double)hs;
+    Fn = fn0 + (double)(un * hs + ah * hd);
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        Ft[s] = ft0[s] + (double)(ut[s] * hs + ht[s]);
+        dFE += ut[s] * ht[s];
+    }
+    FE = fE0 + (double)dFE;
+}
+
+
+// ------------------------------------------------------------- cheap flux
+// Exact all-stencils-kept limit of char_flux: summing the split upwind-5
+// reconstructions gives F = C6 f + R diag(alpha) L D6 U with
+// C6 = (1, -8, 37, 37, -8, 1)/60 and D6 = (1, -5, 10, -10, 5, -1)/60 on
+// i-2..i+3 (same averaged state, L, R and alpha as the full flux).
+template <int ND>
+__device__ __forceinline__ void cheap_flux(const Loc<ND> (&P)[6], const Phys &ph, double &Fr, double &Fn,
+                                           double (&Ft)[2], double &FE) {
+    constexpr int NT = ND - 1;
+    constexpr double C6[6] = {1.0 / 60.0, -8.0 / 60.0, 37.0 / 60.0, 37.0 / 60.0, -8.0 / 60.0, 1.0 / 60.0};
+    constexpr double D6[6] = {1.0 / 60.0, -5.0 / 60.0, 10.0 / 60.0, -10.0 / 60.0, 5.0 / 60.0, -1.0 / 60.0};
+    double sl = 1.0, sr = 1.0;
+    if (ph.roe) {
+        sl = sqrt(P[2].r);
+        sr = sqrt(P[3].r);
+    }
+    const double iw = 1.0 / (sl + sr);
+    const double un = (sl * (P[2].mn * P[2].ri) + sr * (P[3].mn * P[3].ri)) * iw;
+    double ut[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NT; ++s) ut[s] = (sl * (P[2].mt[s] * P[2].ri) + sr * (P[3].mt[s] * P[3].ri)) * iw;
+    const double Hh = (sl * ((P[2].E + P[2].p) * P[2].ri) + sr * ((P[3].E + P[3].p) * P[3].ri)) * iw;
+    double K = un * un;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) K += ut[s] * ut[s];
+    K *= 0.5;
+    const double ah = sqrt(ph.gm1 * (Hh - K));
+    const double ia = 1.0 / ah;
+    const double b = ph.gm1 * ia * ia;
+    double aminus = 0.0, aplus = 0.0, a0 = 0.0;
+    double cr = 0.0, cn = 0.0, ct[2] = {0.0, 0.0}, cE = 0.0;   // C6 f
+    double dr = 0.0, dn = 0.0, dt[2] = {0.0, 0.0}, dE = 0.0;   // D6 U
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double unk = P[k].mn * P[k].ri;
+        aminus = fmax(aminus, fabs(unk - P[k].a));
+        aplus = fmax(aplus, fabs(unk + P[k].a));
+        a0 = fmax(a0, fabs(unk));
+        cr += C6[k] * P[k].mn;
+        cn += C6[k] * (P[k].mn * unk + P[k].p);
+        cE += C6[k] * ((P[k].E + P[k].p) * unk);
+        dr += D6[k] * P[k].r;
+        dn += D6[k] * P[k].mn;
+        dE += D6[k] * P[k].E;
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            ct[s] += C6[k] * (P[k].mt[s] * unk);
+            dt[s] += D6[k] * P[k].mt[s];
+        }
+    }
+    double um = un * dn;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) um += ut[s] * dt[s];
+    const double A = b * (K * dr - um + dE);
+    const double B = (un * dr - dn) * ia;
+    const double v0 = aminus * 0.5 * (A + B);
+    const double v4 = aplus * 0.5 * (A - B);
+    const double v1 = a0 * (dr - A);
+    const double hs = v0 + v1 + v4, hd = v4 - v0;
+    Fr = cr + hs;
+    Fn = cn + un * hs + ah * hd;
+    FE = cE + Hh * (v0 + v4) + ah * un * hd + K * v1;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        const double vt = a0 * (dt[s] - ut[s] * dr);
+        Ft[s] = ct[s] + ut[s] * hs + vt;
+        FE += ut[s] * vt;
+    }
+}
+
+// the cheap flux on FP32 deviations from the FP64 flux of node i
+// (C6 sums to 1 and D6 to 0, so F = f_ref + C6 (f - f_ref) + R alpha L D6 (U - U_i))
+template <int ND>
+__device__ __forceinline__ void cheap_flux_mixed(const Loc<ND> (&P)[6], const Phys &ph, double &Fr, double &Fn,
+                                                 double (&Ft)[2], double &FE) {
+    constexpr int NT = ND - 1;
+    constexpr float C6[6] = {1.0f / 60.0f, -8.0f / 60.0f, 37.0f / 60.0f, 37.0f / 60.0f, -8.0f / 60.0f, 1.0f / 60.0f};
+    constexpr float D6[6] = {1.0f / 60.0f, -5.0f / 60.0f, 10.0f / 60.0f, -10.0f / 60.0f, 5.0f / 60.0f, -1.0f / 60.0f};
+    double un64[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) un64[k] = P[k].mn * P[k].ri;
+    const double fr0 = P[2].mn;
+    const double fn0 = P[2].mn * un64[2] + P[2].p;
+    double ft0[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NT; ++s) ft0[s] = P[2].mt[s] * un64[2];
+    const double fE0 = (P[2].E + P[2].p) * un64[2];
+    float sl = 1.0f, sr = 1.0f;
+    if (ph.roe) {
+        sl = sqrtf((float)P[2].r);
+        sr = sqrtf((float)P[3].r);
+    }
+    const float iw = rcpf(sl + sr);
+    const float un = (sl * (float)un64[2] + sr * (float)un64[3]) * iw;
+    float ut[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < NT; ++s)
+        ut[s] = (sl * (float)(P[2].mt[s] * P[2].ri) + sr * (float)(P[3].mt[s] * P[3].ri)) * iw;
+    const float Hh = (sl * (float)((P[2].E + P[2].p) * P[2].ri) + sr * (float)((P[3].E + P[3].p) * P[3].ri)) * iw;
+    float K = un * un;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) K += ut[s] * ut[s];
+    K *= 0.5f;
+    const float gm1 = (float)ph.gm1;
+    const float ah = sqrtf(gm1 * (Hh - K));
+    const float ia = rcpf(ah);
+    const float b = gm1 * ia * ia;
+    float aminus = 0.0f, aplus = 0.0f, a0 = 0.0f;
+    float cr = 0.0f, cn = 0.0f, ct[2] = {0.0f, 0.0f}, cE = 0.0f;
+    float dr = 0.0f, dn = 0.0f, dt[2] = {0.0f, 0.0f}, dE = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const float unk = (float)un64[k], ak = (float)P[k].a;
+        aminus = fmaxf(aminus, fabsf(unk - ak));
+        aplus = fmaxf(aplus, fabsf(unk + ak));
+        a0 = fmaxf(a0, fabsf(unk));
+        cr += C6[k] * (float)(P[k].mn - fr0);
+        cn += C6[k] * (float)(P[k].mn * un64[k] + P[k].p - fn0);
+        cE += C6[k] * (float)((P[k].E + P[k].p) * un64[k] - fE0);
+        dr += D6[k] * (float)(P[k].r - P[2].r);
+        dn += D6[k] * (float)(P[k].mn - P[2].mn);
+        dE += D6[k] * (float)(P[k].E - P[2].E);
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            ct[s] += C6[k] * (float)(P[k].mt[s] * un64[k] - ft0[s]);
+            dt[s] += D6[k] * (float)(P[k].mt[s] - P[2].mt[s]);
+        }
+    }
+    float um = un * dn;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) um += ut[s] * dt[s];
+    const float A = b * (K * dr - um + dE);
+    const float B = (un * dr - dn) * ia;
+    const float v0 = aminus * 0.5f * (A + B);
+    const float v4 = aplus * 0.5f * (A - B);
+    const float v1 = a0 * (dr - A);
+    const float hs = v0 + v1 + v4, hd = v4 - v0;
+    float dFE = cE + Hh * (v0 + v4) + ah * un * hd + K * v1;
+    Fr = fr0 + (double)(cr + hs);
+    Fn = fn0 + (double)(cn + un * hs + ah * hd);
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        const float vt = a0 * (dt[s] - ut[s] * dr);
+        Ft[s] = ft0[s] + (double)(ct[s] + ut[s] * hs + vt);
+        dFE += ut[s] * vt;
+    }
+    FE = fE0 + (double)dFE;
+}
+
+}  // namespace cf
+}  // namespace osbli

@@ -33,6 +33,7 @@ struct Phys {
     double nu_fac;     // max(4/3, gamma/Pr)
     int sutherland, scheme, roe, viscous;
     int mixed;         // FP32 reconstruction / flux evaluation on FP64 deviations
+    int dilate;        // routed form: cheap flux only if the neighbours along the line are smooth too
 };
 
 // Metric terms.  Separable meshes keep 1/h_d per direction (h_d = D_d x_d);
@@ -46,7 +47,7 @@ struct Metrics {
 
 // Device workspace carve-up (byte offsets into the caller's buffer).
 struct Layout {
-    size_t flags, red, invh[3], S, J, Racc, G, stage, total;
+    size_t flags, red, invh[3], S, J, Racc, G, stage, mask[3], wts, total;
 };
 
 __host__ __device__ inline int64_t ext_index(const Grid &g, int64_t i, int64_t j, int64_t k) {
@@ -69,9 +70,25 @@ hipError_t launch_metrics_separable(const Grid &g, const double *coord1d, double
 hipError_t launch_metrics_general(const Grid &g, const double *coords, double *stage,
                                   double *S, double *J, const double period[3], hipStream_t s);
 hipError_t launch_bc(const Grid &g, const Phys &ph, const osbli_params &p, double *U, hipStream_t s);
-// one convective sweep along dir; first != 0 stores R, otherwise accumulates
+// one convective sweep along dir; first != 0 stores R, otherwise accumulates;
+// mask (may be null): routing mask of the direction's interfaces
 hipError_t launch_convective(const Grid &g, const Phys &ph, const Metrics &m, const double *U,
-                             double *R, unsigned *flags, int dir, int first, hipStream_t s);
+                             double *R, unsigned *flags, int dir, int first, const uint8_t *mask,
+                             hipStream_t s);
+// learned sensor
+int64_t iface_count(const Grid &g, int d);
+hipError_t launch_labels(const Grid &g, const Phys &ph, const double *U, int d, float *feat, uint8_t *lab,
+                         hipStream_t s);
+hipError_t launch_sensor(const Grid &g, const Phys &ph, const double *U, int d, const uint16_t *w, float zcut,
+                         uint8_t *mask, hipStream_t s);
+hipError_t launch_count_u8(const uint8_t *a, int64_t n, unsigned long long *out, hipStream_t s);
+size_t mlp_workspace_bytes(int64_t n);
+hipError_t launch_mlp_grad(const float *X, const uint8_t *y, int64_t n, const uint16_t *w, float wneg,
+                           float *grad, float *loss, float *partial, hipStream_t s);
+hipError_t launch_mlp_adam(float *master, uint16_t *w, const float *grad, float *m, float *v, int64_t t,
+                           float lr, float b1, float b2, float eps, hipStream_t s);
+hipError_t launch_mlp_forward(const float *X, int64_t n, const uint16_t *w, float *z, int inference,
+                              hipStream_t s);
 hipError_t launch_viscous_fluxes(const Grid &g, const Phys &ph, const Metrics &m, const double *U,
                                  double *G, hipStream_t s);
 // mode 0: R_out = Racc + viscous;  mode 1: RK update of U, dU with Racc + viscous

@@ -1,0 +1,498 @@
+// Learned shock sensor (not in the paper; the paper names sensor-switched
+// hybrids of central and shock-capturing fluxes as hard to design by hand):
+//   - sensor features of an interface and the TENO "all stencils kept" label
+//     (training data made by the method itself);
+//   - a 10 -> 32 -> 32 -> 1 network (ReLU, ReLU, sigmoid) with bfloat16
+//     weights: FP32 training forward / backward, a deterministic gradient
+//     reduction and Adam on FP32 master weights;
+//   - inference on the matrix cores (bf16 MFMA, FP32 accumulation), 64
+//     interfaces per wave, producing per-interface routing masks.
+#include "charflux.hpp"
+
+namespace osbli {
+namespace {
+using namespace cf;
+
+constexpr int kIn = 10, kH = 32;
+constexpr int oW1 = 0, oB1 = 320, oW2 = 352, oB2 = 1376, oW3 = 1408, oB3 = 1440;
+constexpr int kNP = 1441;
+constexpr int kNPad = 1442;  // partial record: 1441 gradients + loss
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((unsigned)b) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ------------------------------------------------------------ features
+// Sensor features of interface p+1/2 of a line (separable meshes: n = e_DIR,
+// tangents e_{DIR+1}, e_{DIR+2}); stencil points p-2..p+3 start at ext index
+// e0 with stride st.
+template <int ND, int DIR>
+__device__ __forceinline__ void features(const double *__restrict__ U, int64_t e0, int64_t st, int64_t cs,
+                                         const Phys &ph, float (&f)[kIn]) {
+    double rho[6], p[6], vt[2][6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int64_t e = e0 + k * st;
+        const double r = U[e], ri = 1.0 / r;
+        double ke = 0.0;
+#pragma unroll
+        for (int m = 0; m < ND; ++m) ke += U[e + (1 + m) * cs] * U[e + (1 + m) * cs];
+        rho[k] = r;
+        p[k] = ph.gm1 * (U[e + (ND + 1) * cs] - 0.5 * ke * ri);
+#pragma unroll
+        for (int s = 0; s < ND - 1; ++s) vt[s][k] = U[e + (1 + (DIR + 1 + s) % ND) * cs] * ri;
+    }
+    const double rb = 0.5 * (rho[2] + rho[3]), pb = 0.5 * (p[2] + p[3]);
+    const double irb = 1.0 / rb, ipb = 1.0 / pb, iab = 1.0 / sqrt(ph.gamma * pb * irb);
+    double beta[4], sum = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        double a1 = (rho[m] - 2.0 * rho[m + 1] + rho[m + 2]) * irb, a2 = (rho[m] - rho[m + 2]) * irb;
+        double b = (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
+        a1 = (p[m] - 2.0 * p[m + 1] + p[m + 2]) * ipb;
+        a2 = (p[m] - p[m + 2]) * ipb;
+        b += (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
+#pragma unroll
+        for (int s = 0; s < ND - 1; ++s) {
+            a1 = (vt[s][m] - 2.0 * vt[s][m + 1] + vt[s][m + 2]) * iab;
+            a2 = (vt[s][m] - vt[s][m + 2]) * iab;
+            b += (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
+        }
+        beta[m] = b;
+        sum += b;
+    }
+    const double isum = 1.0 / (sum + 1e-30);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) f[m] = (float)(beta[m] * isum);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        f[4 + m] = (float)(fabs(rho[m + 2] - rho[m + 1]) / (rho[m + 2] + rho[m + 1]));
+        f[7 + m] = (float)(fabs(p[m + 2] - p[m + 1]) / (p[m + 2] + p[m + 1]));
+    }
+}
+
+// interface grid of direction d: extent n_d + 1 along d (position p = index - 1)
+struct IfaceGrid {
+    int64_t E[3], total;
+};
+__host__ __device__ inline IfaceGrid iface_grid(const Grid &g, int d) {
+    IfaceGrid I;
+    for (int e = 0; e < 3; ++e) I.E[e] = g.n[e] + (e == d ? 1 : 0);
+    I.total = I.E[0] * I.E[1] * I.E[2];
+    return I;
+}
+
+// features + label of every interface of direction DIR (TENO5 labels)
+template <int ND, int DIR>
+__global__ void __launch_bounds__(256)
+k_labels(const double *__restrict__ U, Grid g, Phys ph, float *__restrict__ feat, uint8_t *__restrict__ lab) {
+    const IfaceGrid I = iface_grid(g, DIR);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= I.total) return;
+    int64_t q[3];
+    q[0] = t % I.E[0];
+    q[1] = (t / I.E[0]) % I.E[1];
+    q[2] = t / (I.E[0] * I.E[1]);
+    q[DIR] -= 1;  // interface position p in [-1, N-1]
+    const int64_t st = g.es[DIR], cs = g.enpts;
+    const int64_t e0 = ext_index(g, q[0], q[1], q[2]) - 2 * st;
+    float f[kIn];
+    features<ND, DIR>(U, e0, st, cs, ph, f);
+#pragma unroll
+    for (int m = 0; m < kIn; ++m) feat[t * kIn + m] = f[m];
+    Loc<ND> P[6];
+    constexpr int T1 = (DIR + 1) % ND, T2 = (DIR + 2) % ND;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        Pt<ND> w;
+#pragma unroll
+        for (int c = 0; c < ND + 2; ++c) w.U[c] = U[e0 + k * st + c * cs];
+        bool bad = false;
+        finish_point<ND>(ph, w, bad);
+        P[k].r = w.U[0];
+        P[k].mn = w.U[1 + DIR];
+        P[k].mt[0] = ND >= 2 ? w.U[1 + T1] : 0.0;
+        P[k].mt[1] = ND >= 3 ? w.U[1 + T2] : 0.0;
+        P[k].E = w.U[ND + 1];
+        P[k].p = w.p;
+        P[k].a = w.a;
+        P[k].ri = w.ri;
+    }
+    bool kept = true;
+    double Fr, Fn, Ft[2], FE;
+    char_flux<ND, OSBLI_TENO5>(P, ph, Fr, Fn, Ft, FE, &kept);
+    lab[t] = kept ? 1 : 0;
+}
+
+// ------------------------------------------------------ FP32 training pass
+constexpr int kMB = 64;  // samples per block (one wave)
+
+struct Fwd {
+    float a1[kH], a2[kH], z;
+};
+
+__device__ __forceinline__ void fwd_fp32(const float (&x)[kIn], const float *W, Fwd &o) {
+#pragma unroll
+    for (int j = 0; j < kH; ++j) {
+        float s = W[oB1 + j];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) s += x[k] * W[oW1 + k * kH + j];
+        o.a1[j] = s;
+    }
+#pragma unroll
+    for (int j = 0; j < kH; ++j) {
+        float s = W[oB2 + j];
+#pragma unroll
+        for (int k = 0; k < kH; ++k) s += fmaxf(o.a1[k], 0.0f) * W[oW2 + k * kH + j];
+        o.a2[j] = s;
+    }
+    float z = W[oB3];
+#pragma unroll
+    for (int j = 0; j < kH; ++j) z += fmaxf(o.a2[j], 0.0f) * W[oW3 + j];
+    o.z = z;
+}
+
+// per-block partial gradients of the mean class-weighted BCE
+__global__ void __launch_bounds__(kMB)
+k_mlp_grad(const float *__restrict__ X, const uint8_t *__restrict__ y, int64_t n, const uint16_t *__restrict__ w,
+           float wneg, float inv_n, float *__restrict__ partial) {
+    __shared__ float W[kNP];
+    __shared__ float sx[kMB][kIn], sh1[kMB][kH], sd1[kMB][kH], sh2[kMB][kH], sd2[kMB][kH], sdz[kMB], sl[kMB];
+    for (int e = threadIdx.x; e < kNP; e += kMB) W[e] = bf2f(w[e]);
+    __syncthreads();
+    const int tid = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * kMB + tid;
+    const bool valid = s < n;
+    float x[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) x[k] = valid ? X[s * kIn + k] : 0.0f;
+    Fwd o;
+    fwd_fp32(x, W, o);
+    const float yv = valid ? (float)y[s] : 0.0f;
+    const float wt = valid ? (yv > 0.5f ? 1.0f : wneg) : 0.0f;
+    const float sig = 1.0f / (1.0f + expf(-o.z));
+    const float dz = wt * (sig - yv) * inv_n;
+    const float sp = fmaxf(o.z, 0.0f) + log1pf(expf(-fabsf(o.z)));
+    sl[tid] = wt * (sp - yv * o.z) * inv_n;
+    sdz[tid] = dz;
+    float d2[kH];
+#pragma unroll
+    for (int j = 0; j < kH; ++j) {
+        d2[j] = o.a2[j] > 0.0f ? dz * W[oW3 + j] : 0.0f;
+        sd2[tid][j] = d2[j];
+        sh2[tid][j] = fmaxf(o.a2[j], 0.0f);
+        sh1[tid][j] = fmaxf(o.a1[j], 0.0f);
+    }
+#pragma unroll
+    for (int k = 0; k < kH; ++k) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < kH; ++j) acc += d2[j] * W[oW2 + k * kH + j];
+        sd1[tid][k] = o.a1[k] > 0.0f ? acc : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) sx[tid][k] = x[k];
+    __syncthreads();
+    float *out = partial + (int64_t)blockIdx.x * kNPad;
+    for (int e = tid; e < kNPad; e += kMB) {
+        float acc = 0.0f;
+        if (e < oB1) {
+            const int k = e / kH, j = e % kH;
+            for (int t = 0; t < kMB; ++t) acc += sx[t][k] * sd1[t][j];
+        } else if (e < oW2) {
+            const int j = e - oB1;
+            for (int t = 0; t < kMB; ++t) acc += sd1[t][j];
+        } else if (e < oB2) {
+            const int k = (e - oW2) / kH, j = (e - oW2) % kH;
+            for (int t = 0; t < kMB; ++t) acc += sh1[t][k] * sd2[t][j];
+        } else if (e < oW3) {
+            const int j = e - oB2;
+            for (int t = 0; t < kMB; ++t) acc += sd2[t][j];
+        } else if (e < oB3) {
+            const int j = e - oW3;
+            for (int t = 0; t < kMB; ++t) acc += sh2[t][j] * sdz[t];
+        } else if (e == oB3) {
+            for (int t = 0; t < kMB; ++t) acc += sdz[t];
+        } else {
+            for (int t = 0; t < kMB; ++t) acc += sl[t];
+        }
+        out[e] = acc;
+    }
+}
+
+// fixed-order sum of the block partials -> gradient (1441) and loss
+__global__ void k_mlp_reduce(const float *__restrict__ partial, int64_t nblk, float *__restrict__ grad,
+                             float *__restrict__ loss) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kNPad) return;
+    float acc = 0.0f;
+    for (int64_t b = 0; b < nblk; ++b) acc += partial[b * kNPad + e];
+    if (e < kNP) grad[e] = acc;
+    else if (loss) *loss = acc;
+}
+
+__global__ void k_mlp_adam(float *__restrict__ master, uint16_t *__restrict__ w, const float *__restrict__ grad,
+                           float *__restrict__ m, float *__restrict__ v, float lr, float b1, float b2, float eps,
+                           float c1, float c2) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kNP) return;
+    const float g = grad[e];
+    const float mm = b1 * m[e] + (1.0f - b1) * g;
+    const float vv = b2 * v[e] + (1.0f - b2) * g * g;
+    m[e] = mm;
+    v[e] = vv;
+    const float th = master[e] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    master[e] = th;
+    w[e] = f2bf(th);
+}
+
+__global__ void k_mlp_fwd_fp32(const float *__restrict__ X, int64_t n, const uint16_t *__restrict__ w,
+                               float *__restrict__ z) {
+    __shared__ float W[kNP];
+    for (int e = threadIdx.x; e < kNP; e += blockDim.x) W[e] = bf2f(w[e]);
+    __syncthreads();
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    float x[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) x[k] = X[s * kIn + k];
+    Fwd o;
+    fwd_fp32(x, W, o);
+    z[s] = o.z;
+}
+
+// ------------------------------------------------------ MFMA inference
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+// per-lane operand fragments of v_mfma_f32_32x32x16_bf16:
+// B (K x N = 16 x 32): lane l holds column l % 32, rows 8 (l / 32) .. + 7
+struct MlpFrag {
+    bf16x8 w1, w2a, w2b;
+    float b1, b2;
+};
+
+__device__ __forceinline__ bf16x8 pack8(const uint16_t (&u)[8]) {
+    bf16x8 v;
+    __builtin_memcpy(&v, u, sizeof v);
+    return v;
+}
+
+__device__ __forceinline__ void load_frag(const uint16_t *__restrict__ w, int lane, MlpFrag &F) {
+    const int j = lane & 31, kh = 8 * (lane >> 5);
+    uint16_t u[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) u[i] = (kh + i < kIn) ? w[oW1 + (kh + i) * kH + j] : (uint16_t)0;
+    F.w1 = pack8(u);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) u[i] = w[oW2 + (kh + i) * kH + j];
+    F.w2a = pack8(u);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) u[i] = w[oW2 + (16 + kh + i) * kH + j];
+    F.w2b = pack8(u);
+    F.b1 = bf2f(w[oB1 + j]);
+    F.b2 = bf2f(w[oB2 + j]);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// logit of the lane's own sample; every lane of the wave must call it.
+// xs: 64 x 16 bf16 scratch, hs: 64 x 32 bf16 scratch (per wave, LDS);
+// w3s: w3[0..31], b3 as floats (LDS).  Inputs and hidden activations are
+// rounded to bf16 (the A operands), accumulation is FP32.
+__device__ __forceinline__ float mlp_mfma(const float (&x)[kIn], const MlpFrag &F, uint16_t *xs, uint16_t *hs,
+                                          const float *w3s, int lane) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xs[lane * 16 + k] = k < kIn ? f2bf(x[k]) : (uint16_t)0;
+    wave_sync();
+    const int r32 = lane & 31, kh = 8 * (lane >> 5), c = lane & 31;
+    f32x16 acc[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        bf16x8 a;
+        __builtin_memcpy(&a, xs + (rb * 32 + r32) * 16 + kh, sizeof a);
+        f32x16 zero = {0};
+        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, F.w1, zero, 0, 0, 0);
+    }
+    // D layout: register r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            hs[row * 32 + c] = f2bf(fmaxf(acc[rb][r] + F.b1, 0.0f));
+        }
+    wave_sync();
+    f32x16 acc2[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        bf16x8 a0, a1;
+        __builtin_memcpy(&a0, hs + (rb * 32 + r32) * 32 + kh, sizeof a0);
+        __builtin_memcpy(&a1, hs + (rb * 32 + r32) * 32 + 16 + kh, sizeof a1);
+        f32x16 zero = {0};
+        acc2[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, F.w2a, zero, 0, 0, 0);
+        acc2[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, F.w2b, acc2[rb], 0, 0, 0);
+    }
+    wave_sync();
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            hs[row * 32 + c] = f2bf(fmaxf(acc2[rb][r] + F.b2, 0.0f));
+        }
+    wave_sync();
+    float z = w3s[32];
+#pragma unroll
+    for (int j = 0; j < kH; ++j) z += bf2f(hs[lane * 32 + j]) * w3s[j];
+    wave_sync();  // scratch reused by the next call
+    return z;
+}
+
+__global__ void __launch_bounds__(256)
+k_mlp_fwd_mfma(const float *__restrict__ X, int64_t n, const uint16_t *__restrict__ w, float *__restrict__ z) {
+    __shared__ uint16_t xs[4][64 * 16], hs[4][64 * 32];
+    __shared__ float w3s[33];
+    if (threadIdx.x < 33) w3s[threadIdx.x] = bf2f(w[oW3 + threadIdx.x]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sc = s < n ? s : n - 1;
+    float x[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) x[k] = X[sc * kIn + k];
+    MlpFrag F;
+    load_frag(w, lane, F);
+    const float zz = mlp_mfma(x, F, xs[wv], hs[wv], w3s, lane);
+    if (s < n) z[s] = zz;
+}
+
+// routing mask of every interface of direction DIR: 1 when the network's
+// logit reaches zcut (P(smooth) >= threshold)
+template <int ND, int DIR>
+__global__ void __launch_bounds__(256)
+k_sensor(const double *__restrict__ U, Grid g, Phys ph, const uint16_t *__restrict__ w, float zcut,
+         uint8_t *__restrict__ mask) {
+    __shared__ uint16_t xs[4][64 * 16], hs[4][64 * 32];
+    __shared__ float w3s[33];
+    if (threadIdx.x < 33) w3s[threadIdx.x] = bf2f(w[oW3 + threadIdx.x]);
+    __syncthreads();
+    const IfaceGrid I = iface_grid(g, DIR);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tc = t < I.total ? t : I.total - 1;
+    int64_t q[3];
+    q[0] = tc % I.E[0];
+    q[1] = (tc / I.E[0]) % I.E[1];
+    q[2] = tc / (I.E[0] * I.E[1]);
+    q[DIR] -= 1;
+    const int64_t st = g.es[DIR], cs = g.enpts;
+    const int64_t e0 = ext_index(g, q[0], q[1], q[2]) - 2 * st;
+    float f[kIn];
+    features<ND, DIR>(U, e0, st, cs, ph, f);
+    MlpFrag F;
+    load_frag(w, lane, F);
+    const float z = mlp_mfma(f, F, xs[wv], hs[wv], w3s, lane);
+    if (t < I.total) mask[t] = z >= zcut ? 1 : 0;
+}
+
+template <int ND>
+hipError_t labels_nd(const Grid &g, const Phys &ph, const double *U, int d, float *feat, uint8_t *lab,
+                     hipStream_t s) {
+    const IfaceGrid I = iface_grid(g, d);
+    const unsigned nb = (unsigned)((I.total + 255) / 256);
+    if (d == 0) hipLaunchKernelGGL((k_labels<ND, 0>), dim3(nb), dim3(256), 0, s, U, g, ph, feat, lab);
+    else if (d == 1) hipLaunchKernelGGL((k_labels<ND, (ND >= 2 ? 1 : 0)>), dim3(nb), dim3(256), 0, s, U, g, ph, feat, lab);
+    else hipLaunchKernelGGL((k_labels<ND, (ND >= 3 ? 2 : 0)>), dim3(nb), dim3(256), 0, s, U, g, ph, feat, lab);
+    return hipGetLastError();
+}
+
+template <int ND>
+hipError_t sensor_nd(const Grid &g, const Phys &ph, const double *U, int d, const uint16_t *w, float zcut,
+                     uint8_t *mask, hipStream_t s) {
+    const IfaceGrid I = iface_grid(g, d);
+    const unsigned nb = (unsigned)((I.total + 255) / 256);
+    if (d == 0) hipLaunchKernelGGL((k_sensor<ND, 0>), dim3(nb), dim3(256), 0, s, U, g, ph, w, zcut, mask);
+    else if (d == 1) hipLaunchKernelGGL((k_sensor<ND, (ND >= 2 ? 1 : 0)>), dim3(nb), dim3(256), 0, s, U, g, ph, w, zcut, mask);
+    else hipLaunchKernelGGL((k_sensor<ND, (ND >= 3 ? 2 : 0)>), dim3(nb), dim3(256), 0, s, U, g, ph, w, zcut, mask);
+    return hipGetLastError();
+}
+
+// number of nonzero bytes (integer atomics: order independent)
+__global__ void k_count_u8(const uint8_t *__restrict__ a, int64_t n, unsigned long long *out) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += a[i] != 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out, c);
+}
+
+}  // namespace
+
+hipError_t launch_count_u8(const uint8_t *a, int64_t n, unsigned long long *out, hipStream_t s) {
+    int64_t nb = (n + 255) / 256;
+    if (nb > 1024) nb = 1024;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_count_u8, dim3((unsigned)nb), dim3(256), 0, s, a, n, out);
+    return hipGetLastError();
+}
+
+int64_t iface_count(const Grid &g, int d) { return iface_grid(g, d).total; }
+
+hipError_t launch_labels(const Grid &g, const Phys &ph, const double *U, int d, float *feat, uint8_t *lab,
+                         hipStream_t s) {
+    switch (g.nd) {
+        case 1: return labels_nd<1>(g, ph, U, d, feat, lab, s);
+        case 2: return labels_nd<2>(g, ph, U, d, feat, lab, s);
+        default: return labels_nd<3>(g, ph, U, d, feat, lab, s);
+    }
+}
+
+hipError_t launch_sensor(const Grid &g, const Phys &ph, const double *U, int d, const uint16_t *w, float zcut,
+                         uint8_t *mask, hipStream_t s) {
+    switch (g.nd) {
+        case 1: return sensor_nd<1>(g, ph, U, d, w, zcut, mask, s);
+        case 2: return sensor_nd<2>(g, ph, U, d, w, zcut, mask, s);
+        default: return sensor_nd<3>(g, ph, U, d, w, zcut, mask, s);
+    }
+}
+
+size_t mlp_workspace_bytes(int64_t n) {
+    const int64_t nblk = (n + kMB - 1) / kMB;
+    return (size_t)nblk * kNPad * sizeof(float);
+}
+
+hipError_t launch_mlp_grad(const float *X, const uint8_t *y, int64_t n, const uint16_t *w, float wneg, float *grad,
+                           float *loss, float *partial, hipStream_t s) {
+    const int64_t nblk = (n + kMB - 1) / kMB;
+    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)nblk), dim3(kMB), 0, s, X, y, n, w, wneg, 1.0f / (float)n,
+                       partial);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNPad + 255) / 256), dim3(256), 0, s, partial, nblk, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float *master, uint16_t *w, const float *grad, float *m, float *v, int64_t t, float lr,
+                           float b1, float b2, float eps, hipStream_t s) {
+    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kNP + 255) / 256), dim3(256), 0, s, master, w, grad, m, v, lr, b1, b2,
+                       eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float *X, int64_t n, const uint16_t *w, float *z, int inference,
+                              hipStream_t s) {
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (inference) hipLaunchKernelGGL(k_mlp_fwd_mfma, dim3(nb), dim3(256), 0, s, X, n, w, z);
+    else hipLaunchKernelGGL(k_mlp_fwd_fp32, dim3(nb), dim3(256), 0, s, X, n, w, z);
+    return hipGetLastError();
+}
+
+}  // namespace osbli

@@ -1,0 +1,215 @@
+"""Learned shock sensor: training data, training and weights.
+
+All arithmetic runs in libosbli's kernels: label generation with the plain
+TENO5 solver and `osbli_collect_labels`, training with `osbli_mlp_grad` /
+`osbli_mlp_adam` (FP32 forward/backward on bfloat16 weights, Adam on FP32
+master weights).  PyTorch holds the device buffers.
+
+    python -m paper_2007_14933_amd.sensor --out weights.npz   # on a GPU
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import binding as B
+from . import inputs as I
+from .solver import Solver
+
+NPARAM = 1441
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "sensor_weights.npz")
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def init_weights(seed=0):
+    """He-uniform initial weights, zero biases (FP32 master, flat order)."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.uniform(-1, 1, (10, 32)) * np.sqrt(6.0 / 10)
+    w2 = rng.uniform(-1, 1, (32, 32)) * np.sqrt(6.0 / 32)
+    w3 = rng.uniform(-1, 1, 32) * np.sqrt(6.0 / 32)
+    return np.concatenate([w1.ravel(), np.zeros(32), w2.ravel(), np.zeros(32), w3, np.zeros(1)]).astype(np.float32)
+
+
+def bf16_bits(x):
+    f = np.asarray(x, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    return ((b + 0x7FFF + ((b >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+# ------------------------------------------------------------------ labels
+def collect(solver):
+    """Features (n, 10) float32 and labels (n,) uint8 of every interface of
+    the solver's current state (device tensors)."""
+    lib = solver.lib
+    cnt = C.c_int64(0)
+    B.check(lib.osbli_interface_count(solver.ctx, C.byref(cnt)), solver.ctx)
+    n = cnt.value
+    feat = torch.empty((n, 10), dtype=torch.float32, device=solver.device)
+    lab = torch.empty(n, dtype=torch.uint8, device=solver.device)
+    B.check(lib.osbli_collect_labels(solver.ctx, _p(solver.U), _p(feat), _p(lab), n, C.byref(cnt), solver._s()),
+            solver.ctx)
+    return feat, lab
+
+
+def generate(nprob=24, N=256, seed=100, snapshots=(0.05, 0.12, 0.25), per_class=None, rng_seed=7, log=print):
+    """Run seeded random four-quadrant Riemann problems with the plain TENO5
+    solver and gather (features, label) at several times.  Labels are
+    stratified: all non-smooth interfaces are kept and as many smooth ones
+    (or `per_class` of each)."""
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(rng_seed)
+    Xs, ys = [], []
+    rng = np.random.default_rng(seed)
+    t0 = time.time()
+    for k in range(nprob):
+        prob = I.riemann2d(N, rng, t_end=max(snapshots))
+        s = Solver(prob)
+        s.apply_bc()
+        for ts in snapshots:
+            s.run(10 ** 6, cfl=0.5, t_end=ts, start_bc=False)
+            f, l = collect(s)
+            pos = torch.nonzero(l == 1).squeeze(1)
+            neg = torch.nonzero(l == 0).squeeze(1)
+            m = min(len(pos), max(len(neg), 1)) if per_class is None else min(per_class, len(pos))
+            mn = len(neg) if per_class is None else min(per_class, len(neg))
+            keep_p = pos[torch.randperm(len(pos), generator=gen, device=pos.device)[:m]]
+            keep_n = neg[torch.randperm(len(neg), generator=gen, device=neg.device)[:mn]]
+            idx = torch.cat([keep_p, keep_n])
+            Xs.append(f[idx])
+            ys.append(l[idx])
+        s.check()
+        del s
+        if log and (k + 1) % 8 == 0:
+            log("[sensor] labels from %d / %d problems, %d samples, %.1f s" % (
+                k + 1, nprob, sum(len(y) for y in ys), time.time() - t0))
+    X = torch.cat(Xs)
+    y = torch.cat(ys)
+    perm = torch.randperm(len(y), generator=gen, device=y.device)
+    return X[perm].contiguous(), y[perm].contiguous()
+
+
+# ---------------------------------------------------------------- training
+class Trainer:
+    def __init__(self, seed=0, device="cuda:0"):
+        self.lib = B.load()
+        self.device = torch.device(device)
+        self.master = torch.from_numpy(init_weights(seed)).to(self.device)
+        self.w = torch.from_numpy(bf16_bits(init_weights(seed)).view(np.int16)).to(self.device)
+        self.m = torch.zeros(NPARAM, dtype=torch.float32, device=self.device)
+        self.v = torch.zeros(NPARAM, dtype=torch.float32, device=self.device)
+        self.grad = torch.zeros(NPARAM, dtype=torch.float32, device=self.device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.t = 0
+        self.stream = torch.cuda.current_stream(self.device)
+
+    def _s(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def grad_loss(self, X, y, w_neg=10.0):
+        n = len(y)
+        nb = self.lib.osbli_mlp_workspace_bytes(n)
+        ws = torch.empty(nb // 4 + 64, dtype=torch.float32, device=self.device)
+        rc = self.lib.osbli_mlp_grad(_p(X), _p(y), n, _p(self.w), float(w_neg), _p(self.grad), _p(self.loss),
+                                     _p(ws), nb, self._s())
+        B.check(rc)
+        return self.grad, self.loss
+
+    def step(self, X, y, lr=2e-3, w_neg=10.0):
+        self.grad_loss(X, y, w_neg)
+        self.t += 1
+        B.check(self.lib.osbli_mlp_adam(_p(self.master), _p(self.w), _p(self.grad), _p(self.m), _p(self.v), self.t,
+                                        float(lr), 0.9, 0.999, 1e-8, self._s()))
+
+    def forward(self, X, inference=False):
+        z = torch.empty(len(X), dtype=torch.float32, device=self.device)
+        B.check(self.lib.osbli_mlp_forward(_p(X), len(X), _p(self.w), _p(z), int(bool(inference)), self._s()))
+        return z
+
+    def fit(self, X, y, epochs=3, batch=8192, lr=2e-3, w_neg=10.0, seed=0, log=print):
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        n = len(y)
+        for ep in range(epochs):
+            perm = torch.randperm(n, generator=gen, device=y.device)
+            tot = 0.0
+            nb = 0
+            for b0 in range(0, n - batch + 1, batch):
+                idx = perm[b0:b0 + batch]
+                lr_e = lr * (0.3 ** ep)
+                self.step(X[idx].contiguous(), y[idx].contiguous(), lr=lr_e, w_neg=w_neg)
+                if nb % 64 == 0:
+                    tot += float(self.loss.item())
+                nb += 1
+            if log:
+                log("[sensor] epoch %d: %d batches, sampled mean loss %.4f" % (ep, nb, tot / max(1, (nb + 63) // 64)))
+
+    def weights_bits(self):
+        return self.w.cpu().numpy().view(np.uint16).copy()
+
+
+def pick_threshold(z, y, max_false_smooth=1e-3):
+    """Smallest logit cut with at most `max_false_smooth` of the non-smooth
+    (label 0) samples above it; returns (probability threshold, recall of
+    smooth samples)."""
+    z = z.float().cpu().numpy()
+    y = y.cpu().numpy()
+    zn = np.sort(z[y == 0])
+    if len(zn) == 0:
+        return 0.5, 1.0
+    k = int(np.floor((1.0 - max_false_smooth) * len(zn)))
+    cut = zn[min(k, len(zn) - 1)]
+    thr = 1.0 / (1.0 + np.exp(-float(cut)))
+    thr = min(max(thr, 1e-6), 1 - 1e-6)
+    recall = float((z[y == 1] >= cut).mean()) if (y == 1).any() else 0.0
+    return thr, recall
+
+
+def save(path, bits, threshold, meta):
+    np.savez(path, weights_bf16=bits, threshold=np.float64(threshold), **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def load(path=DEFAULT_WEIGHTS):
+    d = np.load(path, allow_pickle=False)
+    return d["weights_bf16"].astype(np.uint16), float(d["threshold"])
+
+
+def train_default(nprob=24, N=256, epochs=3, log=print, seed=100):
+    """The shipped network: labels from `nprob` seeded Riemann runs (seeds
+    disjoint from the benchmark ensemble's), held-out problems for the
+    threshold."""
+    X, y = generate(nprob=nprob, N=N, seed=seed, log=log)
+    Xv, yv = generate(nprob=max(2, nprob // 6), N=N, seed=seed + 1000, log=None)
+    tr = Trainer(seed=0)
+    tr.fit(X, y, epochs=epochs, log=log)
+    zv = tr.forward(Xv, inference=True)
+    thr, rec = pick_threshold(zv, yv)
+    acc = float(((zv >= 0) == (yv == 1)).float().mean().item())
+    meta = {"samples": len(y), "val_samples": len(yv), "val_smooth_recall": rec, "val_acc_at_half": acc,
+            "nprob": nprob, "N": N, "seed": seed}
+    return tr, thr, meta
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--nprob", type=int, default=24)
+    ap.add_argument("--N", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=3)
+    a = ap.parse_args()
+    t0 = time.time()
+    tr, thr, meta = train_default(a.nprob, a.N, a.epochs)
+    save(a.out, tr.weights_bits(), thr, meta)
+    print("[sensor] saved %s threshold %.6f meta %s (%.1f s)" % (a.out, thr, meta, time.time() - t0), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -113,6 +113,24 @@ class Solver:
     def check(self):
         B.check(self.lib.osbli_check(self.ctx), self.ctx)
 
+    # ---- learned-sensor routing (params.sensor = 1) ----
+    def set_sensor(self, bits, threshold, dilate=1, every_substage=0):
+        """bits: 1441 bfloat16 weight patterns (uint16, host)."""
+        w = np.ascontiguousarray(np.asarray(bits, dtype=np.uint16))
+        if w.size != 1441:
+            raise ValueError("expected 1441 weights")
+        self._sensor_bits = w
+        B.check(self.lib.osbli_sensor_set_weights(self.ctx, w.ctypes.data_as(C.c_void_p), 1441, float(threshold),
+                                                  int(dilate), int(every_substage), self._s()), self.ctx)
+
+    def sensor_update(self):
+        B.check(self.lib.osbli_sensor_update(self.ctx, _ptr(self.U), self._s()), self.ctx)
+
+    def sensor_stats(self):
+        sm, tot = C.c_int64(0), C.c_int64(0)
+        B.check(self.lib.osbli_sensor_stats(self.ctx, C.byref(sm), C.byref(tot)), self.ctx)
+        return sm.value, tot.value
+
     # ---- time loop (section 2.7 ordering: residual, update, BCs) ----
     def step(self, dt):
         for s in range(3):

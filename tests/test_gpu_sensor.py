@@ -1,0 +1,219 @@
+"""The learned-sensor form on the GPU: features and TENO labels against the
+oracle, the network's FP32 forward / backward and Adam against the FP64 MLP
+oracle, the MFMA inference path, the routed flux in its two limits (all
+cheap = the oracle's cheap flux everywhere; all full = the plain residual),
+and a trained network's error and gain against the plain form."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from oracle import oracle as O
+from paper_2007_14933_amd import inputs as I
+from parity_util import flux_scale, say
+
+pytestmark = pytest.mark.gpu
+
+
+def iface_stencils(prob, U, d):
+    """(n, 6, nc) stencils of direction d in the library's label order
+    (x fastest over the interface grid, extent n_d + 1 along d)."""
+    nd = prob.ndim
+    E = [prob.n[e] + (1 if e == d else 0) if e < nd else 1 for e in range(3)]
+    kk, jj, ii = np.meshgrid(np.arange(E[2]), np.arange(E[1]), np.arange(E[0]), indexing="ij")
+    pos = [ii.ravel(), jj.ravel(), kk.ravel()]
+    pos[d] = pos[d] - 1
+    out = []
+    for k in range(6):
+        q = [pos[e].copy() for e in range(3)]
+        q[d] = q[d] - 2 + k
+        ix = [q[e] + (3 if e < nd else 0) for e in range(3)]
+        out.append(U[:, ix[2], ix[1], ix[0]].T)
+    return np.stack(out, axis=1)
+
+
+def state_after(prob, nsteps):
+    from parity_util import oracle_run
+    U, _ = oracle_run(prob, nsteps)
+    return O.apply_bc(prob, U)
+
+
+@pytest.mark.parametrize("case", ["riemann2d_48", "smooth3d_10"])
+def test_features_and_labels_match_oracle(case):
+    import torch
+    from paper_2007_14933_amd import sensor as SN
+    from paper_2007_14933_amd.solver import Solver
+    if case == "riemann2d_48":
+        prob = I.riemann2d(48, 3)
+        U = state_after(prob, 30)
+    else:
+        prob = I.smooth_random(3, (10, 9, 8), seed=2, amp=0.3).with_(bc=((I.PERIODIC,) * 2, (I.EXTRAPOLATE,) * 2,
+                                                                     (I.PERIODIC,) * 2))
+        U = O.apply_bc(prob, prob.U0.copy())
+    say("[gpu sensor] labels", case)
+    s = Solver(prob.with_(U0=U))
+    f, l = SN.collect(s)
+    f, l = f.cpu().numpy(), l.cpu().numpy()
+    off = 0
+    nbad = 0
+    for d in range(prob.ndim):
+        st = iface_stencils(prob, U, d)
+        for t in range(len(st)):
+            S = np.eye(3)[d][: prob.ndim]
+            fo, lo = O.features(prob, d, st[t], S)
+            assert np.abs(f[off + t] - fo).max() <= 1e-6 * (1 + np.abs(fo).max()), (d, t, f[off + t], fo)
+            nbad += int(l[off + t] != lo)
+        off += len(st)
+    say("   interfaces %d, label disagreements %d, smooth fraction %.3f" % (off, nbad, l.mean()))
+    assert off == len(l) and nbad == 0
+    del torch
+
+
+def _mlp_data(n=3000, seed=5):
+    rng = np.random.default_rng(seed)
+    theta = mlp.bf16_round(mlp.init(seed) + 0.05 * rng.normal(size=mlp.NPARAM))
+    X = np.concatenate([rng.dirichlet(np.ones(4), n), rng.uniform(0, 0.5, (n, 6))], axis=1).astype(np.float32)
+    y = (rng.uniform(size=n) < 0.6).astype(np.uint8)
+    return theta, X, y
+
+
+def test_mlp_forward_backward_adam_match_oracle():
+    import torch
+    from paper_2007_14933_amd import sensor as SN
+    say("[gpu sensor] mlp fwd/bwd/adam")
+    theta, X, y = _mlp_data()
+    tr = SN.Trainer()
+    tr.w.copy_(torch.from_numpy(mlp.bf16_bits(theta).view(np.int16)).cuda())
+    tr.master.copy_(torch.from_numpy(theta.astype(np.float32)).cuda())
+    Xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
+    z = tr.forward(Xd).cpu().numpy()
+    zo, _ = mlp.forward(theta, X.astype(np.float64))
+    assert np.abs(z - zo).max() <= 1e-5 * (1 + np.abs(zo).max())
+    g, L = tr.grad_loss(Xd, yd)
+    g = g.cpu().numpy()
+    go = mlp.grad(theta, X.astype(np.float64), y)
+    Lo = mlp.loss(theta, X.astype(np.float64), y)
+    say("   max|dz| %.2e  max|dg|/max|g| %.2e  dloss %.2e" % (np.abs(z - zo).max(), np.abs(g - go).max() / np.abs(go).max(),
+                                                           abs(float(L.item()) - Lo)))
+    assert np.abs(g - go).max() <= 1e-5 * np.abs(go).max()
+    assert abs(float(L.item()) - Lo) <= 1e-5 * abs(Lo)
+    # one Adam step from zero moments
+    tr.t = 0
+    tr.step(Xd, yd, lr=1e-3)
+    th1, _, _ = mlp.adam(theta, np.zeros(mlp.NPARAM), np.zeros(mlp.NPARAM), go, 1, lr=1e-3)
+    m1 = tr.master.cpu().numpy()
+    assert np.abs(m1 - th1).max() <= 2e-6
+    assert np.array_equal(tr.w.cpu().numpy().view(np.uint16), mlp.bf16_bits(m1))
+
+
+def test_mlp_mfma_inference_matches_oracle():
+    import torch
+    from paper_2007_14933_amd import sensor as SN
+    say("[gpu sensor] mfma inference")
+    theta, X, y = _mlp_data(n=5000, seed=9)
+    tr = SN.Trainer()
+    tr.w.copy_(torch.from_numpy(mlp.bf16_bits(theta).view(np.int16)).cuda())
+    z = tr.forward(torch.from_numpy(X).cuda(), inference=True).cpu().numpy()
+    zo, _ = mlp.forward(theta, X.astype(np.float64), round_activations=True)
+    err = np.abs(z - zo)
+    say("   max|dz| %.3e  median %.3e  sign agreement %.5f" % (err.max(), np.median(err), np.mean((z >= 0) == (zo >= 0))))
+    assert np.median(err) <= 1e-3 * (1 + np.median(np.abs(zo)))
+    assert err.max() <= 5e-2 * (1 + np.abs(zo).max())
+    assert np.mean((z >= 0) == (zo >= 0)) >= 0.995
+
+
+def const_net(b3):
+    theta = np.zeros(mlp.NPARAM)
+    theta[-1] = b3
+    return mlp.bf16_bits(theta)
+
+
+def oracle_cheap_residual(prob, U):
+    S, J = O.metrics(prob)
+    nd = prob.ndim
+    R = np.zeros(O.int_shape(prob))
+    Ji = O.interior(prob, J[None])[0]
+    for d in range(nd):
+        st = iface_stencils(prob, U, d)
+        F = np.stack([O.cheap_flux(prob, d, st[t], np.eye(3)[d][:nd]) for t in range(len(st))])
+        E = [prob.n[e] + (1 if e == d else 0) if e < nd else 1 for e in range(3)]
+        F = F.reshape(E[2], E[1], E[0], nd + 2)
+        ax = 2 - d
+        hi = [slice(None)] * 3
+        lo = [slice(None)] * 3
+        hi[ax] = slice(1, None)
+        lo[ax] = slice(0, -1)
+        dF = np.moveaxis(F[tuple(hi)] - F[tuple(lo)], -1, 0)
+        # separable uniform meshes: J |S_d| = 1 / h_d
+        h = float(prob.coords1d[d][1] - prob.coords1d[d][0])
+        R -= dF / h
+    return R, S, J
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_routed_limits(mixed):
+    """All interfaces routed cheap: the oracle's cheap flux everywhere; all
+    routed full: the plain residual."""
+    from paper_2007_14933_amd.solver import Solver
+    prob = I.riemann2d(40, 11)
+    U = state_after(prob, 20)
+    p2 = prob.with_(U0=U)
+    say("[gpu sensor] routed limits, mixed =", mixed)
+    s = Solver(p2, sensor=1, form=mixed)
+    s.set_sensor(const_net(30.0), 0.5)
+    Rg = s.residual().cpu().numpy()
+    sm, tot = s.sensor_stats()
+    assert sm == tot
+    Rc, S, J = oracle_cheap_residual(p2, U)
+    sc = flux_scale(p2, U, J, S)
+    err = np.abs(Rg - Rc).max(axis=(1, 2, 3)) / sc
+    say("   all-cheap residual |diff| / flux scale:", err)
+    assert err.max() <= (1e-13 if not mixed else 2e-6)
+    s2 = Solver(p2, sensor=1, form=mixed)
+    s2.set_sensor(const_net(-30.0), 0.5)
+    Rf = s2.residual().cpu().numpy()
+    assert s2.sensor_stats()[0] == 0
+    Rp = Solver(p2, form=mixed).residual().cpu().numpy()
+    assert np.abs(Rf - Rp).max() <= 1e-13 * np.abs(Rp).max()
+
+
+def test_trained_sensor_error_and_gain():
+    """Train the network on method-made labels (small run), then run the
+    shock-vortex field routed vs plain: density L1 error <= 1e-4 relative,
+    most interfaces routed cheap, and the routed sweeps are faster."""
+    import torch
+    from paper_2007_14933_amd import sensor as SN
+    from paper_2007_14933_amd.solver import Solver
+    say("[gpu sensor] train small network")
+    torch.manual_seed(0)
+    X, y = SN.generate(nprob=6, N=128, seed=300, log=say)
+    Xv, yv = SN.generate(nprob=2, N=128, seed=1300, log=None)
+    tr = SN.Trainer(seed=0)
+    tr.fit(X, y, epochs=3, batch=4096, log=say)
+    zv = tr.forward(Xv, inference=True)
+    thr, rec = SN.pick_threshold(zv, yv)
+    acc = float(((zv >= 0) == (yv == 1)).float().mean().item())
+    say("   samples %d, held-out accuracy %.4f, threshold %.4f, smooth recall %.3f" % (len(y), acc, thr, rec))
+    assert acc > 0.9
+    prob = I.shock_vortex(256, 128, seed=42)
+    res = {}
+    for name, kw in (("plain", {}), ("routed", {"sensor": 1})):
+        s = Solver(prob, **kw)
+        if kw:
+            s.set_sensor(tr.weights_bits(), thr)
+        s.apply_bc()
+        dt = s.compute_dt(0.5)
+        s.profile(True)
+        for _ in range(60):
+            s.step(dt)
+        s.check()
+        prof = s.profile_read()
+        res[name] = (s.interior(), sum(prof["sweep_%s" % a][1] for a in "xy"), s.sensor_stats() if kw else None,
+                     prof["sensor"][1])
+    a, b = res["routed"][0], res["plain"][0]
+    l1 = np.abs(a[0] - b[0]).mean() / np.abs(b[0]).mean()
+    sm, tot = res["routed"][2]
+    say("   rel L1(rho) routed vs plain %.3e; smooth fraction %.3f; sweep ms plain %.2f routed %.2f (+ sensor %.2f)"
+        % (l1, sm / tot, res["plain"][1], res["routed"][1], res["routed"][3]))
+    assert l1 <= 1e-4
+    assert sm / tot > 0.5
+    assert res["routed"][1] < res["plain"][1]
