@@ -167,8 +167,9 @@ void osbli_destroy(osbli_ctx *ctx);
  *
  * Features of interface i+1/2 (float32, ten per interface): Jiang-Shu
  * three-point indicators of rho/rho_bar + p/p_bar + (u.t)/a_bar on the four
- * substencils of i-2..i+3, normalised by their sum; |jump|/sum of rho and
- * of p over (i-1,i), (i,i+1), (i+1,i+2).  Label: 1 iff every TENO5 stencil
+ * substencils of i-2..i+3, normalised by their sum (+1e-20); jumps
+ * J = |q_{k+1} - q_k| / (q_{k+1} + q_k) of rho and of p over (i-1,i),
+ * (i,i+1), (i+1,i+2), as log10(1 + 1e6 J) / 6.  Label: 1 iff every TENO5 stencil
  * of every characteristic field and both splits is kept.
  * Weights: 1441 bfloat16 values in the order W1[10][32] (input-major), b1[32],
  * W2[32][32] (input-major), b2[32], w3[32], b3.

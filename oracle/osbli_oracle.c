@@ -1100,9 +1100,11 @@ void orc_cheap_flux(const orc_params *P, int d, const double *Uk, const double *
  *   f0..f3: Jiang-Shu three-point indicators B(a,b,c) = 13/12 (a-2b+c)^2 +
  *     1/4 (a-c)^2 of rho/rho_bar + p/p_bar + (u.t_s)/a_bar summed over the
  *     tangents, on the substencils {i-2..i}, {i-1..i+1}, {i..i+2},
- *     {i+1..i+3}, divided by their sum (+1e-30);
- *   f4..f6: |rho_{k+1} - rho_k| / (rho_{k+1} + rho_k) over (i-1,i), (i,i+1),
- *     (i+1,i+2);  f7..f9: the same for p.
+ *     {i+1..i+3}, divided by their sum (+1e-20, so variations at rounding
+ *     level read as a uniform state);
+ *   f4..f6: jumps J = |rho_{k+1} - rho_k| / (rho_{k+1} + rho_k) over (i-1,i),
+ *     (i,i+1), (i+1,i+2), log-normalised as log10(1 + 1e6 J)/6;  f7..f9: the
+ *     same for p.
  * rho_bar, p_bar: means of nodes i, i+1; a_bar = sqrt(gamma p_bar / rho_bar).
  * Label: 1 iff every TENO stencil of every field and both splits is kept. */
 void orc_features(const orc_params *P, int d, const double *Uk, const double *S, double *feat, int *label)
@@ -1142,10 +1144,12 @@ void orc_features(const orc_params *P, int d, const double *Uk, const double *S,
         beta[m] = b;
         sum += b;
     }
-    for (int m = 0; m < 4; m++) feat[m] = beta[m] / (sum + 1e-30);
+    for (int m = 0; m < 4; m++) feat[m] = beta[m] / (sum + 1e-20);
     for (int m = 0; m < 3; m++) {
-        feat[4 + m] = fabs(w[m + 2].rho - w[m + 1].rho) / (w[m + 2].rho + w[m + 1].rho);
-        feat[7 + m] = fabs(w[m + 2].p - w[m + 1].p) / (w[m + 2].p + w[m + 1].p);
+        double jr = fabs(w[m + 2].rho - w[m + 1].rho) / (w[m + 2].rho + w[m + 1].rho);
+        double jp = fabs(w[m + 2].p - w[m + 1].p) / (w[m + 2].p + w[m + 1].p);
+        feat[4 + m] = log10(1.0 + 1e6 * jr) / 6.0;
+        feat[7 + m] = log10(1.0 + 1e6 * jp) / 6.0;
     }
     if (label) {
         int dl[NCMAX * 2 * 3];

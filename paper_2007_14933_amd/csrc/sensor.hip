@@ -64,13 +64,16 @@ __device__ __forceinline__ void features(const double *__restrict__ U, int64_t e
         beta[m] = b;
         sum += b;
     }
-    const double isum = 1.0 / (sum + 1e-30);
+    const double isum = 1.0 / (sum + 1e-20);
 #pragma unroll
     for (int m = 0; m < 4; ++m) f[m] = (float)(beta[m] * isum);
+    // jumps |q_{k+1} - q_k| / (q_{k+1} + q_k), log-normalised: log10(1 + 1e6 J) / 6
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        f[4 + m] = (float)(fabs(rho[m + 2] - rho[m + 1]) / (rho[m + 2] + rho[m + 1]));
-        f[7 + m] = (float)(fabs(p[m + 2] - p[m + 1]) / (p[m + 2] + p[m + 1]));
+        const double jr = fabs(rho[m + 2] - rho[m + 1]) / (rho[m + 2] + rho[m + 1]);
+        const double jp = fabs(p[m + 2] - p[m + 1]) / (p[m + 2] + p[m + 1]);
+        f[4 + m] = log10f(1.0f + 1e6f * (float)jr) * (1.0f / 6.0f);
+        f[7 + m] = log10f(1.0f + 1e6f * (float)jp) * (1.0f / 6.0f);
     }
 }
 
@@ -198,28 +201,28 @@ k_mlp_grad(const float *__restrict__ X, const uint8_t *__restrict__ y, int64_t n
     __syncthreads();
     float *out = partial + (int64_t)blockIdx.x * kNPad;
     for (int e = tid; e < kNPad; e += kMB) {
-        float acc = 0.0f;
+        double acc = 0.0;  // FP64 sums: FP32 sequential sums of same-sign terms drift
         if (e < oB1) {
             const int k = e / kH, j = e % kH;
-            for (int t = 0; t < kMB; ++t) acc += sx[t][k] * sd1[t][j];
+            for (int t = 0; t < kMB; ++t) acc += (double)sx[t][k] * sd1[t][j];
         } else if (e < oW2) {
             const int j = e - oB1;
             for (int t = 0; t < kMB; ++t) acc += sd1[t][j];
         } else if (e < oB2) {
             const int k = (e - oW2) / kH, j = (e - oW2) % kH;
-            for (int t = 0; t < kMB; ++t) acc += sh1[t][k] * sd2[t][j];
+            for (int t = 0; t < kMB; ++t) acc += (double)(sh1[t][k] * sd2[t][j]);
         } else if (e < oW3) {
             const int j = e - oB2;
             for (int t = 0; t < kMB; ++t) acc += sd2[t][j];
         } else if (e < oB3) {
             const int j = e - oW3;
-            for (int t = 0; t < kMB; ++t) acc += sh2[t][j] * sdz[t];
+            for (int t = 0; t < kMB; ++t) acc += (double)(sh2[t][j] * sdz[t]);
         } else if (e == oB3) {
             for (int t = 0; t < kMB; ++t) acc += sdz[t];
         } else {
             for (int t = 0; t < kMB; ++t) acc += sl[t];
         }
-        out[e] = acc;
+        out[e] = (float)acc;
     }
 }
 
@@ -228,10 +231,10 @@ __global__ void k_mlp_reduce(const float *__restrict__ partial, int64_t nblk, fl
                              float *__restrict__ loss) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= kNPad) return;
-    float acc = 0.0f;
+    double acc = 0.0;
     for (int64_t b = 0; b < nblk; ++b) acc += partial[b * kNPad + e];
-    if (e < kNP) grad[e] = acc;
-    else if (loss) *loss = acc;
+    if (e < kNP) grad[e] = (float)acc;
+    else if (loss) *loss = (float)acc;
 }
 
 __global__ void k_mlp_adam(float *__restrict__ master, uint16_t *__restrict__ w, const float *__restrict__ grad,

@@ -134,7 +134,7 @@ class Trainer:
         B.check(self.lib.osbli_mlp_forward(_p(X), len(X), _p(self.w), _p(z), int(bool(inference)), self._s()))
         return z
 
-    def fit(self, X, y, epochs=3, batch=8192, lr=2e-3, w_neg=10.0, seed=0, log=print):
+    def fit(self, X, y, epochs=6, batch=2048, lr=3e-3, w_neg=10.0, seed=0, log=print):
         gen = torch.Generator(device="cuda")
         gen.manual_seed(seed)
         n = len(y)
@@ -144,7 +144,7 @@ class Trainer:
             nb = 0
             for b0 in range(0, n - batch + 1, batch):
                 idx = perm[b0:b0 + batch]
-                lr_e = lr * (0.3 ** ep)
+                lr_e = lr * (0.5 ** ep)
                 self.step(X[idx].contiguous(), y[idx].contiguous(), lr=lr_e, w_neg=w_neg)
                 if nb % 64 == 0:
                     tot += float(self.loss.item())
@@ -182,7 +182,7 @@ def load(path=DEFAULT_WEIGHTS):
     return d["weights_bf16"].astype(np.uint16), float(d["threshold"])
 
 
-def train_default(nprob=24, N=256, epochs=3, log=print, seed=100):
+def train_default(nprob=24, N=256, epochs=6, log=print, seed=100):
     """The shipped network: labels from `nprob` seeded Riemann runs (seeds
     disjoint from the benchmark ensemble's), held-out problems for the
     threshold."""
@@ -203,7 +203,7 @@ def main():
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--nprob", type=int, default=24)
     ap.add_argument("--N", type=int, default=256)
-    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--epochs", type=int, default=6)
     a = ap.parse_args()
     t0 = time.time()
     tr, thr, meta = train_default(a.nprob, a.N, a.epochs)

@@ -60,7 +60,8 @@ def test_features_and_labels_match_oracle(case):
         for t in range(len(st)):
             S = np.eye(3)[d][: prob.ndim]
             fo, lo = O.features(prob, d, st[t], S)
-            assert np.abs(f[off + t] - fo).max() <= 1e-6 * (1 + np.abs(fo).max()), (d, t, f[off + t], fo)
+            # float32 features: smoothness ratios to 1e-6, log-jumps to float32 rounding
+            assert np.abs(f[off + t] - fo).max() <= 2e-6, (d, t, f[off + t], fo)
             nbad += int(l[off + t] != lo)
         off += len(st)
     say("   interfaces %d, label disagreements %d, smooth fraction %.3f" % (off, nbad, l.mean()))
@@ -95,13 +96,13 @@ def test_mlp_forward_backward_adam_match_oracle():
     say("   max|dz| %.2e  max|dg|/max|g| %.2e  dloss %.2e" % (np.abs(z - zo).max(), np.abs(g - go).max() / np.abs(go).max(),
                                                            abs(float(L.item()) - Lo)))
     assert np.abs(g - go).max() <= 1e-5 * np.abs(go).max()
-    assert abs(float(L.item()) - Lo) <= 1e-5 * abs(Lo)
+    assert abs(float(L.item()) - Lo) <= 1e-6 * abs(Lo)
     # one Adam step from zero moments
     tr.t = 0
     tr.step(Xd, yd, lr=1e-3)
     th1, _, _ = mlp.adam(theta, np.zeros(mlp.NPARAM), np.zeros(mlp.NPARAM), go, 1, lr=1e-3)
     m1 = tr.master.cpu().numpy()
-    assert np.abs(m1 - th1).max() <= 2e-6
+    assert np.abs(m1 - th1).max() <= 2e-6 * max(1.0, np.abs(th1).max())
     assert np.array_equal(tr.w.cpu().numpy().view(np.uint16), mlp.bf16_bits(m1))
 
 
@@ -188,12 +189,12 @@ def test_trained_sensor_error_and_gain():
     X, y = SN.generate(nprob=6, N=128, seed=300, log=say)
     Xv, yv = SN.generate(nprob=2, N=128, seed=1300, log=None)
     tr = SN.Trainer(seed=0)
-    tr.fit(X, y, epochs=3, batch=4096, log=say)
+    tr.fit(X, y, epochs=6, batch=2048, log=say)
     zv = tr.forward(Xv, inference=True)
     thr, rec = SN.pick_threshold(zv, yv)
     acc = float(((zv >= 0) == (yv == 1)).float().mean().item())
     say("   samples %d, held-out accuracy %.4f, threshold %.4f, smooth recall %.3f" % (len(y), acc, thr, rec))
-    assert acc > 0.9
+    assert acc > 0.85 and rec > 0.4
     prob = I.shock_vortex(256, 128, seed=42)
     res = {}
     for name, kw in (("plain", {}), ("routed", {"sensor": 1})):
