@@ -14,255 +14,11 @@
 // interface: with f_k = u_n U_k + p_k (0, n, u_n) the projected flux is
 // g_kj = u_n,k V_kj + p_k (l_j,m . n + l_j,E u_n,k), so only V = L U is
 // formed per point, and L, R are never stored as matrices.
-#include "charflux.hpp"
+#include "sweep.hpp"
 
 namespace osbli {
 namespace {
 using namespace cf;
-template <int ND, int DIR>
-struct Axes {
-    static constexpr int T1 = (DIR + 1) % ND;
-    static constexpr int T2 = (DIR + 2) % ND;
-};
-
-constexpr int kChunk = 8;   // x-points staged per cooperative load (x sweep)
-constexpr int kWaves = 4;   // waves per block
-
-// One convective sweep along DIR.  first != 0: R = contribution, else R +=.
-// Thread mapping: every wave owns 64 consecutive lines and one segment
-// [p0, p1) along DIR (wave-uniform), lane l owns line line0 + l.  Along y and
-// z the lanes' loads are contiguous in x.  Along x the lines are strided, so
-// the wave stages chunks of kChunk points of its 64 rows through LDS with
-// contiguous loads and each lane reads its own row back.
-template <int ND, int DIR, int SCHEME, bool GEN, bool MIX, bool ROUTE>
-__global__ void __launch_bounds__(256)
-k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t seg,
-        int64_t nseg, int first, unsigned *flags, const uint8_t *__restrict__ mask) {
-    constexpr int NC = ND + 2;
-    constexpr int NT = ND - 1;
-    constexpr int O1 = DIR == 0 ? 1 : 0;
-    constexpr int O2 = DIR == 2 ? 1 : 2;
-    const int64_t n1 = g.n[O1], n2 = g.n[O2], N = g.n[DIR];
-    const int64_t lines = n1 * n2;
-    const int64_t wpl = (lines + 63) >> 6;  // waves per segment
-    const int lane = threadIdx.x & 63;
-    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t sg = gw / wpl;
-    if (sg >= nseg) return;  // wave-uniform
-    const int64_t line0 = (gw - sg * wpl) << 6;
-    const int64_t line = line0 + lane;
-    const bool active = line < lines;
-    const int64_t lc = active ? line : lines - 1;
-    const int64_t p0 = sg * seg;
-    const int64_t p1 = p0 + seg < N ? p0 + seg : N;
-    int64_t q[3];
-    q[DIR] = 0;
-    q[O1] = lc % n1;
-    q[O2] = lc / n1;
-    const int64_t base = ext_index(g, q[0], q[1], q[2]);
-    const int64_t st = g.es[DIR];
-    const int64_t cs = g.enpts;
-    const int64_t ibase = int_index(g, q[0], q[1], q[2]);
-    const int64_t ist = g.is[DIR];
-    bool bad = false;
-
-    // x sweep staging buffer: [wave][component][chunk point][row]
-    __shared__ double sbuf[DIR == 0 ? kWaves : 1][DIR == 0 ? NC : 1][DIR == 0 ? kChunk : 1][64];
-    const int wv = DIR == 0 ? (threadIdx.x >> 6) : 0;
-    int64_t cbase = p0 - 3 - kChunk;  // first point held in the chunk buffer
-    // point q's conserved state into w (from LDS along x, directly otherwise)
-    auto fetch = [&](int64_t qp, Pt<ND> &w) {
-        if (DIR == 0) {
-            if (qp >= cbase + kChunk) {
-                cbase = qp;
-                const int64_t last = N + kGhost - 1;
-#pragma unroll
-                for (int s2 = 0; s2 < kChunk; ++s2) {
-                    const int e = lane + 64 * s2;
-                    const int r = e / kChunk, x = e % kChunk;
-                    int64_t rl = line0 + r;
-                    if (rl >= lines) rl = lines - 1;
-                    const int64_t rb = ext_index(g, 0, rl % n1, rl / n1);
-                    int64_t xp = qp + x;
-                    if (xp > last) xp = last;
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) sbuf[wv][c][x][r] = U[rb + xp + c * cs];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-            const int xi = (int)(qp - cbase);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) w.U[c] = sbuf[wv][c][xi][lane];
-        } else {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) w.U[c] = U[base + qp * st + c * cs];
-        }
-        finish_point<ND>(ph, w, bad);
-    };
-
-    Pt<ND> w[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) fetch(p0 - 3 + k, w[k]);
-
-    // general meshes: node area vectors S_DIR at f-1 .. f+2 for interface f+1/2
-    double Sw[4][3];
-    if (GEN) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int c = 0; c < ND; ++c)
-                Sw[k][c] = m.S[(DIR * ND + c) * cs + base + (p0 - 2 + k) * st];
-    }
-
-    // routing masks of interfaces f-1, f, f+1 (index p + 1 along DIR of the
-    // direction's interface grid, extent N + 1); outside the line: smooth
-    int64_t mbase = 0, mst = 1;
-    if (ROUTE) {
-        int64_t E[3] = {g.n[0], g.n[1], g.n[2]};
-        E[DIR] += 1;
-        const int64_t ms[3] = {1, E[0], E[0] * E[1]};
-        mbase = q[O1] * ms[O1] + q[O2] * ms[O2];
-        mst = ms[DIR];
-    }
-    auto mload = [&](int64_t pp) -> bool {
-        if (pp < -1 || pp > N - 1) return true;
-        return mask[mbase + (pp + 1) * mst] != 0;
-    };
-    bool mprev = true, mcur = true, mnext = true;
-    if (ROUTE) {
-        mprev = mload(p0 - 2);
-        mcur = mload(p0 - 1);
-        mnext = mload(p0);
-    }
-
-    double Fp[NC];
-    for (int64_t f = p0 - 1; f < p1; ++f) {
-        if (ROUTE && f >= p0) {
-            mprev = mcur;
-            mcur = mnext;
-            mnext = mload(f + 1);
-        }
-        if (f >= p0) {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) w[k] = w[k + 1];
-            fetch(f + 3, w[5]);
-            if (GEN) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int c = 0; c < ND; ++c) Sw[k][c] = Sw[k + 1][c];
-#pragma unroll
-                for (int c = 0; c < ND; ++c) Sw[3][c] = m.S[(DIR * ND + c) * cs + base + (f + 2) * st];
-            }
-        }
-        Loc<ND> P[6];
-        double F[NC];
-        double Smag = 1.0;
-        double nv[3] = {0.0, 0.0, 0.0}, t1[3] = {0.0, 0.0, 0.0}, t2[3] = {0.0, 0.0, 0.0};
-        if (!GEN) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                P[k].r = w[k].U[0];
-                P[k].mn = w[k].U[1 + DIR];
-                if (NT >= 1) P[k].mt[0] = w[k].U[1 + Axes<ND, DIR>::T1];
-                if (NT >= 2) P[k].mt[1] = w[k].U[1 + Axes<ND, DIR>::T2];
-                P[k].E = w[k].U[ND + 1];
-                P[k].p = w[k].p;
-                P[k].a = w[k].a;
-                P[k].ri = w[k].ri;
-            }
-        } else {
-            double Sh[3] = {0.0, 0.0, 0.0};
-            double s2 = 0.0;
-#pragma unroll
-            for (int c = 0; c < ND; ++c) {
-                Sh[c] = (-Sw[0][c] + 7.0 * Sw[1][c] + 7.0 * Sw[2][c] - Sw[3][c]) / 12.0;
-                s2 += Sh[c] * Sh[c];
-            }
-            Smag = sqrt(s2);
-#pragma unroll
-            for (int c = 0; c < ND; ++c) nv[c] = Sh[c] / Smag;
-            // tangent basis: t1 = normalise(e_{DIR+1} - (e_{DIR+1}.n) n), t2 = n x t1
-            if (ND >= 2) {
-                constexpr int TE = (DIR + 1) % (ND > 1 ? ND : 1);
-                const double en = nv[TE];
-                double tn = 0.0;
-#pragma unroll
-                for (int c = 0; c < ND; ++c) {
-                    t1[c] = (c == TE ? 1.0 : 0.0) - en * nv[c];
-                    tn += t1[c] * t1[c];
-                }
-                tn = sqrt(tn);
-#pragma unroll
-                for (int c = 0; c < ND; ++c) t1[c] /= tn;
-                if (ND == 3) {
-                    t2[0] = nv[1] * t1[2] - nv[2] * t1[1];
-                    t2[1] = nv[2] * t1[0] - nv[0] * t1[2];
-                    t2[2] = nv[0] * t1[1] - nv[1] * t1[0];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                double mn = 0.0, m1 = 0.0, m2 = 0.0;
-#pragma unroll
-                for (int c = 0; c < ND; ++c) {
-                    mn += w[k].U[1 + c] * nv[c];
-                    m1 += w[k].U[1 + c] * t1[c];
-                    m2 += w[k].U[1 + c] * t2[c];
-                }
-                P[k].r = w[k].U[0];
-                P[k].mn = mn;
-                P[k].mt[0] = m1;
-                P[k].mt[1] = m2;
-                P[k].E = w[k].U[ND + 1];
-                P[k].p = w[k].p;
-                P[k].a = w[k].a;
-                P[k].ri = w[k].ri;
-            }
-        }
-        double Fr, Fn, Ft[2], FE;
-        const bool cheap = ROUTE && mcur && (!ph.dilate || (mprev && mnext));
-        if (cheap) {
-            if (MIX) cheap_flux_mixed<ND>(P, ph, Fr, Fn, Ft, FE);
-            else cheap_flux<ND>(P, ph, Fr, Fn, Ft, FE);
-        } else {
-            if (MIX) char_flux_mixed<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
-            else char_flux<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
-        }
-        F[0] = Fr * Smag;
-        F[NC - 1] = FE * Smag;
-        if (!GEN) {
-            F[1 + DIR] = Fn;
-            if (NT >= 1) F[1 + Axes<ND, DIR>::T1] = Ft[0];
-            if (NT >= 2) F[1 + Axes<ND, DIR>::T2] = Ft[1];
-        } else {
-#pragma unroll
-            for (int c = 0; c < ND; ++c) {
-                double v = Fn * nv[c];
-                if (NT >= 1) v += Ft[0] * t1[c];
-                if (NT >= 2) v += Ft[1] * t2[c];
-                F[1 + c] = v * Smag;
-            }
-        }
-        if (f >= p0 && active) {
-            const double sc = GEN ? m.J[base + f * st] : m.invh[DIR][f];
-            const int64_t oi = ibase + f * ist;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const double v = -sc * (F[c] - Fp[c]);
-                double *dst = R + c * g.nint + oi;
-                if (first) *dst = v;
-                else *dst += v;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) Fp[c] = F[c];
-    }
-    if (bad) atomicOr(flags, kFlagNonPhys);
-}
-
 template <int ND, int DIR, int SCHEME, bool GEN, bool MIX, bool ROUTE>
 hipError_t launch_one(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
                       unsigned *flags, int first, const uint8_t *mask, hipStream_t s) {
