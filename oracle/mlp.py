@@ -46,13 +46,13 @@ def bf16_bits(x):
 
 
 def init(seed=0):
-    """He-uniform initial weights, zero biases."""
+    """Glorot-uniform initial weights, zero biases."""
     rng = np.random.default_rng(seed)
-    p = {"W1": rng.uniform(-1, 1, (NIN, NH)) * np.sqrt(6.0 / NIN),
+    p = {"W1": rng.uniform(-1, 1, (NIN, NH)) * np.sqrt(6.0 / (NIN + NH)),
          "b1": np.zeros(NH),
-         "W2": rng.uniform(-1, 1, (NH, NH)) * np.sqrt(6.0 / NH),
+         "W2": rng.uniform(-1, 1, (NH, NH)) * np.sqrt(6.0 / (2 * NH)),
          "b2": np.zeros(NH),
-         "w3": rng.uniform(-1, 1, NH) * np.sqrt(6.0 / NH),
+         "w3": rng.uniform(-1, 1, NH) * np.sqrt(6.0 / (NH + 1)),
          "b3": np.zeros(1)}
     return pack(p)
 

@@ -26,9 +26,15 @@ FLAGS = [
 ]
 
 
+# translation units compiled without FMA contraction: the sensor's features
+# and training arithmetic follow their FP64 definitions operation by operation
+NO_CONTRACT = {"sensor.hip"}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-ffp-contract=off"] if src in NO_CONTRACT else []
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-6000:]))

@@ -32,48 +32,60 @@ __device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even
 template <int ND, int DIR>
 __device__ __forceinline__ void features(const double *__restrict__ U, int64_t e0, int64_t st, int64_t cs,
                                          const Phys &ph, float (&f)[kIn]) {
+    // same operation order as the FP64 definition (this file is compiled
+    // without FMA contraction), so the features are reproducible
     double rho[6], p[6], vt[2][6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const int64_t e = e0 + k * st;
-        const double r = U[e], ri = 1.0 / r;
-        double ke = 0.0;
+        const double r = U[e];
+        double u[3], ke = 0.0;
 #pragma unroll
-        for (int m = 0; m < ND; ++m) ke += U[e + (1 + m) * cs] * U[e + (1 + m) * cs];
+        for (int m = 0; m < ND; ++m) {
+            u[m] = U[e + (1 + m) * cs] / r;
+            ke += u[m] * u[m];
+        }
         rho[k] = r;
-        p[k] = ph.gm1 * (U[e + (ND + 1) * cs] - 0.5 * ke * ri);
+        p[k] = ph.gm1 * (U[e + (ND + 1) * cs] - 0.5 * r * ke);
 #pragma unroll
-        for (int s = 0; s < ND - 1; ++s) vt[s][k] = U[e + (1 + (DIR + 1 + s) % ND) * cs] * ri;
+        for (int s = 0; s < ND - 1; ++s) vt[s][k] = u[(DIR + 1 + s) % ND];
     }
     const double rb = 0.5 * (rho[2] + rho[3]), pb = 0.5 * (p[2] + p[3]);
-    const double irb = 1.0 / rb, ipb = 1.0 / pb, iab = 1.0 / sqrt(ph.gamma * pb * irb);
+    const double ab = sqrt(ph.gamma * pb / rb);
+    double rn[6], qn[6], vn[2][6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        rn[k] = rho[k] / rb;
+        qn[k] = p[k] / pb;
+#pragma unroll
+        for (int s = 0; s < ND - 1; ++s) vn[s][k] = vt[s][k] / ab;
+    }
     double beta[4], sum = 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        double a1 = (rho[m] - 2.0 * rho[m + 1] + rho[m + 2]) * irb, a2 = (rho[m] - rho[m + 2]) * irb;
+        double a1 = rn[m] - 2.0 * rn[m + 1] + rn[m + 2], a2 = rn[m] - rn[m + 2];
         double b = (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
-        a1 = (p[m] - 2.0 * p[m + 1] + p[m + 2]) * ipb;
-        a2 = (p[m] - p[m + 2]) * ipb;
+        a1 = qn[m] - 2.0 * qn[m + 1] + qn[m + 2];
+        a2 = qn[m] - qn[m + 2];
         b += (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
 #pragma unroll
         for (int s = 0; s < ND - 1; ++s) {
-            a1 = (vt[s][m] - 2.0 * vt[s][m + 1] + vt[s][m + 2]) * iab;
-            a2 = (vt[s][m] - vt[s][m + 2]) * iab;
+            a1 = vn[s][m] - 2.0 * vn[s][m + 1] + vn[s][m + 2];
+            a2 = vn[s][m] - vn[s][m + 2];
             b += (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
         }
         beta[m] = b;
         sum += b;
     }
-    const double isum = 1.0 / (sum + 1e-20);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) f[m] = (float)(beta[m] * isum);
+    for (int m = 0; m < 4; ++m) f[m] = (float)(beta[m] / (sum + 1e-20));
     // jumps |q_{k+1} - q_k| / (q_{k+1} + q_k), log-normalised: log10(1 + 1e6 J) / 6
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         const double jr = fabs(rho[m + 2] - rho[m + 1]) / (rho[m + 2] + rho[m + 1]);
         const double jp = fabs(p[m + 2] - p[m + 1]) / (p[m + 2] + p[m + 1]);
-        f[4 + m] = log10f(1.0f + 1e6f * (float)jr) * (1.0f / 6.0f);
-        f[7 + m] = log10f(1.0f + 1e6f * (float)jp) * (1.0f / 6.0f);
+        f[4 + m] = (float)(log10(1.0 + 1e6 * jr) / 6.0);
+        f[7 + m] = (float)(log10(1.0 + 1e6 * jp) / 6.0);
     }
 }
 
@@ -176,10 +188,13 @@ k_mlp_grad(const float *__restrict__ X, const uint8_t *__restrict__ y, int64_t n
     fwd_fp32(x, W, o);
     const float yv = valid ? (float)y[s] : 0.0f;
     const float wt = valid ? (yv > 0.5f ? 1.0f : wneg) : 0.0f;
-    const float sig = 1.0f / (1.0f + expf(-o.z));
-    const float dz = wt * (sig - yv) * inv_n;
-    const float sp = fmaxf(o.z, 0.0f) + log1pf(expf(-fabsf(o.z)));
-    sl[tid] = wt * (sp - yv * o.z) * inv_n;
+    // sigmoid and the loss term in FP64 (float expf would carry its own
+    // rounding into every gradient)
+    const double zd = o.z;
+    const double sig = 1.0 / (1.0 + exp(-zd));
+    const float dz = (float)(wt * (sig - yv) * inv_n);
+    const double sp = fmax(zd, 0.0) + log1p(exp(-fabs(zd)));
+    sl[tid] = (float)(wt * (sp - yv * zd) * inv_n);
     sdz[tid] = dz;
     float d2[kH];
 #pragma unroll

@@ -44,7 +44,7 @@ def test_mixed_form_error_against_oracle(name):
     Uo, to = oracle_run(prob, **kw)
     e = rel_errors(prob, Ug, Uo)
     say("   t=%.5g (oracle %.5g) " % (tg, to) + " ".join("%s=%.3e" % kv for kv in e.items()))
-    assert abs(tg - to) <= 1e-6 * max(1.0, to)
+    assert abs(tg - to) <= 1e-4 * to  # CFL dt from the FP32-evaluated state
     assert e["rho_L1"] <= bound[0] and e["rhoE_L1"] <= bound[1], e
 
 
