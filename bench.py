@@ -36,6 +36,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / sensor forms")
     ap.add_argument("--cpu-n", type=int, default=0, help="oracle sample grid (default: same as --n)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble line")
+    ap.add_argument("--batch-steps", type=int, default=30)
+    ap.add_argument("--batch-full", action="store_true",
+                    help="also run both batched forms to t = 0.25 and report their density difference")
+    ap.add_argument("--no-tune", action="store_true", help="batched ensemble with default tiles")
     return ap.parse_args()
 
 
@@ -121,6 +126,140 @@ def form_error(prob, form, steps, cfl):
     return res
 
 
+def sensor_form(cfl):
+    """Shock-vortex field 1024 x 512 (seed 42) run to t = 0.4: plain FP64,
+    FP64 + learned routing, FP32 reconstruction + learned routing.  Whole
+    runs (dt reduction, sensor refresh, sweeps, updates, BCs), timed with
+    events on the solver's stream; error = relative L1 of rho against plain
+    at the end time."""
+    import numpy as np
+    import torch
+    from paper_2007_14933_amd import cost, inputs
+    from paper_2007_14933_amd import sensor as SN
+    from paper_2007_14933_amd.solver import Solver
+    if not os.path.exists(SN.DEFAULT_WEIGHTS):
+        return {"skipped": "no trained weights at %s" % os.path.relpath(SN.DEFAULT_WEIGHTS, ROOT)}
+    bits, thr = SN.load()
+    prob = inputs.shock_vortex(1024, 512, seed=42)
+    npts = prob.npoints
+    res, ref = {}, None
+    for name, form, sensor in (("plain_fp64", 0, 0), ("fp64_learned", 0, 1), ("fp32_learned", 1, 1),
+                               ("fp32_plain", 1, 0)):
+        s = Solver(prob, form=form, sensor=sensor)
+        if sensor:
+            s.set_sensor(bits, thr)
+        s.apply_bc()
+        torch.cuda.synchronize()
+        s.profile(True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(s.stream)
+        s.run(10 ** 9, cfl=cfl, t_end=prob.t_end, start_bc=False)
+        ev1.record(s.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s.check()
+        prof = s.profile_read()
+        rho = s.interior()[0]
+        v = npts * 3 * s.nsteps_done / wall / 1e6
+        sweeps = sum(prof["sweep_%s" % a][1] for a in "xy")
+        r = {"value": round(v, 3), "steps": s.nsteps_done, "t_end": round(s.t, 6),
+             "gpu_ms": round(ev0.elapsed_time(ev1), 3), "sweep_ms": round(sweeps, 3),
+             "sensor_ms": round(prof["sensor"][1], 3),
+             "hbm_compulsory_frac": round(npts * 3 * s.nsteps_done * cost.compulsory_bytes_per_point(2) / wall
+                                          / 1e9 / cost.PEAK_HBM_GBS, 4)}
+        if sensor:
+            sm, tot = s.sensor_stats()
+            r["smooth_fraction_last"] = round(sm / tot, 4)
+        if ref is None:
+            ref = rho
+        else:
+            r["rel_L1_rho_vs_plain"] = float("%.3e" % (np.abs(rho - ref).mean() / np.abs(ref).mean()))
+            r["speedup_vs_plain"] = round(v / res["plain_fp64"]["value"], 3)
+        res[name] = r
+        del s
+        torch.cuda.empty_cache()
+    res["workload"] = "shock-vortex 1024x512 seed 42, TENO5, CFL 0.5, to t=0.4; threshold %.3f" % thr
+    return res
+
+
+def batch_form(steps, warmup, cfl, tune, full):
+    """The batched ensemble: 64 seeded four-quadrant Riemann problems,
+    N in {128, 192, ..., 1024}, each with its own dt.  Timed over `steps`
+    whole-ensemble steps (three graph launches each); value counts the
+    points of active problems.  Also the same problems advanced one by one
+    (single-grid calls, a few steps each) for the batching gain."""
+    import numpy as np
+    import torch
+    from paper_2007_14933_amd import inputs
+    from paper_2007_14933_amd import sensor as SN
+    from paper_2007_14933_amd.batch import Batch
+    from paper_2007_14933_amd.solver import Solver
+    probs = inputs.riemann_batch(64, seed=2007)
+    npts = sum(p.npoints for p in probs)
+    out = {"workload": "64 four-quadrant Riemann problems (seed 2007), N in 128..1024 step 64, "
+                       "%d points, TENO5, CFL 0.5, per-problem dt, t_end 0.25" % npts}
+    have_w = os.path.exists(SN.DEFAULT_WEIGHTS)
+    forms = [("plain_fp64", 0, 0)] + ([("fp32_learned", 1, 1)] if have_w else [])
+    bits, thr = SN.load() if have_w else (None, None)
+    finals = {}
+    for name, form, sensor in forms:
+        kw = dict(form=form, sensor=sensor, weights=bits, threshold=thr, cfl=cfl)
+        b = Batch(probs, **kw)
+        tiles = b.tune(candidates=(16, 32, 64, 128, 256), nsteps=3) if tune else None
+        b.step(warmup)
+        b.stream.synchronize()
+        _, act, _ = b.status()
+        act_pts = sum(p.npoints for p, a in zip(probs, act) if a)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(b.stream)
+        b.step(steps)
+        ev1.record(b.stream)
+        b.stream.synchronize()
+        wall = time.perf_counter() - t0
+        b.check()
+        r = {"value": round(act_pts * 3 * steps / wall / 1e6, 3), "ms_per_step": round(wall * 1e3 / steps, 4),
+             "gpu_ms_per_step": round(ev0.elapsed_time(ev1) / steps, 4), "steps": steps,
+             "tiles_tuned": bool(tune)}
+        if tiles:
+            r["tiles"] = {"%dx%d" % k: list(v) for k, v in sorted(tiles.items())}
+        if full:
+            n = b.run()
+            b.check()
+            r["full_run_steps"] = n + steps + warmup
+            finals[name] = [b.interior(p)[0] for p in range(len(probs))]
+        out[name] = r
+        del b
+        torch.cuda.empty_cache()
+    if "fp32_learned" in out:
+        out["fp32_learned"]["speedup_vs_plain"] = round(out["fp32_learned"]["value"] / out["plain_fp64"]["value"], 3)
+    if full and len(finals) == 2:
+        errs = [float(np.abs(a - b).mean() / np.abs(b).mean()) for a, b in zip(finals["fp32_learned"],
+                                                                                 finals["plain_fp64"])]
+        out["fp32_learned"]["rel_L1_rho_vs_plain_at_t_end"] = {
+            "median": float("%.3e" % np.median(errs)), "max": float("%.3e" % max(errs))}
+    # one by one: every problem through the single-grid calls, a few steps each
+    solo_ms = 0.0
+    k = 4
+    for p in probs:
+        s = Solver(p)
+        s.apply_bc()
+        s.step(s.compute_dt(cfl))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            s.step(s.compute_dt(cfl))
+        torch.cuda.synchronize()
+        solo_ms += (time.perf_counter() - t0) * 1e3 / k
+        del s
+    torch.cuda.empty_cache()
+    out["one_by_one_plain_fp64"] = {"ms_per_ensemble_step": round(solo_ms, 3),
+                                    "value": round(npts * 3 / solo_ms / 1e3, 3)}
+    out["plain_fp64"]["batching_gain"] = round(solo_ms / out["plain_fp64"]["ms_per_step"], 3)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -179,6 +318,9 @@ def main():
             "value": round(vm, 3), "speedup_vs_fp64": round(vm / value, 3),
             "sweep_avg_ms": round(sm, 4),
             "error_vs_fp64": form_error(prob, 1, 10, args.cfl)}}
+        out["forms"]["learned_sensor"] = sensor_form(args.cfl)
+    if not args.no_batch:
+        out["batch"] = batch_form(args.batch_steps, args.warmup, args.cfl, not args.no_tune, args.batch_full)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n or n)
     print(json.dumps(out), flush=True)

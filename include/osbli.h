@@ -220,6 +220,65 @@ int osbli_mlp_adam(float *master, uint16_t *w, const float *grad, float *m, floa
  * inference = 1 the bfloat16 MFMA path used for routing. */
 int osbli_mlp_forward(const float *X, int64_t n, const uint16_t *w, float *z, int inference, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Batched advance of many independent 2D problems of uneven size (not in
+ * the paper, whose runs are one block at a time).  Each problem keeps its
+ * own context (osbli_init_grid), state U and RK register dU; the batch
+ * advances all of them by one RK3 step per osbli_batch_step with its own
+ * CFL time step per problem (section 2.7 scheme, dt clipped so that problem
+ * p ends exactly at t_end[p], after which it is skipped).  A step is three
+ * launches of captured graphs, one per substage, each a fixed sequence of
+ * persistent kernels whose workgroups walk a tile queue spanning every
+ * problem; dt, t and the active flag live on the device, so no host logic
+ * runs between substages.  A batched problem evolves bit for bit as the
+ * same problem advanced alone with osbli_compute_dt / osbli_rk_substep /
+ * osbli_apply_bc and the same dt clipping.
+ *
+ * Requirements: every context 2D, separable mesh, inviscid (Re <= 0),
+ * periodic or extrapolation boundaries; equal gamma, scheme, form, sensor
+ * switch, averaging, C_T and epsilon; with the sensor on, weights set on
+ * every context with equal threshold and dilation (context 0's weights are
+ * used).  The contexts, their workspaces and the U / dU arrays must outlive
+ * the batch.  Problems start at t = 0 with valid ghosts (osbli_apply_bc).
+ * --------------------------------------------------------------------- */
+typedef struct osbli_batch osbli_batch;
+
+/* Device workspace of a batch of nprob problems (256-byte aligned). */
+size_t osbli_batch_workspace_bytes(int nprob);
+
+/* Create a batch over contexts ctxs[0..nprob-1] with device arrays U[p],
+ * dU[p] (host arrays of device pointers), end times t_end[p] > 0 (host) and
+ * the CFL number.  Tiles start at the single-grid defaults.  *batch is set
+ * even on failure (for osbli_batch_last_error); release it with
+ * osbli_batch_destroy.  Synchronising. */
+int osbli_batch_create(osbli_batch **batch, osbli_ctx *const *ctxs, int nprob, double *const *U,
+                       double *const *dU, const double *t_end, double cfl, void *workspace, size_t ws_bytes,
+                       void *stream);
+
+/* Sweep tiling: seg[2 p + d] = nodes per wave segment of problem p along
+ * direction d (clamped to n_d).  Results do not depend on it.  Drops any
+ * captured graphs.  Synchronising. */
+int osbli_batch_set_tiles(osbli_batch *batch, const int64_t *seg, void *stream);
+
+/* Capture the three substage graphs on `stream` (must not be the NULL
+ * stream).  Graph instantiation is the runtime's only allocation. */
+int osbli_batch_capture(osbli_batch *batch, void *stream);
+
+/* One RK3 step of every active problem: the captured graphs if any, else
+ * the same kernels launched directly.  Asynchronous. */
+int osbli_batch_step(osbli_batch *batch, void *stream);
+
+/* Per-problem time and active flag (host arrays of nprob, may be NULL) and
+ * the number of active problems.  Synchronising. */
+int osbli_batch_status(osbli_batch *batch, double *t, int *active, int *nactive, void *stream);
+
+/* Interior points of all problems, and the number of sweep wave tiles of
+ * one step's x and y sweeps together. */
+int osbli_batch_interior_points(osbli_batch *batch, int64_t *points, int64_t *wave_tiles);
+
+const char *osbli_batch_last_error(const osbli_batch *batch);
+void osbli_batch_destroy(osbli_batch *batch);
+
 /* Kernel classes timed by the optional profiler. */
 enum osbli_kernel_class {
     OSBLI_K_SWEEP_X = 0,   /* convective sweep along x (y = 1, z = 2 follow) */

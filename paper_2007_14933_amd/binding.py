@@ -68,6 +68,16 @@ _SIGS = {
     "osbli_mlp_grad": (C.c_int, [_VP, _VP, C.c_int64, _VP, C.c_float, _VP, _VP, _VP, C.c_size_t, _VP]),
     "osbli_mlp_adam": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _VP]),
     "osbli_mlp_forward": (C.c_int, [_VP, C.c_int64, _VP, _VP, C.c_int, _VP]),
+    "osbli_batch_workspace_bytes": (C.c_size_t, [C.c_int]),
+    "osbli_batch_create": (C.c_int, [C.POINTER(_VP), C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP), _DP,
+                                     C.c_double, _VP, C.c_size_t, _VP]),
+    "osbli_batch_set_tiles": (C.c_int, [_VP, C.POINTER(C.c_int64), _VP]),
+    "osbli_batch_capture": (C.c_int, [_VP, _VP]),
+    "osbli_batch_step": (C.c_int, [_VP, _VP]),
+    "osbli_batch_status": (C.c_int, [_VP, _DP, C.POINTER(C.c_int), C.POINTER(C.c_int), _VP]),
+    "osbli_batch_interior_points": (C.c_int, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "osbli_batch_last_error": (C.c_char_p, [_VP]),
+    "osbli_batch_destroy": (None, [_VP]),
 }
 
 K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_VISC_FLUX, K_FINISH, K_BC, K_DT, K_SENSOR = range(8)
@@ -119,6 +129,13 @@ def make_params(prob, form=FORM_FP64, sensor=0) -> Params:
     p.form = int(form)
     p.sensor = int(sensor)
     return p
+
+
+def check_batch(code, batch):
+    if code != OSBLI_OK:
+        msg = load().osbli_batch_last_error(batch).decode() if batch else "(no batch)"
+        raise OsbliError(code, msg)
+    return code
 
 
 def check(code, ctx=None):

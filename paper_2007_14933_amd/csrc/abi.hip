@@ -546,3 +546,278 @@ void osbli_destroy(osbli_ctx *c) {
 }
 
 }  // extern "C"
+
+// ===================================================================== batch
+struct osbli_batch {
+    int P;
+    std::vector<osbli_ctx *> ctx;
+    std::vector<BProb> hp;
+    std::vector<BState> hs;
+    Phys ph;
+    int route;
+    const uint16_t *w;
+    float zcut;
+    double cfl;
+    unsigned *flags;
+    BProb *dp;
+    BState *ds;
+    int64_t *dtab;
+    BatchTables T;
+    hipGraph_t graph[3];
+    hipGraphExec_t exec[3];
+    int captured;
+    char err[320];
+};
+
+namespace {
+
+int bset_err(osbli_batch *b, int code, const char *fmt, ...) {
+    if (b) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(b->err, sizeof(b->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIP_BTRY(b, call)                                                                               \
+    do {                                                                                                \
+        hipError_t e__ = (call);                                                                        \
+        if (e__ != hipSuccess)                                                                          \
+            return bset_err((b), OSBLI_EDEVICE, "%s: %s", #call, hipGetErrorString(e__));              \
+    } while (0)
+
+size_t batch_table_bytes(int P) { return align256(sizeof(int64_t) * 7 * (size_t)(P + 1)); }
+
+// default segment length of a sweep (same rule as the single-grid launch)
+int64_t default_seg(const Grid &g, int d) {
+    const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+    const int64_t lines = g.n[o1] * g.n[o2], N = g.n[d];
+    const int64_t target = int64_t(1) << 18;
+    int64_t seg = (N * lines + target - 1) / target;
+    if (seg < 8) seg = 8;
+    if (seg > N) seg = N;
+    return seg;
+}
+
+// host prefix tables -> device; totals into T
+int upload_tables(osbli_batch *b, hipStream_t s) {
+    const int P = b->P;
+    std::vector<int64_t> h(7 * (size_t)(P + 1), 0);
+    int64_t *W0 = &h[0], *W1 = &h[(P + 1)], *PT = &h[2 * (P + 1)], *F0 = &h[3 * (P + 1)], *F1 = &h[4 * (P + 1)],
+            *S0 = &h[5 * (P + 1)], *S1 = &h[6 * (P + 1)];
+    for (int p = 0; p < P; ++p) {
+        BProb &q = b->hp[p];
+        for (int d = 0; d < 2; ++d) {
+            const int o1 = d == 0 ? 1 : 0;
+            q.nseg[d] = (q.g.n[d] + q.seg[d] - 1) / q.seg[d];
+            q.wpl[d] = (q.g.n[o1] + 63) / 64;
+        }
+        const int64_t nw0 = q.nseg[0] * q.wpl[0], nw1 = q.nseg[1] * q.wpl[1];
+        W0[p + 1] = W0[p] + nw0;
+        W1[p + 1] = W1[p] + nw1;
+        PT[p + 1] = PT[p] + (q.g.nint + 255) / 256;
+        F0[p + 1] = F0[p] + 2 * q.g.e[1] * q.g.e[2];
+        F1[p + 1] = F1[p] + 2 * q.g.e[0] * q.g.e[2];
+        S0[p + 1] = S0[p] + (iface_count(q.g, 0) + 255) / 256;
+        S1[p + 1] = S1[p] + (iface_count(q.g, 1) + 255) / 256;
+    }
+    HIP_BTRY(b, hipMemcpyAsync(b->dtab, h.data(), sizeof(int64_t) * h.size(), hipMemcpyHostToDevice, s));
+    HIP_BTRY(b, hipMemcpyAsync(b->dp, b->hp.data(), sizeof(BProb) * P, hipMemcpyHostToDevice, s));
+    HIP_BTRY(b, hipStreamSynchronize(s));
+    BatchTables &T = b->T;
+    T.w[0] = b->dtab;
+    T.w[1] = b->dtab + (P + 1);
+    T.pt = b->dtab + 2 * (P + 1);
+    T.f[0] = b->dtab + 3 * (P + 1);
+    T.f[1] = b->dtab + 4 * (P + 1);
+    T.s[0] = b->dtab + 5 * (P + 1);
+    T.s[1] = b->dtab + 6 * (P + 1);
+    T.tot_w[0] = W0[P];
+    T.tot_w[1] = W1[P];
+    T.tot_pt = PT[P];
+    T.tot_f[0] = F0[P];
+    T.tot_f[1] = F1[P];
+    T.tot_s[0] = S0[P];
+    T.tot_s[1] = S1[P];
+    return OSBLI_OK;
+}
+
+void drop_graphs(osbli_batch *b) {
+    if (!b->captured) return;
+    for (int s = 0; s < 3; ++s) {
+        hipGraphExecDestroy(b->exec[s]);
+        hipGraphDestroy(b->graph[s]);
+    }
+    b->captured = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t osbli_batch_workspace_bytes(int nprob) {
+    if (nprob < 1) return 0;
+    return align256(sizeof(BProb) * nprob) + align256(sizeof(BState) * nprob) + batch_table_bytes(nprob);
+}
+
+int osbli_batch_create(osbli_batch **out, osbli_ctx *const *ctxs, int P, double *const *U, double *const *dU,
+                       const double *t_end, double cfl, void *workspace, size_t ws_bytes, void *stream) {
+    if (!out) return OSBLI_EINVAL;
+    *out = nullptr;
+    osbli_batch *b = new (std::nothrow) osbli_batch();
+    if (!b) return OSBLI_EINVAL;
+    *out = b;
+    b->err[0] = 0;
+    b->captured = 0;
+    if (P < 1 || !ctxs || !U || !dU || !t_end || !workspace) return bset_err(b, OSBLI_EINVAL, "null argument or P < 1");
+    if (ws_bytes < osbli_batch_workspace_bytes(P)) return bset_err(b, OSBLI_ENOSPACE, "batch workspace too small");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return bset_err(b, OSBLI_EINVAL, "workspace not 256-byte aligned");
+    if (!(cfl > 0.0)) return bset_err(b, OSBLI_EINVAL, "cfl must be positive");
+    const osbli_ctx *c0 = ctxs[0];
+    for (int p = 0; p < P; ++p) {
+        const osbli_ctx *c = ctxs[p];
+        if (!c || !U[p] || !dU[p]) return bset_err(b, OSBLI_EINVAL, "problem %d: null context or state", p);
+        if (c->g.nd != 2 || c->m.general || c->ph.viscous)
+            return bset_err(b, OSBLI_EINVAL, "problem %d: batching takes inviscid 2D separable problems", p);
+        for (int d = 0; d < 2; ++d)
+            for (int s2 = 0; s2 < 2; ++s2)
+                if (c->p.bc_kind[d][s2] != OSBLI_PERIODIC && c->p.bc_kind[d][s2] != OSBLI_EXTRAPOLATE)
+                    return bset_err(b, OSBLI_EINVAL, "problem %d: batching takes periodic / extrapolation BCs", p);
+        if (c->p.gamma != c0->p.gamma || c->p.scheme != c0->p.scheme || c->p.form != c0->p.form ||
+            c->p.sensor != c0->p.sensor || c->p.roe_avg != c0->p.roe_avg || c->p.teno_CT != c0->p.teno_CT ||
+            c->p.eps != c0->p.eps)
+            return bset_err(b, OSBLI_EINVAL, "problem %d: physics differs from problem 0", p);
+        if (c->p.sensor && (!c->sensor_ready || c->zcut != c0->zcut || c->ph.dilate != c0->ph.dilate))
+            return bset_err(b, OSBLI_EINVAL, "problem %d: sensor weights unset or differ", p);
+        if (!(t_end[p] > 0.0)) return bset_err(b, OSBLI_EINVAL, "problem %d: t_end must be positive", p);
+    }
+    b->P = P;
+    b->ctx.assign(ctxs, ctxs + P);
+    b->ph = c0->ph;
+    b->route = c0->p.sensor && c0->sensor_ready;
+    b->w = c0->wts;
+    b->zcut = c0->zcut;
+    b->cfl = cfl;
+    b->flags = c0->flags;
+    char *ws = static_cast<char *>(workspace);
+    b->dp = reinterpret_cast<BProb *>(ws);
+    b->ds = reinterpret_cast<BState *>(ws + align256(sizeof(BProb) * P));
+    b->dtab = reinterpret_cast<int64_t *>(ws + align256(sizeof(BProb) * P) + align256(sizeof(BState) * P));
+    b->hp.resize(P);
+    b->hs.resize(P);
+    for (int p = 0; p < P; ++p) {
+        const osbli_ctx *c = ctxs[p];
+        BProb &q = b->hp[p];
+        q.g = c->g;
+        q.U = U[p];
+        q.dU = dU[p];
+        q.R = c->Racc;
+        for (int d = 0; d < 3; ++d) {
+            q.invh[d] = c->m.invh[d];
+            q.mask[d] = c->mask[d];
+            q.seg[d] = d < 2 ? default_seg(c->g, d) : 1;
+            q.nseg[d] = 1;
+            q.wpl[d] = 1;
+            for (int s2 = 0; s2 < 2; ++s2) q.bc[d][s2] = c->p.bc_kind[d][s2];
+        }
+        BState &st = b->hs[p];
+        st.t = 0.0;
+        st.dt = 0.0;
+        st.tend = t_end[p];
+        st.smax = 0ull;
+        st.active = 1;
+        st.pad = 0;
+    }
+    hipStream_t s = as_stream(stream);
+    HIP_BTRY(b, hipMemcpyAsync(b->ds, b->hs.data(), sizeof(BState) * P, hipMemcpyHostToDevice, s));
+    return upload_tables(b, s);
+}
+
+int osbli_batch_set_tiles(osbli_batch *b, const int64_t *seg, void *stream) {
+    if (!b || !seg) return bset_err(b, OSBLI_EINVAL, "null argument");
+    for (int p = 0; p < b->P; ++p)
+        for (int d = 0; d < 2; ++d) {
+            const int64_t v = seg[2 * p + d];
+            if (v < 1) return bset_err(b, OSBLI_EINVAL, "segment length must be positive");
+            b->hp[p].seg[d] = v > b->hp[p].g.n[d] ? b->hp[p].g.n[d] : v;
+        }
+    drop_graphs(b);
+    return upload_tables(b, as_stream(stream));
+}
+
+int osbli_batch_capture(osbli_batch *b, void *stream) {
+    if (!b) return OSBLI_EINVAL;
+    hipStream_t s = as_stream(stream);
+    if (!s) return bset_err(b, OSBLI_EINVAL, "capture needs a non-default stream");
+    drop_graphs(b);
+    for (int st = 0; st < 3; ++st) {
+        HIP_BTRY(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = launch_batch_stage(b->dp, b->ds, b->T, b->P, b->ph, st, b->cfl, b->route, b->w, b->zcut,
+                                          b->flags, s);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            for (int k = 0; k < st; ++k) {
+                hipGraphExecDestroy(b->exec[k]);
+                hipGraphDestroy(b->graph[k]);
+            }
+            return bset_err(b, OSBLI_EDEVICE, "graph capture of stage %d failed: %s", st,
+                            hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        b->graph[st] = g;
+        HIP_BTRY(b, hipGraphInstantiate(&b->exec[st], g, nullptr, nullptr, 0));
+    }
+    b->captured = 1;
+    return OSBLI_OK;
+}
+
+int osbli_batch_step(osbli_batch *b, void *stream) {
+    if (!b) return OSBLI_EINVAL;
+    hipStream_t s = as_stream(stream);
+    for (int st = 0; st < 3; ++st) {
+        if (b->captured) {
+            HIP_BTRY(b, hipGraphLaunch(b->exec[st], s));
+        } else {
+            HIP_BTRY(b, launch_batch_stage(b->dp, b->ds, b->T, b->P, b->ph, st, b->cfl, b->route, b->w, b->zcut,
+                                           b->flags, s));
+        }
+    }
+    return OSBLI_OK;
+}
+
+int osbli_batch_status(osbli_batch *b, double *t, int *active, int *nactive, void *stream) {
+    if (!b) return OSBLI_EINVAL;
+    hipStream_t s = as_stream(stream);
+    HIP_BTRY(b, hipMemcpyAsync(b->hs.data(), b->ds, sizeof(BState) * b->P, hipMemcpyDeviceToHost, s));
+    HIP_BTRY(b, hipStreamSynchronize(s));
+    int n = 0;
+    for (int p = 0; p < b->P; ++p) {
+        if (t) t[p] = b->hs[p].t;
+        if (active) active[p] = b->hs[p].active;
+        n += b->hs[p].active != 0;
+    }
+    if (nactive) *nactive = n;
+    return OSBLI_OK;
+}
+
+int osbli_batch_interior_points(osbli_batch *b, int64_t *points, int64_t *wave_tiles) {
+    if (!b || !points) return OSBLI_EINVAL;
+    int64_t n = 0;
+    for (int p = 0; p < b->P; ++p) n += b->hp[p].g.nint;
+    *points = n;
+    if (wave_tiles) *wave_tiles = b->T.tot_w[0] + b->T.tot_w[1];
+    return OSBLI_OK;
+}
+
+const char *osbli_batch_last_error(const osbli_batch *b) { return b ? b->err : "null batch"; }
+
+void osbli_batch_destroy(osbli_batch *b) {
+    if (!b) return;
+    drop_graphs(b);
+    delete b;
+}
+
+}  // extern "C"

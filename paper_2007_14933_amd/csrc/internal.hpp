@@ -99,4 +99,28 @@ hipError_t launch_dt(const Grid &g, const Phys &ph, const Metrics &m, const doub
                      unsigned long long *slot, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int n, hipStream_t s);
 
+// ---- batched advance of many 2D problems (batch.hip) ----
+struct BProb {             // one problem, device resident
+    Grid g;
+    double *U, *dU, *R;
+    const double *invh[3];
+    uint8_t *mask[3];
+    int bc[3][2];
+    int64_t seg[3], nseg[3], wpl[3];   // sweep tiling per direction
+};
+
+struct BState {            // per-problem time state, device resident
+    double t, dt, tend;
+    unsigned long long smax;
+    int active, pad;
+};
+
+struct BatchTables {       // device prefix tables (P + 1 entries) and totals
+    int64_t *w[2], *pt, *f[2], *s[2];
+    int64_t tot_w[2], tot_pt, tot_f[2], tot_s[2];
+};
+
+hipError_t launch_batch_stage(const BProb *pr, BState *st, const BatchTables &T, int P, const Phys &ph, int stage,
+                              double cfl, int route, const uint16_t *w, float zcut, unsigned *flags, hipStream_t s);
+
 }  // namespace osbli

@@ -9,7 +9,7 @@
 // G_k = S_k . Fv, stored once per node.
 // Pass 2 (k_finish): per node, J sum_k D_k G_k added to the convective
 // residual, then either stored (residual call) or folded into the RK update.
-#include "internal.hpp"
+#include "point.hpp"
 
 namespace osbli {
 namespace {
@@ -60,10 +60,6 @@ __device__ __forceinline__ void phi_at(const double *__restrict__ U, int64_t e, 
     phi[ND] = ph.gamma * ph.M2 * p * ri;
 }
 
-__device__ __forceinline__ double viscosity(const Phys &ph, double T) {
-    if (!ph.sutherland) return 1.0;
-    return T * sqrt(T) * (1.0 + ph.Ts) / (T + ph.Ts);
-}
 
 template <int ND, bool GEN>
 __global__ void __launch_bounds__(256)
@@ -201,13 +197,8 @@ k_finish(const double *Racc, const double *__restrict__ G, double *Rout, Grid g,
 #pragma unroll
         for (int c = 0; c < NC; ++c) Rout[c * g.nint + ci] = R[c];
     } else {
-        const double A = rk_A(stage), B = rk_B(stage);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double du = (stage == 0 ? 0.0 : A * dU[c * g.nint + ci]) + dt * R[c];
-            dU[c * g.nint + ci] = du;
-            U[c * g.enpts + e0] += B * du;
-        }
+        for (int c = 0; c < NC; ++c) rk_point(stage, dt, R[c], dU + c * g.nint + ci, U + c * g.enpts + e0);
     }
 }
 
@@ -230,46 +221,7 @@ k_dt(const double *__restrict__ U, Grid g, Phys ph, Metrics m, unsigned long lon
     idx[1] = (int64_t)blockIdx.y * kBY + threadIdx.y;
     const bool inplane = idx[0] < g.n[0] && idx[1] < g.n[1];
     for (idx[2] = blockIdx.z; inplane && idx[2] < g.n[2]; idx[2] += gridDim.z) {
-        const int64_t e = ext_index(g, idx[0], idx[1], idx[2]);
-        const int64_t cs = g.enpts;
-        const double r = U[e], ri = 1.0 / r;
-        double u[3], ke = 0.0;
-#pragma unroll
-        for (int mm = 0; mm < ND; ++mm) {
-            u[mm] = U[e + (1 + mm) * cs] * ri;
-            ke += U[e + (1 + mm) * cs] * U[e + (1 + mm) * cs];
-        }
-        const double p = ph.gm1 * (U[e + (ND + 1) * cs] - 0.5 * ke * ri);
-        const double a = sqrt(ph.gamma * p * ri);
-        double nu = 0.0;
-        if (ph.viscous) {
-            const double T = ph.gamma * ph.M2 * p * ri;
-            nu = ph.nu_fac * viscosity(ph, T) * ri * ph.mu_re;
-        }
-        double conv = 0.0, diff = 0.0;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            double js, un;
-            if (!GEN) {
-                js = m.invh[d][idx[d]];
-                un = u[d];
-            } else {
-                double s2 = 0.0, us = 0.0;
-#pragma unroll
-                for (int c = 0; c < ND; ++c) {
-                    const double sm = m.S[(d * ND + c) * cs + e];
-                    s2 += sm * sm;
-                    us += u[c] * sm;
-                }
-                const double smag = sqrt(s2);
-                js = m.J[e] * smag;
-                un = us / smag;
-            }
-            conv += js * (fabs(un) + a);
-            diff += js * js;
-        }
-        double sn = conv + 2.0 * nu * diff;
-        if (!(sn >= 0.0)) sn = __builtin_inf();  // NaN state: force dt -> 0
+        double sn = dt_node<ND, GEN>(U, g, ph, m, idx);
         s = fmax(s, sn);
     }
     s = wave_max(s);
