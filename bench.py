@@ -66,6 +66,60 @@ def cpu_baseline(n):
             "sample": "one RK substage (residual + low-storage update) of TGV %d^3, FP64, %.1f s" % (n, el)}
 
 
+SWEEP_SOURCES = ("paper_2007_14933_amd/csrc/sweep.hpp", "paper_2007_14933_amd/csrc/charflux.hpp",
+                 "paper_2007_14933_amd/csrc/convective.hip", "paper_2007_14933_amd/csrc/internal.hpp")
+TRAFFIC_PROFILE = "profiles/tgv256_sweep_hbm_traffic.txt"
+
+
+def sweep_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel of known
+    size), or None when the sweep sources changed since it was taken."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != sweep_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_ceiling(nbytes=1 << 30, reps=5):
+    """Device-to-device copy of `nbytes` (read + write) as the achievable HBM
+    rate, GB/s."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def timed_run(prob, form, steps, warmup, cfl):
     """W warm-up steps, then K timed steps (dt reduction + 3 substages + BCs
     each) with the library's per-kernel event timing on."""
@@ -179,6 +233,7 @@ def sensor_form(cfl):
         res[name] = r
         del s
         torch.cuda.empty_cache()
+    res["plain_sensitivity_floor_rel_L1_rho"] = float("%.3e" % SN.sensitivity_floor(prob))
     res["workload"] = "shock-vortex 1024x512 seed 42, TENO5, CFL 0.5, to t=0.4; threshold %.3f" % thr
     return res
 
@@ -270,6 +325,7 @@ def main():
 
     n = args.n
     prob = inputs.tgv(n)
+    copy_gbs = copy_ceiling()
     npts = n ** 3
     wall, gpu_ms, prof = timed_run(prob, 0, args.steps, args.warmup, args.cfl)
     value = npts * 3 * args.steps / wall / 1e6
@@ -282,8 +338,12 @@ def main():
     avg_ms = sweep_ms / max(1, sweep_cnt)
     achieved = fl_launch / (avg_ms * 1e-3) / 1e12
     peak = cost.PEAK_FP64_VALU_TFLOPS
+    traffic = measured_traffic()
+    sweep_alg_bytes = npts * sum(cost.sweep_bytes_per_point(3, d == 0) for d in range(3)) / 3.0
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "traffic_vs_algorithmic": (round(traffic / sweep_alg_bytes, 3) if traffic else None),
+                "algorithmic_bytes_per_launch": sweep_alg_bytes,
                 "kernel": "k_sweep<3,d,TENO5> (average over x, y, z)", "avg_ms": round(avg_ms, 4),
                 "flops_per_launch": fl_launch}
     breakdown = {k: {"launch_groups": c, "avg_ms": round(ms / c, 4) if c else 0.0} for k, (c, ms) in prof.items()}
@@ -307,6 +367,7 @@ def main():
                    "parallelism": "single GPU"},
         "hbm_compulsory_frac": round(npts * 3 * args.steps * cost.compulsory_bytes_per_point(3) / wall / 1e9
                                      / cost.PEAK_HBM_GBS, 4),
+        "copy_ceiling_GBs": round(copy_gbs, 1),
         "roofline": roofline,
         "kernels": breakdown,
     }

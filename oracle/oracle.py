@@ -291,22 +291,3 @@ def features(prob, d, Uk, S):
     _load().orc_features(C.byref(params(prob)), int(d), _dp(Uk), _dp(S3), _dp(f), _ip(lab))
     return f, int(lab[0])
 
-
-def stencils(prob, U, d):
-    """All interface stencils of direction d of a ghosted state: array
-    (n_interfaces, 6, nc) ordered [other dims..., i = -1 .. N-1] with the
-    sweep direction fastest, plus the half-node area vectors (from the
-    oracle's metrics of prob)."""
-    nd = prob.ndim
-    Ui = np.moveaxis(U, 0, -1)               # (ez, ey, ex, nc)
-    ax = 2 - d                               # array axis of direction d
-    N = int(prob.n[d])
-    core = [slice(3, -3) if e < nd else slice(None) for e in (2, 1, 0)]
-    out = []
-    for k in range(6):
-        sl = list(core)
-        sl[ax] = slice(1 + k, 1 + k + N + 1)   # node p-2+k for p = -1..N-1
-        out.append(Ui[tuple(sl)])
-    st = np.stack(out, axis=-2)              # (..., N+1, 6, nc) with d axis in place
-    st = np.moveaxis(st, ax, -3)             # direction d next to the stencil axis
-    return st.reshape(-1, 6, nd + 2)

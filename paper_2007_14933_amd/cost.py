@@ -47,3 +47,11 @@ def interfaces_per_sweep(n, nd: int, d: int) -> int:
 
 def compulsory_bytes_per_point(nd: int) -> int:
     return 4 * (nd + 2) * 8
+
+
+def sweep_bytes_per_point(nd: int, first: bool) -> int:
+    """Unavoidable HBM bytes of one convective sweep per point: read U, write
+    the residual accumulator (first direction) or read and write it (later
+    directions)."""
+    nc = nd + 2
+    return nc * 8 * (2 if first else 3)

@@ -173,15 +173,32 @@ def pick_threshold(z, y, max_false_smooth=1e-3):
     return thr, recall
 
 
-def _plain_density(prob, cache):
-    key = prob.name
+def _plain_density(prob, cache, perturb=0.0):
+    """Density at the end time of the plain solver; with perturb > 0 the
+    initial state is multiplied by 1 + perturb * N(0, 1) (seeded) first."""
+    key = (prob.name, perturb)
     if key not in cache:
+        if perturb:
+            rng = np.random.default_rng(12345)
+            prob = prob.with_(U0=prob.U0 * (1.0 + perturb * rng.standard_normal(prob.U0.shape)))
         sp = Solver(prob)
         sp.run(10 ** 9, cfl=prob.cfl, t_end=prob.t_end)
         sp.check()
         cache[key] = sp.interior()[0]
         del sp
     return cache[key]
+
+
+def _rel_l1(a, b):
+    return float(np.abs(a - b).mean() / np.abs(b).mean())
+
+
+def sensitivity_floor(prob, cache=None, perturb=1e-14):
+    """How far the plain solution itself moves at the end time when the
+    initial state is perturbed at rounding level: the smallest difference
+    against plain that any change which is not bit-exact can be held to."""
+    cache = {} if cache is None else cache
+    return _rel_l1(_plain_density(prob, cache, perturb), _plain_density(prob, cache))
 
 
 def routed_error(bits, threshold, probs, dilate=1, plain_cache=None):
@@ -197,29 +214,37 @@ def routed_error(bits, threshold, probs, dilate=1, plain_cache=None):
         sr.check()
         a = sr.interior()[0]
         sm, tot = sr.sensor_stats()
-        out.append((float(np.abs(a - b).mean() / np.abs(b).mean()), sm / tot))
+        out.append((_rel_l1(a, b), sm / tot))
         del sr
     return out
 
 
-THRESHOLDS = (0.2, 0.35, 0.5, 0.65, 0.8, 0.9, 0.95, 0.98, 0.995)
+THRESHOLDS = (0.05, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.5, 0.65, 0.8, 0.9, 0.95, 0.98)
 
 
 def pick_threshold_by_error(bits, probs, target=1e-4, grid=THRESHOLDS, log=print):
-    """Smallest routing threshold whose routed runs of the held-out problems
-    all keep the relative L1 density error against the plain form within
-    half the target (the form's accuracy bar)."""
+    """Smallest routing threshold (most interfaces routed cheap) whose routed
+    runs of the held-out problems each keep the relative L1 density error
+    against the plain form within half the target, or within twice that
+    problem's own rounding sensitivity where that is larger (a problem whose
+    plain solution moves by 5e-5 under a 1e-14 perturbation cannot certify
+    a smaller difference)."""
     cache = {}
+    floors = [sensitivity_floor(p, cache) for p in probs]
+    allow = [max(0.5 * target, 2.0 * f) for f in floors]
+    if log:
+        log("[sensor] held-out sensitivity floors %s -> allowed %s" % (
+            ["%.1e" % f for f in floors], ["%.1e" % a for a in allow]))
     res = []
     for thr in grid:
         res = routed_error(bits, thr, probs, plain_cache=cache)
-        worst = max(e for e, _ in res)
+        ok = all(e <= a for (e, _), a in zip(res, allow))
         if log:
-            log("[sensor] threshold %.3f: worst rel L1(rho) %.2e, smooth fractions %s" % (
-                thr, worst, ["%.2f" % f for _, f in res]))
-        if worst <= 0.5 * target:
-            return thr, res
-    return grid[-1], res
+            log("[sensor] threshold %.3f: rel L1(rho) %s, smooth fractions %s%s" % (
+                thr, ["%.2e" % e for e, _ in res], ["%.2f" % f for _, f in res], " -> accepted" if ok else ""))
+        if ok:
+            return thr, res, floors
+    return grid[-1], res, floors
 
 
 HELDOUT_SEEDS = (1000, 1001, 1002)
@@ -254,10 +279,10 @@ def train_default(nprob=24, N=256, epochs=6, log=print, seed=100, heldout=(1024,
     if log:
         log("[sensor] validation accuracy at 0.5: %.4f, smooth recall at 0.1%% false-smooth %.3f" % (acc, rec))
     held = heldout_problems(*heldout)
-    thr, res = pick_threshold_by_error(tr.weights_bits(), held, log=log)
+    thr, res, floors = pick_threshold_by_error(tr.weights_bits(), held, log=log)
     meta = {"samples": len(y), "val_samples": len(yv), "val_smooth_recall_at_0.1pct": rec,
             "val_acc_at_half": acc, "heldout_rel_L1_rho": max(e for e, _ in res),
-            "heldout_smooth_fraction": min(f for _, f in res), "nprob": nprob, "N": N, "seed": seed,
+            "heldout_smooth_fraction": min(f for _, f in res), "heldout_floors": max(floors), "nprob": nprob, "N": N, "seed": seed,
             "heldout": "shock_vortex %dx%d seeds %s t_end 0.4" % (heldout[0], heldout[1], list(HELDOUT_SEEDS))}
     return tr, thr, meta
 

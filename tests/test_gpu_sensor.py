@@ -196,7 +196,7 @@ def test_trained_sensor_error_and_gain():
     acc = float(((zv >= 0) == (yv == 1)).float().mean().item())
     say("   samples %d, held-out accuracy %.4f, smooth recall at 0.1%% false-smooth %.3f" % (len(y), acc, rec))
     assert acc > 0.6  # balanced classes: well above chance
-    thr, _ = SN.pick_threshold_by_error(tr.weights_bits(), SN.heldout_problems(256, 128, (1000, 1001)), log=say)
+    thr, _, _ = SN.pick_threshold_by_error(tr.weights_bits(), SN.heldout_problems(256, 128, (1000, 1001)), log=say)
     prob = I.shock_vortex(256, 128, seed=42)
     res = {}
     for name, kw in (("plain", {}), ("routed", {"sensor": 1})):
