@@ -120,12 +120,14 @@ def copy_ceiling(nbytes=1 << 30, reps=5):
     return gbs
 
 
-def timed_run(prob, form, steps, warmup, cfl):
+def timed_run(prob, form, steps, warmup, cfl, sensor=0, bits=None, thr=None, keep_rho=False):
     """W warm-up steps, then K timed steps (dt reduction + 3 substages + BCs
     each) with the library's per-kernel event timing on."""
     import torch
     from paper_2007_14933_amd.solver import Solver
-    s = Solver(prob, form=form)
+    s = Solver(prob, form=form, sensor=sensor)
+    if sensor:
+        s.set_sensor(bits, thr)
     stream = s.stream
     s.apply_bc()
     for _ in range(warmup):
@@ -146,9 +148,16 @@ def timed_run(prob, form, steps, warmup, cfl):
     prof = s.profile_read()
     s.profile(False)
     gpu_ms = ev0.elapsed_time(ev1)
+    extra = {}
+    if sensor:
+        sm, tot = s.sensor_stats()
+        extra["smooth_fraction_last"] = round(sm / tot, 4)
+    if keep_rho:
+        extra["rho"] = s.interior()[0]
+        extra["t"] = s.t
     del s
     torch.cuda.empty_cache()
-    return wall, gpu_ms, prof
+    return wall, gpu_ms, prof, extra
 
 
 def form_error(prob, form, steps, cfl):
@@ -177,6 +186,75 @@ def form_error(prob, form, steps, cfl):
         res["rel_L1_" + name] = float("%.3e" % (d.mean() / np.abs(b[c]).mean()))
         res["rel_Linf_" + name] = float("%.3e" % (d.max() / np.abs(b[c]).max()))
     res["steps"] = steps
+    return res
+
+
+def tgv_learned(prob, args, plain_value, plain_extra):
+    """The headline TGV with learned routing (FP64 and FP32 reconstruction):
+    same steps as the plain run; relative L1 of rho against the plain run's
+    final state."""
+    import numpy as np
+    from paper_2007_14933_amd import sensor as SN
+    if not os.path.exists(SN.DEFAULT_WEIGHTS):
+        return {"skipped": "no trained weights"}
+    bits, thr = SN.load()
+    npts = prob.npoints
+    ref = plain_extra["rho"]
+    res = {"threshold": thr}
+    for name, form in (("fp64_learned", 0), ("fp32_learned", 1)):
+        w, _, p, ex = timed_run(prob, form, args.steps, args.warmup, args.cfl, sensor=1, bits=bits, thr=thr,
+                                keep_rho=True)
+        v = npts * 3 * args.steps / w / 1e6
+        sw = sum(p["sweep_%s" % a][1] for a in "xyz") / max(1, sum(p["sweep_%s" % a][0] for a in "xyz"))
+        res[name] = {"value": round(v, 3), "speedup_vs_plain": round(v / plain_value, 3),
+                     "sweep_avg_ms": round(sw, 4),
+                     "sensor_ms_per_step": round(p["sensor"][1] / max(1, args.steps), 4),
+                     "smooth_fraction_last": ex["smooth_fraction_last"],
+                     "rel_L1_rho_vs_plain": float("%.3e" % (np.abs(ex["rho"] - ref).mean() / np.abs(ref).mean())),
+                     "t_diff_vs_plain": float("%.3e" % (ex["t"] - plain_extra["t"]))}
+    return res
+
+
+def wall_precision(cfl, steps=100):
+    """Supersonic wall-bounded flow 512 x 256 x 256 (tanh wall mesh): plain
+    FP64 and the precision form, `steps` steps each with the CFL time step of
+    the initial state held fixed (both forms reach the same time); relative
+    L1 / Linf of rho and rho E of the precision form against plain."""
+    import numpy as np
+    import torch
+    from paper_2007_14933_amd import inputs
+    from paper_2007_14933_amd.solver import Solver
+    prob = inputs.wall_flow()
+    npts = prob.npoints
+    outs, res, dt = [], {}, None
+    for name, form in (("plain_fp64", 0), ("fp32_recon", 1)):
+        s = Solver(prob, form=form)
+        s.apply_bc()
+        if dt is None:
+            dt = s.compute_dt(cfl)
+        s.step(dt)  # warm-up step (kernels loaded, caches warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps - 1):
+            s.step(dt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s.check()
+        res[name] = {"value": round(npts * 3 * (steps - 1) / wall / 1e6, 3),
+                     "ms_per_step": round(wall * 1e3 / (steps - 1), 3)}
+        outs.append(s.interior())
+        del s
+        torch.cuda.empty_cache()
+    a, b = outs[1], outs[0]
+    err = {}
+    for q, c in (("rho", 0), ("rhoE", prob.nc - 1)):
+        d = np.abs(a[c] - b[c])
+        err["rel_L1_" + q] = float("%.3e" % (d.mean() / np.abs(b[c]).mean()))
+        err["rel_Linf_" + q] = float("%.3e" % (d.max() / np.abs(b[c]).max()))
+    res["fp32_recon"]["speedup_vs_plain"] = round(res["fp32_recon"]["value"] / res["plain_fp64"]["value"], 3)
+    res["fp32_recon"]["error_vs_plain_after_%d_steps" % steps] = err
+    res["workload"] = ("wall-bounded Mach 2, 512x256x256 tanh mesh (beta 2.5), isothermal wall, Sutherland, "
+                       "TENO5 + viscous, dt %.4e fixed" % dt)
     return res
 
 
@@ -327,7 +405,7 @@ def main():
     prob = inputs.tgv(n)
     copy_gbs = copy_ceiling()
     npts = n ** 3
-    wall, gpu_ms, prof = timed_run(prob, 0, args.steps, args.warmup, args.cfl)
+    wall, gpu_ms, prof, plain_extra = timed_run(prob, 0, args.steps, args.warmup, args.cfl, keep_rho=not args.no_forms)
     value = npts * 3 * args.steps / wall / 1e6
 
     # dominant kernel: the convective sweeps (one launch per direction and substage)
@@ -372,14 +450,16 @@ def main():
         "kernels": breakdown,
     }
     if not args.no_forms:
-        wm, _, pm = timed_run(prob, 1, args.steps, args.warmup, args.cfl)
+        wm, _, pm, _ = timed_run(prob, 1, args.steps, args.warmup, args.cfl)
         vm = npts * 3 * args.steps / wm / 1e6
         sm = sum(pm["sweep_%s" % a][1] for a in "xyz") / max(1, sum(pm["sweep_%s" % a][0] for a in "xyz"))
         out["forms"] = {"mixed_fp32": {
             "value": round(vm, 3), "speedup_vs_fp64": round(vm / value, 3),
             "sweep_avg_ms": round(sm, 4),
             "error_vs_fp64": form_error(prob, 1, 10, args.cfl)}}
+        out["forms"]["tgv_learned"] = tgv_learned(prob, args, value, plain_extra)
         out["forms"]["learned_sensor"] = sensor_form(args.cfl)
+        out["forms"]["wall_precision"] = wall_precision(args.cfl)
     if not args.no_batch:
         out["batch"] = batch_form(args.batch_steps, args.warmup, args.cfl, not args.no_tune, args.batch_full)
     if not args.no_cpu_baseline:

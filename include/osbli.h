@@ -148,6 +148,11 @@ int osbli_compute_dt(osbli_ctx *ctx, const double *U, double cfl, double *dt_out
  * the flag. */
 int osbli_check(osbli_ctx *ctx);
 
+/* Launch shape of the convective sweeps (not part of the method; results do
+ * not depend on it): seg[d] nodes per wave segment along direction d, 0 for
+ * the default rule (about 2^18 lanes per sweep, at least 8 nodes). */
+int osbli_set_sweep_segments(osbli_ctx *ctx, const int64_t *seg);
+
 /* Last error message of the context (never NULL). */
 const char *osbli_last_error(const osbli_ctx *ctx);
 

@@ -68,6 +68,7 @@ _SIGS = {
     "osbli_mlp_grad": (C.c_int, [_VP, _VP, C.c_int64, _VP, C.c_float, _VP, _VP, _VP, C.c_size_t, _VP]),
     "osbli_mlp_adam": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _VP]),
     "osbli_mlp_forward": (C.c_int, [_VP, C.c_int64, _VP, _VP, C.c_int, _VP]),
+    "osbli_set_sweep_segments": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "osbli_batch_workspace_bytes": (C.c_size_t, [C.c_int]),
     "osbli_batch_create": (C.c_int, [C.POINTER(_VP), C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP), _DP,
                                      C.c_double, _VP, C.c_size_t, _VP]),

@@ -38,6 +38,7 @@ struct osbli_ctx {
     int sensor_ready;      // weights set
     int sensor_every;      // refresh the routing masks at every substage (else at stage 0)
     float zcut;            // logit of the routing threshold
+    int64_t seg[3];        // sweep segment lengths (0: the default rule)
     hipStream_t last;
     int device;
     char err[320];
@@ -237,7 +238,8 @@ hipError_t convective_all(osbli_ctx *c, const double *U, double *R, hipStream_t 
     const bool route = c->p.sensor && c->sensor_ready;
     for (int d = 0; d < c->g.nd; ++d) {
         Timed t(c, OSBLI_K_SWEEP_X + d, s);
-        hipError_t e = launch_convective(c->g, c->ph, c->m, U, R, c->flags, d, d == 0, route ? c->mask[d] : nullptr, s);
+        hipError_t e = launch_convective(c->g, c->ph, c->m, U, R, c->flags, d, d == 0, route ? c->mask[d] : nullptr,
+                                         c->seg[d], s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -382,6 +384,15 @@ int osbli_rk_substep(osbli_ctx *c, int stage, double dt, double *U, double *dU, 
     {
         Timed t(c, OSBLI_K_FINISH, s);
         HIP_TRY(c, launch_finish(c->g, c->ph, c->m, c->Racc, c->G, nullptr, stage, dt, U, dU, 1, s));
+    }
+    return OSBLI_OK;
+}
+
+int osbli_set_sweep_segments(osbli_ctx *c, const int64_t *seg) {
+    if (!c || !seg) return set_err(c, OSBLI_EINVAL, "null argument");
+    for (int d = 0; d < 3; ++d) {
+        if (seg[d] < 0) return set_err(c, OSBLI_EINVAL, "segment length must be >= 0");
+        c->seg[d] = seg[d];
     }
     return OSBLI_OK;
 }
@@ -590,15 +601,10 @@ int bset_err(osbli_batch *b, int code, const char *fmt, ...) {
 
 size_t batch_table_bytes(int P) { return align256(sizeof(int64_t) * 7 * (size_t)(P + 1)); }
 
-// default segment length of a sweep (same rule as the single-grid launch)
+// default segment length of a sweep (the single-grid rule)
 int64_t default_seg(const Grid &g, int d) {
     const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
-    const int64_t lines = g.n[o1] * g.n[o2], N = g.n[d];
-    const int64_t target = int64_t(1) << 18;
-    int64_t seg = (N * lines + target - 1) / target;
-    if (seg < 8) seg = 8;
-    if (seg > N) seg = N;
-    return seg;
+    return default_segment(g.n[d], g.n[o1] * g.n[o2]);
 }
 
 // host prefix tables -> device; totals into T

@@ -21,14 +21,12 @@ namespace {
 using namespace cf;
 template <int ND, int DIR, int SCHEME, bool GEN, bool MIX, bool ROUTE>
 hipError_t launch_one(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
-                      unsigned *flags, int first, const uint8_t *mask, hipStream_t s) {
+                      unsigned *flags, int first, const uint8_t *mask, int64_t seg_req, hipStream_t s) {
     constexpr int O1 = DIR == 0 ? 1 : 0;
     constexpr int O2 = DIR == 2 ? 1 : 2;
     const int64_t lines = g.n[O1] * g.n[O2];
     const int64_t N = g.n[DIR];
-    const int64_t target = int64_t(1) << 18;  // threads in flight to aim for
-    int64_t seg = (N * lines + target - 1) / target;
-    if (seg < 8) seg = 8;
+    int64_t seg = seg_req > 0 ? seg_req : default_segment(N, lines);
     if (seg > N) seg = N;
     const int64_t nseg = (N + seg - 1) / seg;
     const int64_t waves = ((lines + 63) / 64) * nseg;
@@ -41,55 +39,55 @@ hipError_t launch_one(const Grid &g, const Phys &ph, const Metrics &m, const dou
 
 template <int ND, int SCHEME, bool GEN, bool MIX, bool ROUTE>
 hipError_t launch_dir_r(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
-                        unsigned *flags, int dir, int first, const uint8_t *mask, hipStream_t s) {
-    if (dir == 0) return launch_one<ND, 0, SCHEME, GEN, MIX, ROUTE>(g, ph, m, U, R, flags, first, mask, s);
+                        unsigned *flags, int dir, int first, const uint8_t *mask, int64_t sq, hipStream_t s) {
+    if (dir == 0) return launch_one<ND, 0, SCHEME, GEN, MIX, ROUTE>(g, ph, m, U, R, flags, first, mask, sq, s);
     if (dir == 1)
-        return launch_one<ND, (ND >= 2 ? 1 : 0), SCHEME, GEN, MIX, ROUTE>(g, ph, m, U, R, flags, first, mask, s);
-    return launch_one<ND, (ND >= 3 ? 2 : 0), SCHEME, GEN, MIX, ROUTE>(g, ph, m, U, R, flags, first, mask, s);
+        return launch_one<ND, (ND >= 2 ? 1 : 0), SCHEME, GEN, MIX, ROUTE>(g, ph, m, U, R, flags, first, mask, sq, s);
+    return launch_one<ND, (ND >= 3 ? 2 : 0), SCHEME, GEN, MIX, ROUTE>(g, ph, m, U, R, flags, first, mask, sq, s);
 }
 
 template <int ND, int SCHEME, bool GEN, bool MIX>
 hipError_t launch_dir_f(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
-                        unsigned *flags, int dir, int first, const uint8_t *mask, hipStream_t s) {
+                        unsigned *flags, int dir, int first, const uint8_t *mask, int64_t sq, hipStream_t s) {
     // routing only on separable meshes with TENO5 (validated at set-up)
     if (mask && !GEN && SCHEME == OSBLI_TENO5)
         return launch_dir_r<ND, SCHEME, GEN, MIX, (!GEN && SCHEME == OSBLI_TENO5)>(g, ph, m, U, R, flags, dir, first,
-                                                                               mask, s);
-    return launch_dir_r<ND, SCHEME, GEN, MIX, false>(g, ph, m, U, R, flags, dir, first, nullptr, s);
+                                                                               mask, sq, s);
+    return launch_dir_r<ND, SCHEME, GEN, MIX, false>(g, ph, m, U, R, flags, dir, first, nullptr, sq, s);
 }
 
 template <int ND, int SCHEME, bool GEN>
 hipError_t launch_dir(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
-                      unsigned *flags, int dir, int first, const uint8_t *mask, hipStream_t s) {
-    if (ph.mixed) return launch_dir_f<ND, SCHEME, GEN, true>(g, ph, m, U, R, flags, dir, first, mask, s);
-    return launch_dir_f<ND, SCHEME, GEN, false>(g, ph, m, U, R, flags, dir, first, mask, s);
+                      unsigned *flags, int dir, int first, const uint8_t *mask, int64_t sq, hipStream_t s) {
+    if (ph.mixed) return launch_dir_f<ND, SCHEME, GEN, true>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
+    return launch_dir_f<ND, SCHEME, GEN, false>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
 }
 
 template <int ND, int SCHEME>
 hipError_t launch_mesh(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
-                       unsigned *flags, int dir, int first, const uint8_t *mask, hipStream_t s) {
+                       unsigned *flags, int dir, int first, const uint8_t *mask, int64_t sq, hipStream_t s) {
     if (ND >= 2 && m.general)
-        return launch_dir<ND, SCHEME, (ND >= 2)>(g, ph, m, U, R, flags, dir, first, mask, s);
-    return launch_dir<ND, SCHEME, false>(g, ph, m, U, R, flags, dir, first, mask, s);
+        return launch_dir<ND, SCHEME, (ND >= 2)>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
+    return launch_dir<ND, SCHEME, false>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
 }
 
 template <int ND>
 hipError_t launch_scheme(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
-                         unsigned *flags, int dir, int first, const uint8_t *mask, hipStream_t s) {
+                         unsigned *flags, int dir, int first, const uint8_t *mask, int64_t sq, hipStream_t s) {
     if (ph.scheme == OSBLI_WENOZ5)
-        return launch_mesh<ND, OSBLI_WENOZ5>(g, ph, m, U, R, flags, dir, first, mask, s);
-    return launch_mesh<ND, OSBLI_TENO5>(g, ph, m, U, R, flags, dir, first, mask, s);
+        return launch_mesh<ND, OSBLI_WENOZ5>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
+    return launch_mesh<ND, OSBLI_TENO5>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
 }
 
 }  // namespace
 
 hipError_t launch_convective(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
-                             unsigned *flags, int dir, int first, const uint8_t *mask, hipStream_t s) {
+                             unsigned *flags, int dir, int first, const uint8_t *mask, int64_t sq, hipStream_t s) {
     if (dir < 0 || dir >= g.nd) return hipErrorInvalidValue;
     switch (g.nd) {
-        case 1: return launch_scheme<1>(g, ph, m, U, R, flags, dir, first, mask, s);
-        case 2: return launch_scheme<2>(g, ph, m, U, R, flags, dir, first, mask, s);
-        default: return launch_scheme<3>(g, ph, m, U, R, flags, dir, first, mask, s);
+        case 1: return launch_scheme<1>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
+        case 2: return launch_scheme<2>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
+        default: return launch_scheme<3>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
     }
 }
 

@@ -72,9 +72,19 @@ hipError_t launch_metrics_general(const Grid &g, const double *coords, double *s
 hipError_t launch_bc(const Grid &g, const Phys &ph, const osbli_params &p, double *U, hipStream_t s);
 // one convective sweep along dir; first != 0 stores R, otherwise accumulates;
 // mask (may be null): routing mask of the direction's interfaces
+// segment length (nodes per wave along the sweep) of the single-grid rule:
+// about 2^18 lanes per launch, at least 8 nodes per segment
+inline int64_t default_segment(int64_t N, int64_t lines) {
+    const int64_t target = int64_t(1) << 18;
+    int64_t seg = (N * lines + target - 1) / target;
+    if (seg < 8) seg = 8;
+    return seg < N ? seg : N;
+}
+
+// seg_req > 0 overrides the segment length of the sweep
 hipError_t launch_convective(const Grid &g, const Phys &ph, const Metrics &m, const double *U,
                              double *R, unsigned *flags, int dir, int first, const uint8_t *mask,
-                             hipStream_t s);
+                             int64_t seg_req, hipStream_t s);
 // learned sensor
 int64_t iface_count(const Grid &g, int d);
 hipError_t launch_labels(const Grid &g, const Phys &ph, const double *U, int d, float *feat, uint8_t *lab,

@@ -61,48 +61,51 @@ __device__ __forceinline__ void phi_at(const double *__restrict__ U, int64_t e, 
 }
 
 
-template <int ND, bool GEN>
-__global__ void __launch_bounds__(256)
-k_visc_flux(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys ph, Metrics m) {
+// D_kk (per unit index) of the node primitives at e0 (position p along kk),
+// from global loads: the interior operator on ghost copies for periodic
+// directions, the one-sided closures near non-periodic ends
+template <int ND>
+__device__ __forceinline__ void dk_global(const double *__restrict__ U, int64_t e0, int64_t cs, const Phys &ph,
+                                          const Grid &g, int kk, int64_t p, double (&D)[ND + 1]) {
     constexpr int NV = ND + 1;
-    int64_t idx[3];
-    if (!node_of_thread(g, idx)) return;
-    const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
-    const int64_t e0 = ext_index(g, idx[0], idx[1], idx[2]);
-    const int64_t cs = g.enpts;
-
-    double phi0[NV];
-    phi_at<ND>(U, e0, cs, ph, phi0);
-    double Dk[ND][NV];
+    const int64_t N = g.n[kk], st = g.es[kk];
+    const int64_t eline = e0 - p * st;
+    const bool per = g.periodic[kk] != 0;
+    // evaluate the five-point operator component-wise from one set of loads
+    if (per || (p >= 2 && p <= N - 3)) {
+        double fm2[NV], fm1[NV], fp1[NV], fp2[NV];
+        phi_at<ND>(U, e0 - 2 * st, cs, ph, fm2);
+        phi_at<ND>(U, e0 - st, cs, ph, fm1);
+        phi_at<ND>(U, e0 + st, cs, ph, fp1);
+        phi_at<ND>(U, e0 + 2 * st, cs, ph, fp2);
 #pragma unroll
-    for (int kk = 0; kk < ND; ++kk) {
-        const int64_t N = g.n[kk], p = idx[kk], st = g.es[kk];
-        const int64_t eline = e0 - p * st;
-        const bool per = g.periodic[kk] != 0;
+        for (int v = 0; v < NV; ++v) D[v] = (2.0 / 3.0) * (fp1[v] - fm1[v]) - (1.0 / 12.0) * (fp2[v] - fm2[v]);
+    } else {
+        // the five nodes at one end; p sits at window position 0, 1, 3 or 4
+        double f[5][NV];
+        const int64_t q0 = p < 2 ? 0 : N - 5;
+        const int r = (int)(p - q0);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Dk[kk][v] = 0.0;
-        // evaluate the five-point operator component-wise from one set of loads
-        if (per || (p >= 2 && p <= N - 3)) {
-            double fm2[NV], fm1[NV], fp1[NV], fp2[NV];
-            phi_at<ND>(U, e0 - 2 * st, cs, ph, fm2);
-            phi_at<ND>(U, e0 - st, cs, ph, fm1);
-            phi_at<ND>(U, e0 + st, cs, ph, fp1);
-            phi_at<ND>(U, e0 + 2 * st, cs, ph, fp2);
+        for (int k = 0; k < 5; ++k) phi_at<ND>(U, eline + (q0 + k) * st, cs, ph, f[k]);
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                Dk[kk][v] = (2.0 / 3.0) * (fp1[v] - fm1[v]) - (1.0 / 12.0) * (fp2[v] - fm2[v]);
-        } else {
-            double f[5][NV];
-            const int64_t q0 = p < 2 ? 0 : N - 5;
-#pragma unroll
-            for (int r = 0; r < 5; ++r) phi_at<ND>(U, eline + (q0 + r) * st, cs, ph, f[r]);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                auto at = [&](int64_t q) { return f[q - q0][v]; };
-                Dk[kk][v] = dline(at, p, N, false);
-            }
+        for (int v = 0; v < NV; ++v) {
+            const double f0 = f[0][v], f1 = f[1][v], f2 = f[2][v], f3 = f[3][v], f4 = f[4][v];
+            if (r == 0) D[v] = (-25.0 * f0 + 48.0 * f1 - 36.0 * f2 + 16.0 * f3 - 3.0 * f4) / 12.0;
+            else if (r == 1) D[v] = (-3.0 * f0 - 10.0 * f1 + 18.0 * f2 - 6.0 * f3 + f4) / 12.0;
+            else if (r == 3) D[v] = (-f0 + 6.0 * f1 - 18.0 * f2 + 10.0 * f3 + 3.0 * f4) / 12.0;
+            else D[v] = (3.0 * f0 - 16.0 * f1 + 36.0 * f2 - 48.0 * f3 + 25.0 * f4) / 12.0;
         }
     }
+}
+
+// gradients from D_k, stress tensor, heat flux and the stored contravariant
+// viscous fluxes G_k = S_k . Fv of one node
+template <int ND, bool GEN>
+__device__ __forceinline__ void visc_store(const double (&phi0)[ND + 1], const double (&Dk)[ND][ND + 1],
+                                           double *__restrict__ G, const Grid &g, const Phys &ph, const Metrics &m,
+                                           const int64_t (&idx)[3], int64_t ci, int64_t e0) {
+    constexpr int NV = ND + 1;
+    const int64_t cs = g.enpts;
     double grad[NV][ND];
     double Jc = 1.0;
     if (GEN) Jc = m.J[e0];
@@ -152,6 +155,105 @@ k_visc_flux(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys p
             }
             G[(kk * NV + v) * g.nint + ci] = s;
         }
+}
+
+template <int ND, bool GEN>
+__global__ void __launch_bounds__(256)
+k_visc_flux(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys ph, Metrics m) {
+    constexpr int NV = ND + 1;
+    int64_t idx[3];
+    if (!node_of_thread(g, idx)) return;
+    const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
+    const int64_t e0 = ext_index(g, idx[0], idx[1], idx[2]);
+    const int64_t cs = g.enpts;
+    double phi0[NV];
+    phi_at<ND>(U, e0, cs, ph, phi0);
+    double Dk[ND][NV];
+#pragma unroll
+    for (int kk = 0; kk < ND; ++kk) dk_global<ND>(U, e0, cs, ph, g, kk, idx[kk], Dk[kk]);
+    visc_store<ND, GEN>(phi0, Dk, G, g, ph, m, idx, ci, e0);
+}
+
+// 3D separable meshes: a block owns a kZX x kZY tile of (x, y) columns and
+// marches kZC planes along z.  The primitives of the current plane (tile plus
+// a two-node halo, read from U including ghost copies) sit in LDS for the x
+// and y derivatives; each column keeps its own z-2 .. z+2 primitives in
+// registers.  Nodes within two of a non-periodic end take that direction's
+// closure from global loads.  The arithmetic per node is that of k_visc_flux.
+constexpr int kZX = 64, kZY = 8, kZC = 32;
+constexpr int kHX = kZX + 4, kHY = kZY + 4;
+
+__global__ void __launch_bounds__(kZX * kZY, 4)
+k_visc_flux_zm(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys ph, Metrics m) {
+    constexpr int NV = 4;
+    __shared__ double tile[2][NV][kHY][kHX];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kZX + tx;
+    const int64_t x0 = (int64_t)blockIdx.x * kZX, y0 = (int64_t)blockIdx.y * kZY;
+    const int64_t x = x0 + tx, y = y0 + ty;
+    const int64_t Nx = g.n[0], Ny = g.n[1], Nz = g.n[2];
+    const int64_t z0 = (int64_t)blockIdx.z * kZC;
+    const int64_t z1 = z0 + kZC < Nz ? z0 + kZC : Nz;
+    const bool own = x < Nx && y < Ny;
+    const int64_t xc = x < Nx ? x : Nx - 1, yc = y < Ny ? y : Ny - 1;
+    const int64_t cs = g.enpts, sz = g.es[2];
+    const bool perx = g.periodic[0] != 0, pery = g.periodic[1] != 0, perz = g.periodic[2] != 0;
+    const bool intx = perx || (x >= 2 && x <= Nx - 3);
+    const bool inty = pery || (y >= 2 && y <= Ny - 3);
+    const int64_t ecol = ext_index(g, xc, yc, 0);
+
+    double w[5][NV];  // primitives of this column at z-2 .. z+2
+#pragma unroll
+    for (int k = 1; k < 5; ++k) phi_at<3>(U, ecol + (z0 - 3 + k) * sz, cs, ph, w[k]);
+
+    for (int64_t z = z0; z < z1; ++z) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) w[k][v] = w[k + 1][v];
+        phi_at<3>(U, ecol + (z + 2) * sz, cs, ph, w[4]);
+        const int b = (int)((z - z0) & 1);
+        for (int t = tid; t < kHX * kHY; t += kZX * kZY) {
+            const int cx = t % kHX, cy = t / kHX;
+            int64_t gx = x0 - 2 + cx, gy = y0 - 2 + cy;
+            gx = gx > Nx + 2 ? Nx + 2 : gx;
+            gy = gy > Ny + 2 ? Ny + 2 : gy;
+            double f[NV];
+            phi_at<3>(U, ext_index(g, gx, gy, z), cs, ph, f);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) tile[b][v][cy][cx] = f[v];
+        }
+        __syncthreads();
+        if (own) {
+            const int64_t idx[3] = {x, y, z};
+            const int64_t e0 = ecol + z * sz;
+            double Dk[3][NV];
+            const int cx = tx + 2, cy = ty + 2;
+            if (intx) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    Dk[0][v] = (2.0 / 3.0) * (tile[b][v][cy][cx + 1] - tile[b][v][cy][cx - 1]) -
+                               (1.0 / 12.0) * (tile[b][v][cy][cx + 2] - tile[b][v][cy][cx - 2]);
+            } else {
+                dk_global<3>(U, e0, cs, ph, g, 0, x, Dk[0]);
+            }
+            if (inty) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    Dk[1][v] = (2.0 / 3.0) * (tile[b][v][cy + 1][cx] - tile[b][v][cy - 1][cx]) -
+                               (1.0 / 12.0) * (tile[b][v][cy + 2][cx] - tile[b][v][cy - 2][cx]);
+            } else {
+                dk_global<3>(U, e0, cs, ph, g, 1, y, Dk[1]);
+            }
+            if (perz || (z >= 2 && z <= Nz - 3)) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    Dk[2][v] = (2.0 / 3.0) * (w[3][v] - w[1][v]) - (1.0 / 12.0) * (w[4][v] - w[0][v]);
+            } else {
+                dk_global<3>(U, e0, cs, ph, g, 2, z, Dk[2]);
+            }
+            visc_store<3, false>(w[2], Dk, G, g, ph, m, idx, int_index(g, x, y, z), e0);
+        }
+    }
 }
 
 // R = Racc (+ viscous divergence); mode 0 stores R, mode 1 applies the RK stage.
@@ -275,8 +377,13 @@ hipError_t launch_viscous_fluxes(const Grid &g, const Phys &ph, const Metrics &m
             else hipLaunchKernelGGL((k_visc_flux<2, false>), nb, bs, 0, s, U, G, g, ph, m);
             break;
         default:
-            if (gen) hipLaunchKernelGGL((k_visc_flux<3, true>), nb, bs, 0, s, U, G, g, ph, m);
-            else hipLaunchKernelGGL((k_visc_flux<3, false>), nb, bs, 0, s, U, G, g, ph, m);
+            if (gen) {
+                hipLaunchKernelGGL((k_visc_flux<3, true>), nb, bs, 0, s, U, G, g, ph, m);
+            } else {
+                const dim3 zb((unsigned)((g.n[0] + kZX - 1) / kZX), (unsigned)((g.n[1] + kZY - 1) / kZY),
+                              (unsigned)((g.n[2] + kZC - 1) / kZC));
+                hipLaunchKernelGGL(k_visc_flux_zm, zb, dim3(kZX, kZY), 0, s, U, G, g, ph, m);
+            }
     }
     return hipGetLastError();
 }

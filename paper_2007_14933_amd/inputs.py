@@ -215,12 +215,15 @@ def wall_flow(nx=512, ny=256, nz=256, L=(100.0, 20.0, 20.0), M=2.0, Re=750.0, Pr
     kz = rng.integers(-4, 5, size=(3, nmodes))
     ph = rng.uniform(0.0, 2.0 * math.pi, size=(3, nmodes))
     am = rng.uniform(0.5, 1.0, size=(3, nmodes))
-    X, Y, Z = _mesh((x, y, z), 3)
+    # A depends on (x, z) only: evaluate it on one plane, broadcast along y
+    X = x[None, None, :]
+    Z = z[:, None, None]
+    Y = np.broadcast_to(y[None, :, None], (nz, ny, nx))
     f = (Y / delta) ** 2 * np.exp(-(Y / delta) ** 2)
     fy = (2.0 * Y / delta ** 2) * (1.0 - (Y / delta) ** 2) * np.exp(-(Y / delta) ** 2)
-    A = [np.zeros_like(X) for _ in range(3)]
-    dAx = [np.zeros_like(X) for _ in range(3)]
-    dAz = [np.zeros_like(X) for _ in range(3)]
+    A = [np.zeros((nz, 1, nx)) for _ in range(3)]
+    dAx = [np.zeros((nz, 1, nx)) for _ in range(3)]
+    dAz = [np.zeros((nz, 1, nx)) for _ in range(3)]
     for c in range(3):
         for m in range(nmodes):
             ax = 2 * math.pi * kx[c, m] / L[0]

@@ -98,6 +98,11 @@ class Solver:
         B.check(self.lib.osbli_compute_dt(self.ctx, _ptr(self.U), float(cfl), C.byref(out), self._s()), self.ctx)
         return out.value
 
+    def set_sweep_segments(self, seg):
+        """Nodes per wave segment of each direction's sweep (0: default)."""
+        a = (C.c_int64 * 3)(*[int(v) for v in list(seg) + [0] * (3 - len(seg))])
+        B.check(self.lib.osbli_set_sweep_segments(self.ctx, a), self.ctx)
+
     def profile(self, enable=True):
         B.check(self.lib.osbli_profile_enable(self.ctx, int(enable)), self.ctx)
 
