@@ -1101,12 +1101,21 @@ void orc_cheap_flux(const orc_params *P, int d, const double *Uk, const double *
  *     1/4 (a-c)^2 of rho/rho_bar + p/p_bar + (u.t_s)/a_bar summed over the
  *     tangents, on the substencils {i-2..i}, {i-1..i+1}, {i..i+2},
  *     {i+1..i+3}, divided by their sum (+1e-20, so variations at rounding
- *     level read as a uniform state);
+ *     level read as a uniform state).  B is quadratic, so each variable's
+ *     indicator is evaluated on the unscaled values and multiplied by the
+ *     inverse square of its scale: 1/rho_bar^2, 1/p_bar^2 and
+ *     1/a_bar^2 = rho_bar / (gamma p_bar);
  *   f4..f6: jumps J = |rho_{k+1} - rho_k| / (rho_{k+1} + rho_k) over (i-1,i),
  *     (i,i+1), (i+1,i+2), log-normalised as log10(1 + 1e6 J)/6;  f7..f9: the
  *     same for p.
- * rho_bar, p_bar: means of nodes i, i+1; a_bar = sqrt(gamma p_bar / rho_bar).
+ * rho_bar, p_bar: means of nodes i, i+1.
  * Label: 1 iff every TENO stencil of every field and both splits is kept. */
+static double js3(const double *q, int m)
+{
+    const double a1 = q[m] - 2.0 * q[m + 1] + q[m + 2], a2 = q[m] - q[m + 2];
+    return (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
+}
+
 void orc_features(const orc_params *P, int d, const double *Uk, const double *S, double *feat, int *label)
 {
     const int nd = P->ndim, nc = nd + 2;
@@ -1119,32 +1128,26 @@ void orc_features(const orc_params *P, int d, const double *Uk, const double *S,
     prim_t w[6];
     for (int k = 0; k < 6; k++) to_prim(P, nd, Uk + k * nc, &w[k]);
     const double rb = 0.5 * (w[2].rho + w[3].rho), pb = 0.5 * (w[2].p + w[3].p);
-    const double ab = sqrt(P->gamma * pb / rb);
+    const double sr = 1.0 / (rb * rb), sp = 1.0 / (pb * pb), sv = rb / (P->gamma * pb);
     double r[6], q[6], vt[2][6];
     for (int k = 0; k < 6; k++) {
-        r[k] = w[k].rho / rb;
-        q[k] = w[k].p / pb;
+        r[k] = w[k].rho;
+        q[k] = w[k].p;
         for (int s = 0; s < nd - 1; s++) {
             double ut = 0.0;
             for (int m = 0; m < nd; m++) ut += w[k].u[m] * t[s][m];
-            vt[s][k] = ut / ab;
+            vt[s][k] = ut;
         }
     }
     double beta[4], sum = 0.0;
     for (int m = 0; m < 4; m++) {
-        double a1, a2, b;
-        a1 = r[m] - 2.0 * r[m + 1] + r[m + 2]; a2 = r[m] - r[m + 2];
-        b = (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
-        a1 = q[m] - 2.0 * q[m + 1] + q[m + 2]; a2 = q[m] - q[m + 2];
-        b += (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
-        for (int s = 0; s < nd - 1; s++) {
-            a1 = vt[s][m] - 2.0 * vt[s][m + 1] + vt[s][m + 2]; a2 = vt[s][m] - vt[s][m + 2];
-            b += (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
-        }
+        double b = sr * js3(r, m) + sp * js3(q, m);
+        for (int s = 0; s < nd - 1; s++) b += sv * js3(vt[s], m);
         beta[m] = b;
         sum += b;
     }
-    for (int m = 0; m < 4; m++) feat[m] = beta[m] / (sum + 1e-20);
+    const double inv = 1.0 / (sum + 1e-20);
+    for (int m = 0; m < 4; m++) feat[m] = beta[m] * inv;
     for (int m = 0; m < 3; m++) {
         double jr = fabs(w[m + 2].rho - w[m + 1].rho) / (w[m + 2].rho + w[m + 1].rho);
         double jp = fabs(w[m + 2].p - w[m + 1].p) / (w[m + 2].p + w[m + 1].p);

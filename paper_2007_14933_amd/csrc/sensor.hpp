@@ -22,14 +22,24 @@ __device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even
 }
 
 // ------------------------------------------------------------ features
+__device__ __forceinline__ double js3(const double (&q)[6], int m) {
+#pragma clang fp contract(off)
+    const double a1 = q[m] - 2.0 * q[m + 1] + q[m + 2], a2 = q[m] - q[m + 2];
+    return (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
+}
+
 // Sensor features of interface p+1/2 of a line (separable meshes: n = e_DIR,
 // tangents e_{DIR+1}, e_{DIR+2}); stencil points p-2..p+3 start at ext index
-// e0 with stride st.
+// e0 with stride st.  Features 0..3: three-point Jiang-Shu indicators of
+// rho/rho_bar + p/p_bar + u_t/a_bar on the four substencils (each variable's
+// indicator on unscaled values times the inverse square of its scale), over
+// their sum + 1e-20; 4..9: log10(1 + 1e6 J)/6 of the rho and p jumps
+// J = |q_{k+1} - q_k| / (q_{k+1} + q_k) over (p-1,p), (p,p+1), (p+1,p+2).
 template <int ND, int DIR>
 __device__ __forceinline__ void features(const double *__restrict__ U, int64_t e0, int64_t st, int64_t cs,
                                          const Phys &ph, float (&f)[kIn]) {
-    // same operation order as the FP64 definition and no FMA contraction, so
-    // every translation unit computes the same features
+    // the FP64 operations of the definition in its order, no FMA contraction,
+    // so that every translation unit computes the same features
 #pragma clang fp contract(off)
     double rho[6], p[6], vt[2][6];
 #pragma unroll
@@ -48,41 +58,26 @@ __device__ __forceinline__ void features(const double *__restrict__ U, int64_t e
         for (int s = 0; s < ND - 1; ++s) vt[s][k] = u[(DIR + 1 + s) % ND];
     }
     const double rb = 0.5 * (rho[2] + rho[3]), pb = 0.5 * (p[2] + p[3]);
-    const double ab = sqrt(ph.gamma * pb / rb);
-    double rn[6], qn[6], vn[2][6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        rn[k] = rho[k] / rb;
-        qn[k] = p[k] / pb;
-#pragma unroll
-        for (int s = 0; s < ND - 1; ++s) vn[s][k] = vt[s][k] / ab;
-    }
+    const double sr = 1.0 / (rb * rb), sp = 1.0 / (pb * pb), sv = rb / (ph.gamma * pb);
     double beta[4], sum = 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        double a1 = rn[m] - 2.0 * rn[m + 1] + rn[m + 2], a2 = rn[m] - rn[m + 2];
-        double b = (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
-        a1 = qn[m] - 2.0 * qn[m + 1] + qn[m + 2];
-        a2 = qn[m] - qn[m + 2];
-        b += (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
+        double b = sr * js3(rho, m) + sp * js3(p, m);
 #pragma unroll
-        for (int s = 0; s < ND - 1; ++s) {
-            a1 = vn[s][m] - 2.0 * vn[s][m + 1] + vn[s][m + 2];
-            a2 = vn[s][m] - vn[s][m + 2];
-            b += (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
-        }
+        for (int s = 0; s < ND - 1; ++s) b += sv * js3(vt[s], m);
         beta[m] = b;
         sum += b;
     }
+    const double inv = 1.0 / (sum + 1e-20);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) f[m] = (float)(beta[m] / (sum + 1e-20));
-    // jumps |q_{k+1} - q_k| / (q_{k+1} + q_k), log-normalised: log10(1 + 1e6 J) / 6
+    for (int m = 0; m < 4; ++m) f[m] = (float)(beta[m] * inv);
+    // jump logarithms in FP32 (inputs of a bfloat16 network)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         const double jr = fabs(rho[m + 2] - rho[m + 1]) / (rho[m + 2] + rho[m + 1]);
         const double jp = fabs(p[m + 2] - p[m + 1]) / (p[m + 2] + p[m + 1]);
-        f[4 + m] = (float)(log10(1.0 + 1e6 * jr) / 6.0);
-        f[7 + m] = (float)(log10(1.0 + 1e6 * jp) / 6.0);
+        f[4 + m] = log10f((float)(1.0 + 1e6 * jr)) * (1.0f / 6.0f);
+        f[7 + m] = log10f((float)(1.0 + 1e6 * jp)) * (1.0f / 6.0f);
     }
 }
 

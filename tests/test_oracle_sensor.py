@@ -75,6 +75,55 @@ def test_features_of_uniform_and_step_states():
     assert f[4] == 0 and f[6] == 0
 
 
+def _js_exact(q, m):
+    from fractions import Fraction as Fr
+    a1 = q[m] - 2 * q[m + 1] + q[m + 2]
+    a2 = q[m] - q[m + 2]
+    return Fr(13, 12) * a1 * a1 + Fr(1, 4) * a2 * a2
+
+
+def test_indicator_features_of_one_varying_variable():
+    """Only rho varies (u = 0, p uniform): the four indicator features are
+    B_m(rho) / sum B(rho) whatever the normalisation, B the three-point
+    Jiang-Shu indicator on substencils starting at i-2, i-1, i, i+1 (exact
+    rational reference).  With p proportional to rho (p = 7 rho) the two
+    variables' normalised indicators coincide, so the features are the same."""
+    from fractions import Fraction as Fr
+    prob = _prob(1)
+    rho = [Fr(1), Fr(11, 10), Fr(13, 10), Fr(8, 5), Fr(17, 10), Fr(19, 10)]
+    tot = sum(_js_exact(rho, m) for m in range(4))
+    want = np.array([float(_js_exact(rho, m) / tot) for m in range(4)])
+    r = np.array([float(v) for v in rho])
+    for p in (np.full(6, 2.0), 7.0 * r):
+        U = np.stack(I.conserved(1.4, r, [0 * r], p), axis=1)
+        f, _ = O.features(prob, 0, U, [1.0])
+        assert np.abs(f[:4] - want).max() < 1e-13, (f[:4], want)
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_features_invariant_under_velocity_pressure_scaling(nd):
+    """u -> lam u, p -> lam^2 p (rho fixed) scales the sound speed by lam, so
+    u_t / a_bar, p / p_bar and the jumps, hence all features, are unchanged;
+    a tangential velocity scaled by anything but a_bar would break this."""
+    prob = _prob(nd)
+    rng = np.random.default_rng(7 + nd)
+    x = 0.05 * np.arange(6)
+    rho = 1.0 + 0.2 * np.sin(x + 0.3)
+    vel = [0.4 * np.cos(3 * x + m) for m in range(nd)]
+    p = 1.0 + 0.3 * np.cos(2 * x)
+    S = np.eye(nd)[0]
+    f0, _ = O.features(prob, 0, np.stack(I.conserved(1.4, rho, vel, p), axis=1), S)
+    for lam in (0.1, 3.0):
+        f1, _ = O.features(prob, 0, np.stack(I.conserved(1.4, rho, [lam * v for v in vel], lam * lam * p),
+                                             axis=1), S)
+        assert np.abs(f1 - f0).max() < 1e-12
+    # the tangential velocity does enter: changing its profile moves the indicator features
+    vel2 = [vel[0]] + [v + 0.3 * x * x for v in vel[1:]]
+    f2, _ = O.features(prob, 0, np.stack(I.conserved(1.4, rho, vel2, p), axis=1), S)
+    assert np.abs(f2[:4] - f0[:4]).max() > 1e-3
+    del rng
+
+
 def test_bf16_rounding():
     x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -2.5, 3.0e-3])
     r = mlp.bf16_round(x)
