@@ -26,6 +26,15 @@ hipError_t launch_one(const Grid &g, const Phys &ph, const Metrics &m, const dou
     constexpr int O2 = DIR == 2 ? 1 : 2;
     const int64_t lines = g.n[O1] * g.n[O2];
     const int64_t N = g.n[DIR];
+    if (DIR == 0 && !GEN && seg_req <= 0 && N + 1 >= 64) {
+        // lanes along x: 63 new interfaces per wave
+        const int64_t totalJ = lines * (N + 1);
+        const int64_t waves = (totalJ - 2) / 63 + 1;
+        const int64_t nb = (waves + kWaves - 1) / kWaves;
+        hipLaunchKernelGGL((k_sweep_xl<ND, SCHEME, MIX, ROUTE>), dim3((unsigned)nb), dim3(64 * kWaves), 0, s, U, R,
+                           g, ph, m, totalJ, first, flags, mask);
+        return hipGetLastError();
+    }
     int64_t seg = seg_req > 0 ? seg_req : default_segment(N, lines);
     if (seg > N) seg = N;
     const int64_t nseg = (N + seg - 1) / seg;

@@ -266,5 +266,140 @@ k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, M
                                                  sbuf[DIR == 0 ? (threadIdx.x >> 6) : 0]);
 }
 
+// ---------------------------------------------------------------------------
+// x sweep on separable meshes with lanes along x.  The interfaces of all rows
+// are numbered J = row * (N + 1) + (q + 1) for the interface q + 1/2,
+// q = -1 .. N-1 (the interface-grid order of the routing masks).  A wave owns
+// 64 consecutive interfaces J0 .. J0 + 63, J0 = 63 w: consecutive waves share
+// one interface, so every node whose two interfaces lie in the same row is
+// written by exactly one wave, and the rows' points are read with contiguous
+// loads.  Lane l loads the point q_l + 3 of its row (the right end of its
+// stencil); the five points left of lane 0's stencil end, and the first five
+// points of a row that starts inside the wave, go to extra slots.  Needs
+// N + 1 >= 64 (at most one row start per wave).
+constexpr int kXlSlots = 64 + 10;
+
+template <int ND>
+struct XlLds {
+    double pt[ND + 5][kXlSlots];  // U[0..nc), ri, p, a of the staged points
+    double fl[ND + 2][64];        // interface fluxes of the wave
+};
+
+template <int ND, int SCHEME, bool MIX, bool ROUTE>
+__device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, double *__restrict__ R, const Grid &g,
+                                              const Phys &ph, const Metrics &m, int64_t J0, int64_t totalJ,
+                                              int first, unsigned *flags, const uint8_t *__restrict__ mask,
+                                              XlLds<ND> &sm) {
+    constexpr int NC = ND + 2;
+    constexpr int NT = ND - 1;
+    const int lane = threadIdx.x & 63;
+    const int64_t N = g.n[0], NI = N + 1, n1 = g.n[1];
+    const int64_t cs = g.enpts;
+    const int64_t J = J0 + lane;
+    const bool valid = J < totalJ;
+    const int64_t Jc = valid ? J : totalJ - 1;
+    const int64_t row = Jc / NI;
+    const int64_t q = Jc - row * NI - 1;
+    const int64_t rowb = ext_index(g, 0, row % n1, row / n1);
+    // wave-uniform: lane 0's row and interface, and the first lane of the next row
+    const int64_t row0 = J0 / NI, q0 = J0 - row0 * NI - 1;
+    const int Lnext = (int)(NI - (q0 + 1));  // lane index where row0 + 1 starts (>= 64: none)
+    bool bad = false;
+
+    auto stage = [&](int slot, int64_t base, int64_t pos) {
+        Pt<ND> w;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w.U[c] = U[base + pos + c * cs];
+        finish_point<ND>(ph, w, bad);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sm.pt[c][slot] = w.U[c];
+        sm.pt[NC][slot] = w.ri;
+        sm.pt[NC + 1][slot] = w.p;
+        sm.pt[NC + 2][slot] = w.a;
+    };
+    stage(lane, rowb, q + 3);
+    if (lane < 5) {
+        // points q0 - 2 .. q0 + 2 of lane 0's row
+        stage(64 + lane, ext_index(g, 0, row0 % n1, row0 / n1), q0 - 2 + lane);
+    } else if (lane < 10 && Lnext < 64) {
+        // points -3 .. 1 of the row starting inside the wave
+        const int64_t r1 = row0 + 1 < totalJ / NI ? row0 + 1 : row0;
+        stage(64 + lane, ext_index(g, 0, r1 % n1, r1 / n1), (int64_t)(lane - 5) - 3);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // stencil q - 2 .. q + 3 of this lane
+    const bool inrow0 = lane < Lnext;
+    Loc<ND> P[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int src = lane - 5 + k;
+        int slot;
+        if (inrow0) slot = src >= 0 ? src : 64 + lane + k;
+        else slot = src >= Lnext ? src : 69 + (lane - Lnext) + k;
+        P[k].r = sm.pt[0][slot];
+        P[k].mn = sm.pt[1][slot];
+        if (NT >= 1) P[k].mt[0] = sm.pt[1 + Axes<ND, 0>::T1][slot];
+        if (NT >= 2) P[k].mt[1] = sm.pt[1 + Axes<ND, 0>::T2][slot];
+        P[k].E = sm.pt[ND + 1][slot];
+        P[k].ri = sm.pt[NC][slot];
+        P[k].p = sm.pt[NC + 1][slot];
+        P[k].a = sm.pt[NC + 2][slot];
+    }
+    bool cheap = false;
+    if (ROUTE) {
+        // interfaces outside the line count as smooth
+        const bool mc = mask[Jc] != 0;
+        const bool mp = q - 1 < -1 ? true : mask[Jc - 1] != 0;
+        const bool mn = q + 1 > N - 1 ? true : mask[Jc + 1] != 0;
+        cheap = mc && (!ph.dilate || (mp && mn));
+    }
+    double Fr, Fn, Ft[2], FE;
+    if (cheap) {
+        if (MIX) cheap_flux_mixed<ND>(P, ph, Fr, Fn, Ft, FE);
+        else cheap_flux<ND>(P, ph, Fr, Fn, Ft, FE);
+    } else {
+        if (MIX) char_flux_mixed<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
+        else char_flux<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
+    }
+    double F[NC];
+    F[0] = Fr;
+    F[1] = Fn;
+    if (NT >= 1) F[1 + Axes<ND, 0>::T1] = Ft[0];
+    if (NT >= 2) F[1 + Axes<ND, 0>::T2] = Ft[1];
+    F[NC - 1] = FE;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sm.fl[c][lane] = F[c];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // node q: its left interface belongs to lane - 1 of the same row
+    if (valid && lane >= 1 && q >= 0 && lane != Lnext) {
+        const double sc = m.invh[0][q];
+        const int64_t oi = (row % n1) * g.is[1] + (row / n1) * g.is[2] + q;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double v = -sc * (F[c] - sm.fl[c][lane - 1]);
+            double *dst = R + c * g.nint + oi;
+            if (first) *dst = v;
+            else *dst += v;
+        }
+    }
+    if (bad) atomicOr(flags, kFlagNonPhys);
+}
+
+template <int ND, int SCHEME, bool MIX, bool ROUTE>
+__global__ void __launch_bounds__(64 * kWaves, 3)
+k_sweep_xl(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t totalJ,
+           int first, unsigned *flags, const uint8_t *__restrict__ mask) {
+    __shared__ XlLds<ND> sm[kWaves];
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t J0 = gw * 63;
+    if (J0 + 1 >= totalJ) return;  // wave-uniform: no node left
+    sweep_x_lanes<ND, SCHEME, MIX, ROUTE>(U, R, g, ph, m, J0, totalJ, first, flags, mask, sm[threadIdx.x >> 6]);
+}
+
 }  // namespace cf
 }  // namespace osbli
