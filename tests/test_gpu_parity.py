@@ -138,7 +138,7 @@ def test_minimum_sizes(n):
 
 X_SWEEP_CASES = {
     # rows of N + 1 >= 64 interfaces: lanes-along-x sweep; ragged last waves
-    "smooth3d_100x7x5_viscous": lambda: I.smooth_random(3, (100, 7, 5), seed=4, amp=0.2, Re=200.0),
+    "smooth3d_100x7x6_viscous": lambda: I.smooth_random(3, (100, 7, 6), seed=4, amp=0.2, Re=200.0),
     "riemann2d_131": lambda: I.riemann2d(131, 8),
     "sod_63_extrapolate": lambda: I.sod(63),
     "wall_70x9x6": lambda: I.wall_flow(70, 9, 6, L=(10.0, 6.0, 4.0)),
