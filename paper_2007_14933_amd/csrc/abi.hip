@@ -620,7 +620,10 @@ int upload_tables(osbli_batch *b, hipStream_t s) {
             q.nseg[d] = (q.g.n[d] + q.seg[d] - 1) / q.seg[d];
             q.wpl[d] = (q.g.n[o1] + 63) / 64;
         }
-        const int64_t nw0 = q.nseg[0] * q.wpl[0], nw1 = q.nseg[1] * q.wpl[1];
+        // x: lanes along x for rows of >= 64 interfaces (as the single-grid launch)
+        const int64_t totalJ = q.g.n[1] * (q.g.n[0] + 1);
+        const int64_t nw0 = q.xl ? (totalJ - 2) / 63 + 1 : q.nseg[0] * q.wpl[0];
+        const int64_t nw1 = q.nseg[1] * q.wpl[1];
         W0[p + 1] = W0[p] + nw0;
         W1[p + 1] = W1[p] + nw1;
         PT[p + 1] = PT[p] + (q.g.nint + 255) / 256;
@@ -720,6 +723,8 @@ int osbli_batch_create(osbli_batch **out, osbli_ctx *const *ctxs, int P, double 
         q.U = U[p];
         q.dU = dU[p];
         q.R = c->Racc;
+        q.xl = c->g.n[0] + 1 >= 64 ? 1 : 0;
+        q.pad = 0;
         for (int d = 0; d < 3; ++d) {
             q.invh[d] = c->m.invh[d];
             q.mask[d] = c->mask[d];

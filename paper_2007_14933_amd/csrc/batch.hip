@@ -103,7 +103,12 @@ template <int DIR, int SCHEME, bool MIX, bool ROUTE>
 __global__ void __launch_bounds__(256)
 k_b_sweep(const BProb *__restrict__ pr, const BState *__restrict__ st, const int64_t *__restrict__ off, int P,
           int64_t total, Phys ph, int first, unsigned *flags) {
-    __shared__ double sbuf[DIR == 0 ? kWaves : 1][4][kChunk][64];
+    // per wave: the marching sweep's staging chunk or the x-lanes sweep's points
+    union WaveLds {
+        SweepLds<2> chunk;
+        XlLds<2> xl;
+    };
+    __shared__ WaveLds sm[DIR == 0 ? kWaves : 1];
     const int wv = threadIdx.x >> 6;
     const int64_t nw = (int64_t)gridDim.x * kWaves;
     for (int64_t wt = (int64_t)blockIdx.x * kWaves + wv; wt < total; wt += nw) {
@@ -111,11 +116,17 @@ k_b_sweep(const BProb *__restrict__ pr, const BState *__restrict__ st, const int
         if (!st[p].active) continue;
         const BProb &b = pr[p];
         const int64_t local = wt - off[p];
+        const Metrics m = sep_metrics(b);
+        if (DIR == 0 && b.xl) {
+            // same mapping as the single-grid x sweep: 63 new interfaces per wave
+            sweep_x_lanes<2, SCHEME, MIX, ROUTE>(b.U, b.R, b.g, ph, m, local * 63, b.g.n[1] * (b.g.n[0] + 1), first,
+                                                 flags, ROUTE ? b.mask[0] : nullptr, sm[wv].xl);
+            continue;
+        }
         const int64_t sg = local / b.wpl[DIR];
         const int64_t line0 = (local - sg * b.wpl[DIR]) << 6;
-        const Metrics m = sep_metrics(b);
         sweep_wave<2, DIR, SCHEME, false, MIX, ROUTE>(b.U, b.R, b.g, ph, m, b.seg[DIR], sg, line0, first, flags,
-                                                      ROUTE ? b.mask[DIR] : nullptr, sbuf[DIR == 0 ? wv : 0]);
+                                                      ROUTE ? b.mask[DIR] : nullptr, sm[DIR == 0 ? wv : 0].chunk);
     }
 }
 

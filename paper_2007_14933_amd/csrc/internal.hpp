@@ -116,7 +116,8 @@ struct BProb {             // one problem, device resident
     const double *invh[3];
     uint8_t *mask[3];
     int bc[3][2];
-    int64_t seg[3], nseg[3], wpl[3];   // sweep tiling per direction
+    int xl, pad;                       // x sweep with lanes along x (rows of >= 64 interfaces)
+    int64_t seg[3], nseg[3], wpl[3];   // sweep tiling per direction (marching sweeps)
 };
 
 struct BState {            // per-problem time state, device resident
