@@ -169,7 +169,9 @@ def test_x_sweep_lanes_equal_marching(name, form):
     scale = flux_scale(prob, Uo, J, S)
     dab = np.abs(Ra - Rb).max(axis=tuple(range(1, Ra.ndim))) / scale
     say("   lanes vs marching |diff| / flux scale:", dab)
-    assert dab.max() <= TOL_ONE, dab
+    # the precision form rounds its deviations in FP32 (bar of its residual
+    # against the FP64 oracle: 2e-6 of the flux scale)
+    assert dab.max() <= (TOL_ONE if form == 0 else 2e-6), dab
     # and the lanes sweep agrees with the oracle's residual at the same state
     if form == 0:
         Ro = O.residual(prob, S, J, Uo)
