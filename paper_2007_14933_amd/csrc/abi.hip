@@ -599,7 +599,8 @@ int bset_err(osbli_batch *b, int code, const char *fmt, ...) {
             return bset_err((b), OSBLI_EDEVICE, "%s: %s", #call, hipGetErrorString(e__));              \
     } while (0)
 
-size_t batch_table_bytes(int P) { return align256(sizeof(int64_t) * 7 * (size_t)(P + 1)); }
+constexpr int kTables = 8;
+size_t batch_table_bytes(int P) { return align256(sizeof(int64_t) * kTables * (size_t)(P + 1)); }
 
 // default segment length of a sweep (the single-grid rule)
 int64_t default_seg(const Grid &g, int d) {
@@ -610,9 +611,9 @@ int64_t default_seg(const Grid &g, int d) {
 // host prefix tables -> device; totals into T
 int upload_tables(osbli_batch *b, hipStream_t s) {
     const int P = b->P;
-    std::vector<int64_t> h(7 * (size_t)(P + 1), 0);
+    std::vector<int64_t> h(kTables * (size_t)(P + 1), 0);
     int64_t *W0 = &h[0], *W1 = &h[(P + 1)], *PT = &h[2 * (P + 1)], *F0 = &h[3 * (P + 1)], *F1 = &h[4 * (P + 1)],
-            *S0 = &h[5 * (P + 1)], *S1 = &h[6 * (P + 1)];
+            *S0 = &h[5 * (P + 1)], *S1 = &h[6 * (P + 1)], *WX = &h[7 * (P + 1)];
     for (int p = 0; p < P; ++p) {
         BProb &q = b->hp[p];
         for (int d = 0; d < 2; ++d) {
@@ -622,8 +623,10 @@ int upload_tables(osbli_batch *b, hipStream_t s) {
         }
         // x: lanes along x for rows of >= 64 interfaces (as the single-grid launch)
         const int64_t totalJ = q.g.n[1] * (q.g.n[0] + 1);
-        const int64_t nw0 = q.xl ? (totalJ - 2) / 63 + 1 : q.nseg[0] * q.wpl[0];
+        const int64_t nwx = q.xl ? (totalJ - 2) / 63 + 1 : 0;
+        const int64_t nw0 = q.xl ? 0 : q.nseg[0] * q.wpl[0];
         const int64_t nw1 = q.nseg[1] * q.wpl[1];
+        WX[p + 1] = WX[p] + nwx;
         W0[p + 1] = W0[p] + nw0;
         W1[p + 1] = W1[p] + nw1;
         PT[p + 1] = PT[p] + (q.g.nint + 255) / 256;
@@ -643,6 +646,8 @@ int upload_tables(osbli_batch *b, hipStream_t s) {
     T.f[1] = b->dtab + 4 * (P + 1);
     T.s[0] = b->dtab + 5 * (P + 1);
     T.s[1] = b->dtab + 6 * (P + 1);
+    T.wx = b->dtab + 7 * (P + 1);
+    T.tot_wx = WX[P];
     T.tot_w[0] = W0[P];
     T.tot_w[1] = W1[P];
     T.tot_pt = PT[P];

@@ -103,12 +103,29 @@ template <int DIR, int SCHEME, bool MIX, bool ROUTE>
 __global__ void __launch_bounds__(256)
 k_b_sweep(const BProb *__restrict__ pr, const BState *__restrict__ st, const int64_t *__restrict__ off, int P,
           int64_t total, Phys ph, int first, unsigned *flags) {
-    // per wave: the marching sweep's staging chunk or the x-lanes sweep's points
-    union WaveLds {
-        SweepLds<2> chunk;
-        XlLds<2> xl;
-    };
-    __shared__ WaveLds sm[DIR == 0 ? kWaves : 1];
+    __shared__ double sbuf[DIR == 0 ? kWaves : 1][4][kChunk][64];
+    const int wv = threadIdx.x >> 6;
+    const int64_t nw = (int64_t)gridDim.x * kWaves;
+    for (int64_t wt = (int64_t)blockIdx.x * kWaves + wv; wt < total; wt += nw) {
+        const int p = find_prob(off, P, wt);
+        if (!st[p].active) continue;
+        const BProb &b = pr[p];
+        const int64_t local = wt - off[p];
+        const int64_t sg = local / b.wpl[DIR];
+        const int64_t line0 = (local - sg * b.wpl[DIR]) << 6;
+        const Metrics m = sep_metrics(b);
+        sweep_wave<2, DIR, SCHEME, false, MIX, ROUTE>(b.U, b.R, b.g, ph, m, b.seg[DIR], sg, line0, first, flags,
+                                                      ROUTE ? b.mask[DIR] : nullptr, sbuf[DIR == 0 ? wv : 0]);
+    }
+}
+
+// x sweep of the problems with rows of >= 64 interfaces: lanes along x, the
+// mapping of the single-grid x sweep (63 new interfaces per wave)
+template <int SCHEME, bool MIX, bool ROUTE>
+__global__ void __launch_bounds__(256, 3)
+k_b_sweep_xl(const BProb *__restrict__ pr, const BState *__restrict__ st, const int64_t *__restrict__ off, int P,
+             int64_t total, Phys ph, int first, unsigned *flags) {
+    __shared__ XlLds<2> sm[kWaves];
     const int wv = threadIdx.x >> 6;
     const int64_t nw = (int64_t)gridDim.x * kWaves;
     for (int64_t wt = (int64_t)blockIdx.x * kWaves + wv; wt < total; wt += nw) {
@@ -117,16 +134,8 @@ k_b_sweep(const BProb *__restrict__ pr, const BState *__restrict__ st, const int
         const BProb &b = pr[p];
         const int64_t local = wt - off[p];
         const Metrics m = sep_metrics(b);
-        if (DIR == 0 && b.xl) {
-            // same mapping as the single-grid x sweep: 63 new interfaces per wave
-            sweep_x_lanes<2, SCHEME, MIX, ROUTE>(b.U, b.R, b.g, ph, m, local * 63, b.g.n[1] * (b.g.n[0] + 1), first,
-                                                 flags, ROUTE ? b.mask[0] : nullptr, sm[wv].xl);
-            continue;
-        }
-        const int64_t sg = local / b.wpl[DIR];
-        const int64_t line0 = (local - sg * b.wpl[DIR]) << 6;
-        sweep_wave<2, DIR, SCHEME, false, MIX, ROUTE>(b.U, b.R, b.g, ph, m, b.seg[DIR], sg, line0, first, flags,
-                                                      ROUTE ? b.mask[DIR] : nullptr, sm[DIR == 0 ? wv : 0].chunk);
+        sweep_x_lanes<2, SCHEME, MIX, ROUTE>(b.U, b.R, b.g, ph, m, local * 63, b.g.n[1] * (b.g.n[0] + 1), first, flags,
+                                             ROUTE ? b.mask[0] : nullptr, sm[wv]);
     }
 }
 
@@ -197,8 +206,12 @@ static unsigned grid_of(int64_t items, int64_t per_block, unsigned cap) {
 template <int SCHEME, bool MIX, bool ROUTE>
 static hipError_t b_sweeps(const BProb *pr, const BState *st, const BatchTables &T, int P, const Phys &ph,
                            unsigned *flags, hipStream_t s) {
-    hipLaunchKernelGGL((k_b_sweep<0, SCHEME, MIX, ROUTE>), dim3(grid_of(T.tot_w[0], kWaves, 1024)), dim3(256), 0, s,
-                       pr, st, T.w[0], P, T.tot_w[0], ph, 1, flags);
+    if (T.tot_wx > 0)
+        hipLaunchKernelGGL((k_b_sweep_xl<SCHEME, MIX, ROUTE>), dim3(grid_of(T.tot_wx, kWaves, 2048)), dim3(256), 0, s,
+                           pr, st, T.wx, P, T.tot_wx, ph, 1, flags);
+    if (T.tot_w[0] > 0)
+        hipLaunchKernelGGL((k_b_sweep<0, SCHEME, MIX, ROUTE>), dim3(grid_of(T.tot_w[0], kWaves, 1024)), dim3(256), 0,
+                           s, pr, st, T.w[0], P, T.tot_w[0], ph, 1, flags);
     hipLaunchKernelGGL((k_b_sweep<1, SCHEME, MIX, ROUTE>), dim3(grid_of(T.tot_w[1], kWaves, 1024)), dim3(256), 0, s,
                        pr, st, T.w[1], P, T.tot_w[1], ph, 0, flags);
     return hipGetLastError();

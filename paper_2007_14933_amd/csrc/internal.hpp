@@ -127,8 +127,8 @@ struct BState {            // per-problem time state, device resident
 };
 
 struct BatchTables {       // device prefix tables (P + 1 entries) and totals
-    int64_t *w[2], *pt, *f[2], *s[2];
-    int64_t tot_w[2], tot_pt, tot_f[2], tot_s[2];
+    int64_t *w[2], *wx, *pt, *f[2], *s[2];    // wx: x-lanes sweep waves, w[0]: marching x sweep waves
+    int64_t tot_w[2], tot_wx, tot_pt, tot_f[2], tot_s[2];
 };
 
 hipError_t launch_batch_stage(const BProb *pr, BState *st, const BatchTables &T, int P, const Phys &ph, int stage,

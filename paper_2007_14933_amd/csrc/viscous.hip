@@ -194,9 +194,7 @@ k_visc_flux_zm(const double *__restrict__ U, double *__restrict__ G, Grid g, Phy
     const int64_t z0 = (int64_t)blockIdx.z * kZC;
     const int64_t z1 = z0 + kZC < Nz ? z0 + kZC : Nz;
     const bool own = x < Nx && y < Ny;
-    // column of this thread: its node, or (outside the grid) the nearest
-    // ghost column, whose values the tile needs for the last nodes' stencils
-    const int64_t xc = x < Nx + 2 ? x : Nx + 2, yc = y < Ny + 2 ? y : Ny + 2;
+    const int64_t xc = x < Nx ? x : Nx - 1, yc = y < Ny ? y : Ny - 1;
     const int64_t cs = g.enpts, sz = g.es[2];
     const bool perx = g.periodic[0] != 0, pery = g.periodic[1] != 0, perz = g.periodic[2] != 0;
     const bool intx = perx || (x >= 2 && x <= Nx - 3);
@@ -214,14 +212,8 @@ k_visc_flux_zm(const double *__restrict__ U, double *__restrict__ G, Grid g, Phy
             for (int v = 0; v < NV; ++v) w[k][v] = w[k + 1][v];
         phi_at<3>(U, ecol + (z + 2) * sz, cs, ph, w[4]);
         const int b = (int)((z - z0) & 1);
-        // the tile of plane z: this column's value from the window, the
-        // two-node halo (two rows above and below, two columns left and
-        // right) from U
-#pragma unroll
-        for (int v = 0; v < NV; ++v) tile[b][v][ty + 2][tx + 2] = w[2][v];
         for (int t = tid; t < kHX * kHY; t += kZX * kZY) {
             const int cx = t % kHX, cy = t / kHX;
-            if (cx >= 2 && cx < kZX + 2 && cy >= 2 && cy < kZY + 2) continue;  // a column's own cell
             int64_t gx = x0 - 2 + cx, gy = y0 - 2 + cy;
             gx = gx > Nx + 2 ? Nx + 2 : gx;
             gy = gy > Ny + 2 ? Ny + 2 : gy;
@@ -312,80 +304,6 @@ k_finish(const double *Racc, const double *__restrict__ G, double *Rout, Grid g,
     }
 }
 
-// 3D separable meshes with viscous terms, periodic in z, RK update: the same
-// pass by z-marching columns; each column keeps G_z of planes z-2 .. z+2 in
-// registers (the x and y neighbours are read directly and hit the caches).
-// Arithmetic per node as k_finish.
-__global__ void __launch_bounds__(kZX * kZY)
-k_finish_zm(const double *Racc, const double *__restrict__ G, Grid g, Phys ph, Metrics m, int stage, double dt,
-            double *__restrict__ U, double *__restrict__ dU) {
-    constexpr int NC = 5, NV = 4;
-    const int64_t x = (int64_t)blockIdx.x * kZX + threadIdx.x, y = (int64_t)blockIdx.y * kZY + threadIdx.y;
-    const int64_t Nx = g.n[0], Ny = g.n[1], Nz = g.n[2];
-    if (x >= Nx || y >= Ny) return;  // no barriers below
-    const int64_t z0 = (int64_t)blockIdx.z * kZC;
-    const int64_t z1 = z0 + kZC < Nz ? z0 + kZC : Nz;
-    const int64_t col = x + y * g.is[1], sz = g.is[2];
-    const double *Gz = G + (2 * NV) * g.nint + col;
-    auto zw = [&](int64_t q) -> int64_t { return q < 0 ? q + Nz : (q >= Nz ? q - Nz : q); };
-    double gz[5][NV];
-#pragma unroll
-    for (int k = 1; k < 5; ++k)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) gz[k][v] = Gz[v * g.nint + zw(z0 - 3 + k) * sz];
-    const int64_t idx01[2] = {x, y};
-#pragma unroll 1
-    for (int64_t z = z0; z < z1; ++z) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) gz[k][v] = gz[k + 1][v];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) gz[4][v] = Gz[v * g.nint + zw(z + 2) * sz];
-        const int64_t ci = col + z * sz;
-        double R[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) R[c] = Racc[c * g.nint + ci];
-        double acc[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-            const int64_t N = g.n[kk], p = idx01[kk], st = g.is[kk];
-            const int64_t line = ci - p * st;
-            const bool per = g.periodic[kk] != 0;
-            const double sc = m.invh[kk][p];
-            if (per || (p >= 2 && p <= N - 3)) {
-                auto wr = [&](int64_t q) { return (per ? (q < 0 ? q + N : (q >= N ? q - N : q)) : q) * st; };
-                const int64_t om2 = wr(p - 2), om1 = wr(p - 1), op1 = wr(p + 1), op2 = wr(p + 2);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const double *Gv = G + (kk * NV + v) * g.nint + line;
-                    acc[v] += sc * ((2.0 / 3.0) * (Gv[op1] - Gv[om1]) - (1.0 / 12.0) * (Gv[op2] - Gv[om2]));
-                }
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const double *Gv = G + (kk * NV + v) * g.nint + line;
-                    auto at = [&](int64_t q) { return Gv[q * st]; };
-                    acc[v] += sc * dline(at, p, N, false);
-                }
-            }
-        }
-        {
-            const double sc = m.invh[2][z];
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-                acc[v] += sc * ((2.0 / 3.0) * (gz[3][v] - gz[1][v]) - (1.0 / 12.0) * (gz[4][v] - gz[0][v]));
-        }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) R[1 + v] += 1.0 * acc[v];
-        const int64_t e0 = ext_index(g, x, y, z);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) rk_point(stage, dt, R[c], dU + c * g.nint + ci, U + c * g.enpts + e0);
-    }
-}
-
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -428,12 +346,6 @@ template <int ND, bool GEN>
 hipError_t finish_nd(const Grid &g, const Phys &ph, const Metrics &m, const double *Racc, const double *G,
                      double *Rout, int stage, double dt, double *U, double *dU, int mode, hipStream_t s) {
     const dim3 nb = node_grid(g), bs(kBX, kBY);
-    if (ND == 3 && !GEN && ph.viscous && g.periodic[2] && mode == 1) {
-        const dim3 zb((unsigned)((g.n[0] + kZX - 1) / kZX), (unsigned)((g.n[1] + kZY - 1) / kZY),
-                      (unsigned)((g.n[2] + kZC - 1) / kZC));
-        hipLaunchKernelGGL(k_finish_zm, zb, dim3(kZX, kZY), 0, s, Racc, G, g, ph, m, stage, dt, U, dU);
-        return hipGetLastError();
-    }
     if (ph.viscous) {
         if (mode == 0)
             hipLaunchKernelGGL((k_finish<ND, GEN, true, 0>), nb, bs, 0, s, Racc, G, Rout, g, ph, m,
