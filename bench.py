@@ -120,14 +120,14 @@ def copy_ceiling(nbytes=1 << 30, reps=5):
     return gbs
 
 
-def timed_run(prob, form, steps, warmup, cfl, sensor=0, bits=None, thr=None, keep_rho=False):
+def timed_run(prob, form, steps, warmup, cfl, sensor=0, bits=None, thr=None, keep_rho=False, dilate=1):
     """W warm-up steps, then K timed steps (dt reduction + 3 substages + BCs
     each) with the library's per-kernel event timing on."""
     import torch
     from paper_2007_14933_amd.solver import Solver
     s = Solver(prob, form=form, sensor=sensor)
     if sensor:
-        s.set_sensor(bits, thr)
+        s.set_sensor(bits, thr, dilate=dilate)
     stream = s.stream
     s.apply_bc()
     for _ in range(warmup):
@@ -198,12 +198,13 @@ def tgv_learned(prob, args, plain_value, plain_extra):
     if not os.path.exists(SN.DEFAULT_WEIGHTS):
         return {"skipped": "no trained weights"}
     bits, thr = SN.load()
+    dil = SN.load_dilate()
     npts = prob.npoints
     ref = plain_extra["rho"]
-    res = {"threshold": thr}
+    res = {"threshold": thr, "dilate": dil}
     for name, form in (("fp64_learned", 0), ("fp32_learned", 1)):
         w, _, p, ex = timed_run(prob, form, args.steps, args.warmup, args.cfl, sensor=1, bits=bits, thr=thr,
-                                keep_rho=True)
+                                keep_rho=True, dilate=dil)
         v = npts * 3 * args.steps / w / 1e6
         sw = sum(p["sweep_%s" % a][1] for a in "xyz") / max(1, sum(p["sweep_%s" % a][0] for a in "xyz"))
         res[name] = {"value": round(v, 3), "speedup_vs_plain": round(v / plain_value, 3),
@@ -272,6 +273,7 @@ def sensor_form(cfl):
     if not os.path.exists(SN.DEFAULT_WEIGHTS):
         return {"skipped": "no trained weights at %s" % os.path.relpath(SN.DEFAULT_WEIGHTS, ROOT)}
     bits, thr = SN.load()
+    dil = SN.load_dilate()
     prob = inputs.shock_vortex(1024, 512, seed=42)
     npts = prob.npoints
     res, ref = {}, None
@@ -279,7 +281,7 @@ def sensor_form(cfl):
                                ("fp32_plain", 1, 0)):
         s = Solver(prob, form=form, sensor=sensor)
         if sensor:
-            s.set_sensor(bits, thr)
+            s.set_sensor(bits, thr, dilate=dil)
         s.apply_bc()
         torch.cuda.synchronize()
         s.profile(True)
@@ -312,7 +314,7 @@ def sensor_form(cfl):
         del s
         torch.cuda.empty_cache()
     res["plain_sensitivity_floor_rel_L1_rho"] = float("%.3e" % SN.sensitivity_floor(prob))
-    res["workload"] = "shock-vortex 1024x512 seed 42, TENO5, CFL 0.5, to t=0.4; threshold %.3f" % thr
+    res["workload"] = "shock-vortex 1024x512 seed 42, TENO5, CFL 0.5, to t=0.4; threshold %.3f, dilate %d" % (thr, dil)
     return res
 
 
@@ -335,9 +337,10 @@ def batch_form(steps, warmup, cfl, tune, full):
     have_w = os.path.exists(SN.DEFAULT_WEIGHTS)
     forms = [("plain_fp64", 0, 0)] + ([("fp32_learned", 1, 1)] if have_w else [])
     bits, thr = SN.load() if have_w else (None, None)
+    dil = SN.load_dilate() if have_w else 1
     finals = {}
     for name, form, sensor in forms:
-        kw = dict(form=form, sensor=sensor, weights=bits, threshold=thr, cfl=cfl)
+        kw = dict(form=form, sensor=sensor, weights=bits, threshold=thr, cfl=cfl, dilate=dil)
         b = Batch(probs, **kw)
         tiles = b.tune(candidates=(16, 32, 64, 128, 256), nsteps=3) if tune else None
         b.step(warmup)

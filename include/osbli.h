@@ -181,10 +181,11 @@ void osbli_destroy(osbli_ctx *ctx);
  * --------------------------------------------------------------------- */
 
 /* Copy the routing network's weights (host array) into the context; route
- * an interface to the cheap flux when P(smooth) >= threshold (and, with
- * dilate, also at its two neighbours along the sweep).  Masks are refreshed
- * at stage 0 of each RK step (every substage with every_substage) and by
- * osbli_residual.  Synchronising. */
+ * an interface to the cheap flux when P(smooth) >= threshold there and at the
+ * `dilate` (0, 1 or 2) interfaces on each side along the sweep.  Masks are
+ * refreshed at stage 0 of each RK step (every substage with every_substage)
+ * and by osbli_residual.  OSBLI_EINVAL for n != 1441, a threshold outside
+ * (0, 1) or dilate outside 0..2.  Synchronising. */
 int osbli_sensor_set_weights(osbli_ctx *ctx, const uint16_t *w_bf16_host, int n, double threshold, int dilate,
                              int every_substage, void *stream);
 

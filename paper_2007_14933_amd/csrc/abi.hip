@@ -436,13 +436,14 @@ int osbli_sensor_set_weights(osbli_ctx *c, const uint16_t *w, int n, double thre
     if (!c || !w) return set_err(c, OSBLI_EINVAL, "null argument");
     if (!c->p.sensor) return set_err(c, OSBLI_EINVAL, "context created without sensor routing");
     if (n != 1441) return set_err(c, OSBLI_EINVAL, "expected 1441 bfloat16 weights, got %d", n);
+    if (dilate < 0 || dilate > 2) return set_err(c, OSBLI_EINVAL, "dilate must be 0, 1 or 2");
     if (!(threshold > 0.0 && threshold < 1.0)) return set_err(c, OSBLI_EINVAL, "threshold must lie in (0, 1)");
     hipStream_t s = as_stream(stream);
     c->last = s;
     HIP_TRY(c, hipMemcpyAsync(c->wts, w, sizeof(uint16_t) * 1441, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     c->zcut = (float)log(threshold / (1.0 - threshold));
-    c->ph.dilate = dilate != 0;
+    c->ph.dilate = dilate;
     c->sensor_every = every_substage != 0;
     c->sensor_ready = 1;
     return OSBLI_OK;

@@ -33,7 +33,7 @@ struct Phys {
     double nu_fac;     // max(4/3, gamma/Pr)
     int sutherland, scheme, roe, viscous;
     int mixed;         // FP32 reconstruction / flux evaluation on FP64 deviations
-    int dilate;        // routed form: cheap flux only if the neighbours along the line are smooth too
+    int dilate;        // routed form: cheap flux only if the interfaces within `dilate` along the line are smooth too
 };
 
 // Metric terms.  Separable meshes keep 1/h_d per direction (h_d = D_d x_d);

@@ -110,19 +110,19 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
         if (pp < -1 || pp > N - 1) return true;
         return mask[mbase + (pp + 1) * mst] != 0;
     };
-    bool mprev = true, mcur = true, mnext = true;
+    // masks of interfaces f-2 .. f+2 (f = the interface being evaluated)
+    bool mw[5] = {true, true, true, true, true};
     if (ROUTE) {
-        mprev = mload(p0 - 2);
-        mcur = mload(p0 - 1);
-        mnext = mload(p0);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) mw[k] = mload(p0 - 3 + k);
     }
 
     double Fp[NC];
     for (int64_t f = p0 - 1; f < p1; ++f) {
         if (ROUTE && f >= p0) {
-            mprev = mcur;
-            mcur = mnext;
-            mnext = mload(f + 1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) mw[k] = mw[k + 1];
+            mw[4] = mload(f + 2);
         }
         if (f >= p0) {
 #pragma unroll
@@ -203,7 +203,7 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
             }
         }
         double Fr, Fn, Ft[2], FE;
-        const bool cheap = ROUTE && mcur && (!ph.dilate || (mprev && mnext));
+        const bool cheap = ROUTE && mw[2] && (ph.dilate < 1 || (mw[1] && mw[3])) && (ph.dilate < 2 || (mw[0] && mw[4]));
         if (cheap) {
             if (MIX) cheap_flux_mixed<ND>(P, ph, Fr, Fn, Ft, FE);
             else cheap_flux<ND>(P, ph, Fr, Fn, Ft, FE);
@@ -351,10 +351,8 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
     bool cheap = false;
     if (ROUTE) {
         // interfaces outside the line count as smooth
-        const bool mc = mask[Jc] != 0;
-        const bool mp = q - 1 < -1 ? true : mask[Jc - 1] != 0;
-        const bool mn = q + 1 > N - 1 ? true : mask[Jc + 1] != 0;
-        cheap = mc && (!ph.dilate || (mp && mn));
+        auto ml = [&](int o) { return (q + o < -1 || q + o > N - 1) ? true : mask[Jc + o] != 0; };
+        cheap = ml(0) && (ph.dilate < 1 || (ml(-1) && ml(1))) && (ph.dilate < 2 || (ml(-2) && ml(2)));
     }
     double Fr, Fn, Ft[2], FE;
     if (cheap) {

@@ -222,29 +222,39 @@ def routed_error(bits, threshold, probs, dilate=1, plain_cache=None):
 THRESHOLDS = (0.05, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.5, 0.65, 0.8, 0.9, 0.95, 0.98)
 
 
-def pick_threshold_by_error(bits, probs, target=1e-4, grid=THRESHOLDS, log=print):
-    """Smallest routing threshold (most interfaces routed cheap) whose routed
-    runs of the held-out problems each keep the relative L1 density error
-    against the plain form within half the target, or within twice that
-    problem's own rounding sensitivity where that is larger (a problem whose
-    plain solution moves by 5e-5 under a 1e-14 perturbation cannot certify
-    a smaller difference)."""
+def pick_threshold_by_error(bits, probs, target=1e-4, grid=THRESHOLDS, dilations=(1, 2), log=print):
+    """Routing configuration (threshold, dilation) for held-out problems:
+    for each dilation the smallest threshold whose routed runs each keep the
+    relative L1 density error against the plain form within half the target,
+    or within twice that problem's own rounding sensitivity where that is
+    larger (a problem whose plain solution moves by 5e-5 under a 1e-14
+    perturbation cannot certify a smaller difference); then the dilation
+    whose accepted threshold routes the most interfaces (smallest smooth
+    fraction over the problems).  Returns (threshold, results, floors,
+    dilation)."""
     cache = {}
     floors = [sensitivity_floor(p, cache) for p in probs]
     allow = [max(0.5 * target, 2.0 * f) for f in floors]
     if log:
         log("[sensor] held-out sensitivity floors %s -> allowed %s" % (
             ["%.1e" % f for f in floors], ["%.1e" % a for a in allow]))
-    res = []
-    for thr in grid:
-        res = routed_error(bits, thr, probs, plain_cache=cache)
-        ok = all(e <= a for (e, _), a in zip(res, allow))
-        if log:
-            log("[sensor] threshold %.3f: rel L1(rho) %s, smooth fractions %s%s" % (
-                thr, ["%.2e" % e for e, _ in res], ["%.2f" % f for _, f in res], " -> accepted" if ok else ""))
-        if ok:
-            return thr, res, floors
-    return grid[-1], res, floors
+    best = None
+    for dil in dilations:
+        res = []
+        for thr in grid:
+            res = routed_error(bits, thr, probs, dilate=dil, plain_cache=cache)
+            ok = all(e <= a for (e, _), a in zip(res, allow))
+            if log:
+                log("[sensor] dilate %d threshold %.3f: rel L1(rho) %s, smooth fractions %s%s" % (
+                    dil, thr, ["%.2e" % e for e, _ in res], ["%.2f" % f for _, f in res], " -> accepted" if ok else ""))
+            if ok:
+                frac = min(f for _, f in res)
+                if best is None or frac > best[0]:
+                    best = (frac, thr, res, dil)
+                break
+    if best is None:
+        return grid[-1], res, floors, dilations[0]
+    return best[1], best[2], floors, best[3]
 
 
 HELDOUT_SEEDS = (1000, 1001, 1002)
@@ -260,8 +270,15 @@ def save(path, bits, threshold, meta):
 
 
 def load(path=DEFAULT_WEIGHTS):
+    """(bfloat16 weight bits, routing threshold) of a saved network."""
     d = np.load(path, allow_pickle=False)
     return d["weights_bf16"].astype(np.uint16), float(d["threshold"])
+
+
+def load_dilate(path=DEFAULT_WEIGHTS):
+    """Routing dilation stored with a saved network (1 when absent)."""
+    d = np.load(path, allow_pickle=False)
+    return int(d["dilate"]) if "dilate" in d.files else 1
 
 
 def train_default(nprob=24, N=256, epochs=6, log=print, seed=100, heldout=(1024, 512)):
@@ -279,10 +296,11 @@ def train_default(nprob=24, N=256, epochs=6, log=print, seed=100, heldout=(1024,
     if log:
         log("[sensor] validation accuracy at 0.5: %.4f, smooth recall at 0.1%% false-smooth %.3f" % (acc, rec))
     held = heldout_problems(*heldout)
-    thr, res, floors = pick_threshold_by_error(tr.weights_bits(), held, log=log)
+    thr, res, floors, dil = pick_threshold_by_error(tr.weights_bits(), held, log=log)
     meta = {"samples": len(y), "val_samples": len(yv), "val_smooth_recall_at_0.1pct": rec,
             "val_acc_at_half": acc, "heldout_rel_L1_rho": max(e for e, _ in res),
-            "heldout_smooth_fraction": min(f for _, f in res), "heldout_floors": max(floors), "nprob": nprob, "N": N, "seed": seed,
+            "heldout_smooth_fraction": min(f for _, f in res), "heldout_floors": max(floors), "dilate": dil,
+            "nprob": nprob, "N": N, "seed": seed,
             "heldout": "shock_vortex %dx%d seeds %s t_end 0.4" % (heldout[0], heldout[1], list(HELDOUT_SEEDS))}
     return tr, thr, meta
 
@@ -293,11 +311,22 @@ def main():
     ap.add_argument("--nprob", type=int, default=24)
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--reselect", default=None,
+                    help="keep the network of this weights file, choose its routing again")
     a = ap.parse_args()
     t0 = time.time()
-    tr, thr, meta = train_default(a.nprob, a.N, a.epochs)
-    save(a.out, tr.weights_bits(), thr, meta)
-    print("[sensor] saved %s threshold %.6f meta %s (%.1f s)" % (a.out, thr, meta, time.time() - t0), flush=True)
+    if a.reselect:
+        d = np.load(a.reselect, allow_pickle=False)
+        bits = d["weights_bf16"].astype(np.uint16)
+        meta = {k: d[k] for k in d.files if k not in ("weights_bf16", "threshold")}
+        thr, res, floors, dil = pick_threshold_by_error(bits, heldout_problems())
+        meta.update({"heldout_rel_L1_rho": max(e for e, _ in res), "heldout_smooth_fraction": min(f for _, f in res),
+                     "heldout_floors": max(floors), "dilate": dil})
+        save(a.out, bits, thr, meta)
+    else:
+        tr, thr, meta = train_default(a.nprob, a.N, a.epochs)
+        save(a.out, tr.weights_bits(), thr, meta)
+    print("[sensor] saved %s threshold %.6f (%.1f s)" % (a.out, thr, time.time() - t0), flush=True)
 
 
 if __name__ == "__main__":

@@ -177,6 +177,49 @@ def test_routed_limits(mixed):
     assert np.abs(Rf - Rp).max() <= 1e-13 * np.abs(Rp).max()
 
 
+def jump_net():
+    """Smooth unless one of the six log-jump features is sizeable:
+    z = 4 - 40 relu(relu(sum of jumps))."""
+    theta = np.zeros(mlp.NPARAM)
+    for i in range(4, 10):
+        theta[i * 32] = 1.0
+    theta[352] = 1.0
+    theta[1408] = -40.0
+    theta[1440] = 4.0
+    return mlp.bf16_bits(theta)
+
+
+@pytest.mark.parametrize("dilate", [0, 1, 2])
+def test_routing_dilation(dilate):
+    """Sod's initial jump: the interfaces whose stencil sees the jump are
+    routed full, and with dilation d also the d interfaces on each side;
+    every other interface takes the cheap flux.  The residual matches the
+    oracle's fluxes chosen the same way."""
+    from paper_2007_14933_amd.solver import Solver
+    prob = I.sod(80).with_(scheme=I.TENO5)
+    U = O.apply_bc(prob, prob.U0.copy())
+    say("[gpu sensor] dilation", dilate)
+    s = Solver(prob.with_(U0=U), sensor=1)
+    s.set_sensor(jump_net(), 0.5, dilate=dilate)
+    Rg = s.residual().cpu().numpy()
+    st = iface_stencils(prob, U, 0)
+    smooth = np.array([O.features(prob, 0, st[t], [1.0])[0][4:].max() == 0.0 for t in range(len(st))])
+    route = smooth.copy()
+    for o in range(1, dilate + 1):
+        route[o:] &= smooth[:-o]
+        route[:-o] &= smooth[o:]
+    F = np.stack([O.cheap_flux(prob, 0, st[t], [1.0]) if route[t] else O.iface_flux(prob, 0, st[t], [1.0])[0]
+                  for t in range(len(st))])
+    h = float(prob.coords1d[0][1] - prob.coords1d[0][0])
+    Ro = -(F[1:] - F[:-1]).T / h
+    S, J = O.metrics(prob)
+    err = np.abs(Rg.reshape(Ro.shape) - Ro).max(axis=1) / flux_scale(prob, U, J, S)
+    sm, tot = s.sensor_stats()
+    say("   routed cheap %d of %d (oracle %d); residual |diff| / flux scale %s" % (sm, tot, int(smooth.sum()), err))
+    assert sm == int(smooth.sum()) and (~route).sum() == 3 + 2 * dilate
+    assert err.max() <= 1e-13
+
+
 def test_trained_sensor_error_and_gain():
     """Train the network on method-made labels (small run), choose the
     threshold on held-out shock-vortex seeds, then run the measured
@@ -196,13 +239,14 @@ def test_trained_sensor_error_and_gain():
     acc = float(((zv >= 0) == (yv == 1)).float().mean().item())
     say("   samples %d, held-out accuracy %.4f, smooth recall at 0.1%% false-smooth %.3f" % (len(y), acc, rec))
     assert acc > 0.6  # balanced classes: well above chance
-    thr, _, _ = SN.pick_threshold_by_error(tr.weights_bits(), SN.heldout_problems(256, 128, (1000, 1001)), log=say)
+    thr, _, _, dil = SN.pick_threshold_by_error(tr.weights_bits(), SN.heldout_problems(256, 128, (1000, 1001)),
+                                                 log=say)
     prob = I.shock_vortex(256, 128, seed=42)
     res = {}
     for name, kw in (("plain", {}), ("routed", {"sensor": 1})):
         s = Solver(prob, **kw)
         if kw:
-            s.set_sensor(tr.weights_bits(), thr)
+            s.set_sensor(tr.weights_bits(), thr, dilate=dil)
         s.profile(True)
         s.run(10 ** 9, cfl=prob.cfl, t_end=prob.t_end)
         s.check()
