@@ -100,7 +100,7 @@ __global__ void k_b_dt_final(BState *st, int P, double cfl, unsigned *flags) {
 }
 
 template <int DIR, int SCHEME, bool MIX, bool ROUTE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_b_sweep(const BProb *__restrict__ pr, const BState *__restrict__ st, const int64_t *__restrict__ off, int P,
           int64_t total, Phys ph, int first, unsigned *flags) {
     __shared__ double sbuf[DIR == 0 ? kWaves : 1][4][kChunk][64];
