@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--batch-full", action="store_true",
                     help="also run both batched forms to t = 0.25 and report their density difference")
     ap.add_argument("--no-tune", action="store_true", help="batched ensemble with default tiles")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="also time the oracle on every workload (bounded samples, all threads and one thread)")
     return ap.parse_args()
 
 
@@ -118,6 +120,58 @@ def copy_ceiling(nbytes=1 << 30, reps=5):
     del src, dst
     torch.cuda.empty_cache()
     return gbs
+
+
+def cpu_table():
+    """The oracle on each workload (bounded samples) on all host threads, and
+    one TGV 64^3 substage on one thread (a child process)."""
+    import subprocess
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2007_14933_amd import inputs
+
+    out = {"threads": O.num_threads()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            out["cpu"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        out["cpu"] = "unknown"
+    cases = [("sod400_full_run", inputs.sod(400), 10 ** 6, 0.2),
+             ("tgv256_2_steps", inputs.tgv(256), 2, 0.0),
+             ("tgv64_100_steps", inputs.tgv(64), 100, 0.0),
+             ("wall512x256x256_1_step", inputs.wall_flow(), 1, 0.0),
+             ("shockvortex1024x512_10_steps", inputs.shock_vortex(1024, 512, seed=42), 10, 0.0)]
+    rng = np.random.default_rng(2007)
+    for n in (128, 448, 768, 1024):
+        cases.append(("riemann%d_10_steps" % n, inputs.riemann2d(n, rng), 10, 0.0))
+    for name, prob, nst, te in cases:
+        S, J = O.metrics(prob)
+        U = prob.U0.copy()
+        t0 = time.perf_counter()
+        if te > 0.0:
+            steps, tt = 0, 0.0
+            while tt < te and steps < 10 ** 6:
+                tt = O.run(prob, S, J, U, 1, cfl=0.5, t_end=te, t0=tt)
+                steps += 1
+        else:
+            O.run(prob, S, J, U, nst, cfl=0.5)
+            steps = nst
+        el = time.perf_counter() - t0
+        out[name] = {"seconds": round(el, 3), "steps": steps,
+                     "Mpoint_substeps_per_s": round(prob.npoints * 3 * steps / el / 1e6, 3)}
+    code = ("import sys, time; sys.path.insert(0, %r); from oracle import oracle as O; "
+            "from paper_2007_14933_amd import inputs; import numpy as np; p = inputs.tgv(64); S, J = O.metrics(p); "
+            "U = p.U0.copy(); O.apply_bc(p, U); dU = np.zeros(O.int_shape(p)); dt = O.compute_dt(p, S, J, U, 0.5); "
+            "t0 = time.perf_counter(); O.rk_substep(p, S, J, 0, dt, U, dU); "
+            "print(64 ** 3 / (time.perf_counter() - t0) / 1e6, O.num_threads())" % ROOT)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    try:
+        v, th = r.stdout.split()[-2:]
+        out["tgv64_1_substage_one_thread"] = {"Mpoint_substeps_per_s": round(float(v), 3), "threads": int(th)}
+    except ValueError:
+        out["tgv64_1_substage_one_thread"] = {"error": r.stderr[-300:]}
+    return out
 
 
 def timed_run(prob, form, steps, warmup, cfl, sensor=0, bits=None, thr=None, keep_rho=False, dilate=1):
@@ -467,6 +521,8 @@ def main():
         out["batch"] = batch_form(args.batch_steps, args.warmup, args.cfl, not args.no_tune, args.batch_full)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n or n)
+    if args.cpu_table:
+        out["cpu_table"] = cpu_table()
     print(json.dumps(out), flush=True)
 
 

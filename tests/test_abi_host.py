@@ -95,3 +95,33 @@ def test_small_workspace_rejected(lib):
     rc = lib.osbli_init_grid(C.byref(ctx), C.byref(p), x, None, None, C.c_void_p(256), need - 8, None)
     assert rc == B.OSBLI_ENOSPACE
     lib.osbli_destroy(ctx)
+
+
+def _gpu_test_problems():
+    """Every problem the GPU tests construct, as (name, problem, form, sensor)."""
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, here)
+    import test_gpu_batch as TB
+    import test_gpu_forms as TF
+    import test_gpu_parity as TP
+    out = []
+    for name, mk in TP.X_SWEEP_CASES.items():
+        for form in (0, 1):
+            out.append((name, mk(), form, 0))
+    for name, (mk, _, _) in TF.CASES.items():
+        out.append((name, mk(), 1, 0))
+    for sensor in (0, 1):
+        for p in TB.ensemble(TB.SIZES, 11, TB.T_ENDS):
+            out.append((p.name, p, 1, sensor))
+    out.append(("sod80_teno", I.sod(80).with_(scheme=I.TENO5), 0, 1))
+    return out
+
+
+def test_gpu_test_problems_are_valid_parameters(lib):
+    """The parameter check of osbli_workspace_bytes runs on the host: every
+    grid the GPU tests build must pass it (a size or BC mistake in a test
+    then shows here, without a GPU)."""
+    for name, prob, form, sensor in _gpu_test_problems():
+        p = B.make_params(prob, form=form, sensor=sensor)
+        assert lib.osbli_workspace_bytes(C.byref(p)) > 0, (name, form, sensor)
