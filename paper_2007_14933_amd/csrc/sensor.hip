@@ -242,14 +242,82 @@ hipError_t labels_nd(const Grid &g, const Phys &ph, const double *U, int d, floa
     return hipGetLastError();
 }
 
+// y and z directions: each wave marches a segment of interfaces along 64
+// neighbouring lines (sensor_line)
+template <int ND, int DIR>
+__global__ void __launch_bounds__(256)
+k_sensor_line(const double *__restrict__ U, Grid g, Phys ph, const uint16_t *__restrict__ w, float zcut,
+              uint8_t *__restrict__ mask, int64_t seg, int64_t nseg) {
+    __shared__ uint16_t xs[4][64 * 16], hs[4][64 * 32];
+    __shared__ float w3s[33];
+    if (threadIdx.x < 33) w3s[threadIdx.x] = bf2f(w[oW3 + threadIdx.x]);
+    __syncthreads();
+    constexpr int O1 = DIR == 0 ? 1 : 0;
+    constexpr int O2 = DIR == 2 ? 1 : 2;
+    const int64_t lines = g.n[O1] * g.n[O2];
+    const int64_t wpl = (lines + 63) >> 6;
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t sg = gw / wpl;
+    if (sg >= nseg) return;  // wave-uniform
+    const int64_t line0 = (gw - sg * wpl) << 6;
+    const int64_t NI = g.n[DIR] + 1;
+    const int64_t iq0 = sg * seg, iq1 = iq0 + seg < NI ? iq0 + seg : NI;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    MlpFrag F;
+    load_frag(w, lane, F);
+    sensor_line<ND, DIR>(U, g, ph, F, zcut, mask, line0, iq0, iq1, xs[wv], hs[wv], w3s);
+}
+
+// x direction, rows of >= 64 interfaces: 64 interfaces per wave with the
+// points staged once (sensor_x_lanes)
+template <int ND>
+__global__ void __launch_bounds__(256)
+k_sensor_xl(const double *__restrict__ U, Grid g, Phys ph, const uint16_t *__restrict__ w, float zcut,
+            uint8_t *__restrict__ mask, int64_t totalJ) {
+    __shared__ uint16_t xs[4][64 * 16], hs[4][64 * 32];
+    __shared__ float w3s[33];
+    __shared__ SxLds<ND> sp[4];
+    if (threadIdx.x < 33) w3s[threadIdx.x] = bf2f(w[oW3 + threadIdx.x]);
+    __syncthreads();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t J0 = gw * 64;
+    if (J0 >= totalJ) return;  // wave-uniform
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    MlpFrag F;
+    load_frag(w, lane, F);
+    sensor_x_lanes<ND>(U, g, ph, F, zcut, mask, J0, totalJ, sp[wv], xs[wv], hs[wv], w3s);
+}
+
 template <int ND>
 hipError_t sensor_nd(const Grid &g, const Phys &ph, const double *U, int d, const uint16_t *w, float zcut,
                      uint8_t *mask, hipStream_t s) {
     const IfaceGrid I = iface_grid(g, d);
-    const unsigned nb = (unsigned)((I.total + 255) / 256);
-    if (d == 0) hipLaunchKernelGGL((k_sensor<ND, 0>), dim3(nb), dim3(256), 0, s, U, g, ph, w, zcut, mask);
-    else if (d == 1) hipLaunchKernelGGL((k_sensor<ND, (ND >= 2 ? 1 : 0)>), dim3(nb), dim3(256), 0, s, U, g, ph, w, zcut, mask);
-    else hipLaunchKernelGGL((k_sensor<ND, (ND >= 3 ? 2 : 0)>), dim3(nb), dim3(256), 0, s, U, g, ph, w, zcut, mask);
+    if (d == 0 && g.n[0] + 1 >= 64) {
+        const int64_t waves = (I.total + 63) / 64;
+        const unsigned nb = (unsigned)((waves + 3) / 4);
+        hipLaunchKernelGGL((k_sensor_xl<ND>), dim3(nb), dim3(256), 0, s, U, g, ph, w, zcut, mask, I.total);
+        return hipGetLastError();
+    }
+    if (d == 0 || ND == 1) {
+        const unsigned nb = (unsigned)((I.total + 255) / 256);
+        hipLaunchKernelGGL((k_sensor<ND, 0>), dim3(nb), dim3(256), 0, s, U, g, ph, w, zcut, mask);
+        return hipGetLastError();
+    }
+    const int o1 = 0, o2 = d == 2 ? 1 : 2;  // lines of the y and z directions run along x
+    const int64_t lines = g.n[o1] * g.n[o2], NI = g.n[d] + 1;
+    // about 2^19 lanes (the network's cost per interface does not shrink with
+    // longer segments, so parallelism is worth more than the shared prologue)
+    int64_t seg = (NI * lines + (int64_t(1) << 19) - 1) >> 19;
+    seg = seg < 2 ? 2 : (seg > NI ? NI : seg);
+    const int64_t nseg = (NI + seg - 1) / seg;
+    const int64_t waves = ((lines + 63) / 64) * nseg;
+    const unsigned nb = (unsigned)((waves + 3) / 4);
+    if (d == 1)
+        hipLaunchKernelGGL((k_sensor_line<ND, (ND >= 2 ? 1 : 0)>), dim3(nb), dim3(256), 0, s, U, g, ph, w, zcut, mask,
+                           seg, nseg);
+    else
+        hipLaunchKernelGGL((k_sensor_line<ND, (ND >= 3 ? 2 : 0)>), dim3(nb), dim3(256), 0, s, U, g, ph, w, zcut, mask,
+                           seg, nseg);
     return hipGetLastError();
 }
 

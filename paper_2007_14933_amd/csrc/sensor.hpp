@@ -22,63 +22,114 @@ __device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even
 }
 
 // ------------------------------------------------------------ features
-__device__ __forceinline__ double js3(const double (&q)[6], int m) {
+// Features 0..3 of interface p+1/2: three-point Jiang-Shu indicators of
+// rho/rho_bar + p/p_bar + u_t/a_bar on the four substencils of p-2..p+3
+// (each variable's indicator on unscaled values times the inverse square of
+// its scale), over their sum + 1e-20; 4..9: log10(1 + 1e6 J)/6 of the rho
+// and p jumps J = |q_{k+1} - q_k| / (q_{k+1} + q_k) over (p-1,p), (p,p+1),
+// (p+1,p+2).  The FP64 operations follow the definition's order without FMA
+// contraction, so every kernel (per interface, marching, batched) computes
+// the same features.
+
+// density, pressure and tangential velocities of one point
+template <int ND>
+struct SPoint {
+    double r, p, vt[2];
+};
+
+template <int ND, int DIR>
+__device__ __forceinline__ void spoint(const double *__restrict__ U, int64_t e, int64_t cs, const Phys &ph,
+                                       SPoint<ND> &o) {
 #pragma clang fp contract(off)
-    const double a1 = q[m] - 2.0 * q[m + 1] + q[m + 2], a2 = q[m] - q[m + 2];
+    const double r = U[e];
+    double u[3], ke = 0.0;
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+        u[m] = U[e + (1 + m) * cs] / r;
+        ke += u[m] * u[m];
+    }
+    o.r = r;
+    o.p = ph.gm1 * (U[e + (ND + 1) * cs] - 0.5 * r * ke);
+#pragma unroll
+    for (int s = 0; s < ND - 1; ++s) o.vt[s] = u[(DIR + 1 + s) % ND];
+}
+
+__device__ __forceinline__ double js3v(double a, double b, double c) {
+#pragma clang fp contract(off)
+    const double a1 = a - 2.0 * b + c, a2 = a - c;
     return (13.0 / 12.0) * a1 * a1 + 0.25 * a2 * a2;
 }
 
-// Sensor features of interface p+1/2 of a line (separable meshes: n = e_DIR,
-// tangents e_{DIR+1}, e_{DIR+2}); stencil points p-2..p+3 start at ext index
-// e0 with stride st.  Features 0..3: three-point Jiang-Shu indicators of
-// rho/rho_bar + p/p_bar + u_t/a_bar on the four substencils (each variable's
-// indicator on unscaled values times the inverse square of its scale), over
-// their sum + 1e-20; 4..9: log10(1 + 1e6 J)/6 of the rho and p jumps
-// J = |q_{k+1} - q_k| / (q_{k+1} + q_k) over (p-1,p), (p,p+1), (p+1,p+2).
-template <int ND, int DIR>
-__device__ __forceinline__ void features(const double *__restrict__ U, int64_t e0, int64_t st, int64_t cs,
-                                         const Phys &ph, float (&f)[kIn]) {
-    // the FP64 operations of the definition in its order, no FMA contraction,
-    // so that every translation unit computes the same features
+// indicators of one substencil (first point k): rho, p, tangential velocities
+template <int ND>
+struct STriple {
+    double br, bp, bv[2];
+};
+
+template <int ND>
+__device__ __forceinline__ void striple(const SPoint<ND> &a, const SPoint<ND> &b, const SPoint<ND> &c,
+                                        STriple<ND> &o) {
+    o.br = js3v(a.r, b.r, c.r);
+    o.bp = js3v(a.p, b.p, c.p);
+#pragma unroll
+    for (int s = 0; s < ND - 1; ++s) o.bv[s] = js3v(a.vt[s], b.vt[s], c.vt[s]);
+}
+
+// log-normalised rho and p jumps between two points (inputs of a bfloat16
+// network: the logarithm is taken in FP32)
+template <int ND>
+__device__ __forceinline__ void sjump(const SPoint<ND> &a, const SPoint<ND> &b, float &lr, float &lp) {
 #pragma clang fp contract(off)
-    double rho[6], p[6], vt[2][6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int64_t e = e0 + k * st;
-        const double r = U[e];
-        double u[3], ke = 0.0;
-#pragma unroll
-        for (int m = 0; m < ND; ++m) {
-            u[m] = U[e + (1 + m) * cs] / r;
-            ke += u[m] * u[m];
-        }
-        rho[k] = r;
-        p[k] = ph.gm1 * (U[e + (ND + 1) * cs] - 0.5 * r * ke);
-#pragma unroll
-        for (int s = 0; s < ND - 1; ++s) vt[s][k] = u[(DIR + 1 + s) % ND];
-    }
-    const double rb = 0.5 * (rho[2] + rho[3]), pb = 0.5 * (p[2] + p[3]);
+    const double jr = fabs(b.r - a.r) / (b.r + a.r);
+    const double jp = fabs(b.p - a.p) / (b.p + a.p);
+    lr = log10f((float)(1.0 + 1e6 * jr)) * (1.0f / 6.0f);
+    lp = log10f((float)(1.0 + 1e6 * jp)) * (1.0f / 6.0f);
+}
+
+// the ten features from the two middle points, the four substencils'
+// indicators and the three jumps
+template <int ND>
+__device__ __forceinline__ void sfeatures(const SPoint<ND> &m2, const SPoint<ND> &m3, const STriple<ND> (&T)[4],
+                                          const float (&lr)[3], const float (&lp)[3], const Phys &ph,
+                                          float (&f)[kIn]) {
+#pragma clang fp contract(off)
+    const double rb = 0.5 * (m2.r + m3.r), pb = 0.5 * (m2.p + m3.p);
     const double sr = 1.0 / (rb * rb), sp = 1.0 / (pb * pb), sv = rb / (ph.gamma * pb);
     double beta[4], sum = 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        double b = sr * js3(rho, m) + sp * js3(p, m);
+        double b = sr * T[m].br + sp * T[m].bp;
 #pragma unroll
-        for (int s = 0; s < ND - 1; ++s) b += sv * js3(vt[s], m);
+        for (int s = 0; s < ND - 1; ++s) b += sv * T[m].bv[s];
         beta[m] = b;
         sum += b;
     }
     const double inv = 1.0 / (sum + 1e-20);
 #pragma unroll
     for (int m = 0; m < 4; ++m) f[m] = (float)(beta[m] * inv);
-    // jump logarithms in FP32 (inputs of a bfloat16 network)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        const double jr = fabs(rho[m + 2] - rho[m + 1]) / (rho[m + 2] + rho[m + 1]);
-        const double jp = fabs(p[m + 2] - p[m + 1]) / (p[m + 2] + p[m + 1]);
-        f[4 + m] = log10f((float)(1.0 + 1e6 * jr)) * (1.0f / 6.0f);
-        f[7 + m] = log10f((float)(1.0 + 1e6 * jp)) * (1.0f / 6.0f);
+        f[4 + m] = lr[m];
+        f[7 + m] = lp[m];
     }
+}
+
+// features of interface p+1/2 of a line (separable meshes: n = e_DIR,
+// tangents e_{DIR+1}, e_{DIR+2}); stencil points p-2..p+3 start at ext
+// index e0 with stride st
+template <int ND, int DIR>
+__device__ __forceinline__ void features(const double *__restrict__ U, int64_t e0, int64_t st, int64_t cs,
+                                         const Phys &ph, float (&f)[kIn]) {
+    SPoint<ND> P[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) spoint<ND, DIR>(U, e0 + k * st, cs, ph, P[k]);
+    STriple<ND> T[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) striple<ND>(P[m], P[m + 1], P[m + 2], T[m]);
+    float lr[3], lp[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) sjump<ND>(P[m + 1], P[m + 2], lr[m], lp[m]);
+    sfeatures<ND>(P[2], P[3], T, lr, lp, ph, f);
 }
 
 // interface grid of direction d: extent n_d + 1 along d (position p = index - 1)
@@ -207,6 +258,134 @@ __device__ __forceinline__ void sensor_item(const double *__restrict__ U, const 
     load_frag(w, lane, F);
     const float z = mlp_mfma(f, F, xs, hs, w3s, lane);
     if (t < I.total) mask[t] = z >= zcut ? 1 : 0;
+}
+
+// Routing decisions of the interfaces iq0 .. iq1-1 (iq = p + 1, interface
+// p+1/2) of the lane's line along DIR (DIR >= 1: neighbouring lanes own
+// neighbouring x, so loads and mask stores are contiguous).  The six points,
+// four substencil indicators and three jumps slide along the line, so each
+// point, substencil and jump is evaluated once.  Every lane of the wave must
+// call it with the same iq0, iq1.
+template <int ND, int DIR>
+__device__ __forceinline__ void sensor_line(const double *__restrict__ U, const Grid &g, const Phys &ph,
+                                            const MlpFrag &F, float zcut, uint8_t *__restrict__ mask, int64_t line0,
+                                            int64_t iq0, int64_t iq1, uint16_t *xs, uint16_t *hs, const float *w3s) {
+    constexpr int O1 = DIR == 0 ? 1 : 0;
+    constexpr int O2 = DIR == 2 ? 1 : 2;
+    const int lane = threadIdx.x & 63;
+    const int64_t n1 = g.n[O1], n2 = g.n[O2], lines = n1 * n2;
+    const int64_t line = line0 + lane;
+    const bool active = line < lines;
+    const int64_t lc = active ? line : lines - 1;
+    int64_t q[3];
+    q[DIR] = 0;
+    q[O1] = lc % n1;
+    q[O2] = lc / n1;
+    const int64_t base = ext_index(g, q[0], q[1], q[2]);
+    const int64_t st = g.es[DIR], cs = g.enpts;
+    int64_t E[3] = {g.n[0], g.n[1], g.n[2]};
+    E[DIR] += 1;
+    const int64_t ms[3] = {1, E[0], E[0] * E[1]};
+    const int64_t mbase = q[O1] * ms[O1] + q[O2] * ms[O2], mst = ms[DIR];
+    // interface iq: points iq-3 .. iq+2
+    SPoint<ND> P[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) spoint<ND, DIR>(U, base + (iq0 - 3 + k) * st, cs, ph, P[k]);
+    STriple<ND> T[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) striple<ND>(P[m], P[m + 1], P[m + 2], T[m]);
+    float lr[3], lp[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) sjump<ND>(P[m + 1], P[m + 2], lr[m], lp[m]);
+    for (int64_t iq = iq0; iq < iq1; ++iq) {
+        if (iq > iq0) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) P[k] = P[k + 1];
+            spoint<ND, DIR>(U, base + (iq + 2) * st, cs, ph, P[5]);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) T[m] = T[m + 1];
+            striple<ND>(P[3], P[4], P[5], T[3]);
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                lr[m] = lr[m + 1];
+                lp[m] = lp[m + 1];
+            }
+            sjump<ND>(P[3], P[4], lr[2], lp[2]);
+        }
+        float f[kIn];
+        sfeatures<ND>(P[2], P[3], T, lr, lp, ph, f);
+        const float z = mlp_mfma(f, F, xs, hs, w3s, lane);
+        if (active) mask[mbase + iq * mst] = z >= zcut ? 1 : 0;
+    }
+}
+
+// Routing decisions of the x interfaces J0 .. J0+63 of the row-major
+// interface numbering J = row (N + 1) + p + 1 (rows of N + 1 >= 64
+// interfaces, so a wave spans at most two rows): each lane evaluates the
+// point p + 3 of its row once (plus the five points left of lane 0's stencil
+// and the first five points of a row starting inside the wave), the stencils
+// are gathered from LDS.  Every lane of the wave must call it.
+constexpr int kSxSlots = 64 + 10;
+
+template <int ND>
+struct SxLds {
+    double v[ND + 1][kSxSlots];  // r, p, vt[0..ND-2] of the staged points
+};
+
+template <int ND>
+__device__ __forceinline__ void sensor_x_lanes(const double *__restrict__ U, const Grid &g, const Phys &ph,
+                                               const MlpFrag &F, float zcut, uint8_t *__restrict__ mask, int64_t J0,
+                                               int64_t totalJ, SxLds<ND> &sp, uint16_t *xs, uint16_t *hs,
+                                               const float *w3s) {
+    const int lane = threadIdx.x & 63;
+    const int64_t N = g.n[0], NI = N + 1, n1 = g.n[1], cs = g.enpts;
+    const int64_t J = J0 + lane;
+    const bool valid = J < totalJ;
+    const int64_t Jc = valid ? J : totalJ - 1;
+    const int64_t row = Jc / NI;
+    const int64_t q = Jc - row * NI - 1;
+    const int64_t row0 = J0 / NI, q0 = J0 - row0 * NI - 1;
+    const int Lnext = (int)(NI - (q0 + 1));  // first lane of row0 + 1 (>= 64: none)
+    auto stage = [&](int slot, int64_t r, int64_t pos) {
+        SPoint<ND> o;
+        spoint<ND, 0>(U, ext_index(g, 0, r % n1, r / n1) + pos, cs, ph, o);
+        sp.v[0][slot] = o.r;
+        sp.v[1][slot] = o.p;
+#pragma unroll
+        for (int s = 0; s < ND - 1; ++s) sp.v[2 + s][slot] = o.vt[s];
+    };
+    stage(lane, row, q + 3);
+    if (lane < 5) {
+        stage(64 + lane, row0, q0 - 2 + lane);
+    } else if (lane < 10 && Lnext < 64) {
+        const int64_t r1 = row0 + 1 < totalJ / NI ? row0 + 1 : row0;
+        stage(64 + lane, r1, (int64_t)(lane - 5) - 3);
+    }
+    wave_sync();
+    const bool inrow0 = lane < Lnext;
+    SPoint<ND> P[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int src = lane - 5 + k;
+        int slot;
+        if (inrow0) slot = src >= 0 ? src : 64 + lane + k;
+        else slot = src >= Lnext ? src : 69 + (lane - Lnext) + k;
+        P[k].r = sp.v[0][slot];
+        P[k].p = sp.v[1][slot];
+#pragma unroll
+        for (int s = 0; s < ND - 1; ++s) P[k].vt[s] = sp.v[2 + s][slot];
+    }
+    STriple<ND> T[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) striple<ND>(P[m], P[m + 1], P[m + 2], T[m]);
+    float lr[3], lp[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) sjump<ND>(P[m + 1], P[m + 2], lr[m], lp[m]);
+    float f[kIn];
+    sfeatures<ND>(P[2], P[3], T, lr, lp, ph, f);
+    const float z = mlp_mfma(f, F, xs, hs, w3s, lane);
+    if (valid) mask[J] = z >= zcut ? 1 : 0;
+    wave_sync();  // the staging buffer is reused by the next call
 }
 
 }  // namespace sn

@@ -220,6 +220,44 @@ def test_routing_dilation(dilate):
     assert err.max() <= 1e-13
 
 
+@pytest.mark.parametrize("case", ["riemann2d_48", "smooth3d_10"])
+def test_routing_masks_match_oracle_decisions(case):
+    """The routed-interface count of the sensor kernels (per interface along
+    x, marching along y and z) lies between the oracle's sure and possible
+    counts: oracle features, the FP64 network on bfloat16-rounded inputs and
+    activations, decisions within 0.02 of the cut counted as either."""
+    from paper_2007_14933_amd import sensor as SN
+    from paper_2007_14933_amd.solver import Solver
+    if case == "riemann2d_48":
+        prob = I.riemann2d(48, 3)
+        U = state_after(prob, 30)
+    else:
+        prob = I.smooth_random(3, (70, 9, 8), seed=2, amp=0.3)
+        U = O.apply_bc(prob, prob.U0.copy())
+    # scaled random weights: logits spread over tens of units; b3 puts the
+    # cut near the median so that both classes occur
+    w = SN.init_weights(4) * 3.0
+    w[1440] = 3.2 if case == "riemann2d_48" else 15.4
+    bits = SN.bf16_bits(w)
+    theta = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    thr = 0.5
+    s = Solver(prob.with_(U0=U), sensor=1)
+    s.set_sensor(bits, thr, dilate=0)
+    s.sensor_update()
+    sm, tot = s.sensor_stats()
+    Z = []
+    for d in range(prob.ndim):
+        st = iface_stencils(prob, U, d)
+        F = np.array([O.features(prob, d, st[t], np.eye(3)[d][:prob.ndim])[0] for t in range(len(st))])
+        z, _ = mlp.forward(theta, F, round_activations=True)
+        Z.append(z)
+    z = np.concatenate(Z)
+    zc = np.log(thr / (1 - thr))
+    sure, possible = int((z >= zc + 0.02).sum()), int((z >= zc - 0.02).sum())
+    say("[gpu sensor] %s: routed %d of %d, oracle sure %d possible %d" % (case, sm, tot, sure, possible))
+    assert tot == len(z) and sure <= sm <= possible
+
+
 def test_trained_sensor_error_and_gain():
     """Train the network on method-made labels (small run), choose the
     routing (threshold, dilation) on held-out shock-vortex seeds, then run
