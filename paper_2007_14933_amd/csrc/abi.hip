@@ -624,7 +624,7 @@ int upload_tables(osbli_batch *b, hipStream_t s) {
         }
         // x: lanes along x for rows of >= 64 interfaces (as the single-grid launch)
         const int64_t totalJ = q.g.n[1] * (q.g.n[0] + 1);
-        const int64_t nwx = q.xl ? (totalJ - 2) / 63 + 1 : 0;
+        const int64_t nwx = q.xl ? ((totalJ - 2) / 63 + kXlPerTile) / kXlPerTile : 0;
         const int64_t nw0 = q.xl ? 0 : q.nseg[0] * q.wpl[0];
         const int64_t nw1 = q.nseg[1] * q.wpl[1];
         WX[p + 1] = WX[p] + nwx;

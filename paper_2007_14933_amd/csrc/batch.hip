@@ -58,28 +58,43 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// dt denominator of each problem (separable 2D meshes), max per problem
+// dt denominator of each problem (separable 2D meshes), max per problem.
+// Each block walks a contiguous run of tiles and issues one atomic max per
+// problem it touches (tiles of a problem are contiguous).
+__device__ __forceinline__ void b_dt_flush(BState *st, int p, double run, double *part) {
+    run = wave_max(run);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double m = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
+        atomicMax(&st[p].smax, (unsigned long long)__double_as_longlong(m));
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(256)
 k_b_dt(const BProb *__restrict__ pr, BState *st, const int64_t *__restrict__ off, int P, int64_t total, Phys ph) {
     __shared__ double part[4];
-    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        const int p = find_prob(off, P, tile);
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * per;
+    const int64_t t1 = t0 + per < total ? t0 + per : total;
+    int cur = -1;
+    double run = 0.0;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int p = find_prob(off, P, tile);  // block-uniform
+        if (p != cur) {
+            if (cur >= 0) b_dt_flush(st, cur, run, part);
+            cur = p;
+            run = 0.0;
+        }
         const BProb &b = pr[p];
-        double s = 0.0;
         const int64_t ci = (tile - off[p]) * kPT + threadIdx.x;
         if (st[p].active && ci < b.g.nint) {
             const int64_t idx[3] = {ci % b.g.n[0], ci / b.g.n[0], 0};
-            s = dt_node<2, false>(b.U, b.g, ph, sep_metrics(b), idx);
+            run = fmax(run, dt_node<2, false>(b.U, b.g, ph, sep_metrics(b), idx));
         }
-        s = wave_max(s);
-        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double m = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
-            atomicMax(&st[p].smax, (unsigned long long)__double_as_longlong(m));
-        }
-        __syncthreads();
     }
+    if (cur >= 0) b_dt_flush(st, cur, run, part);
 }
 
 __global__ void k_b_dt_final(BState *st, int P, double cfl, unsigned *flags) {
@@ -134,8 +149,14 @@ k_b_sweep_xl(const BProb *__restrict__ pr, const BState *__restrict__ st, const 
         const BProb &b = pr[p];
         const int64_t local = wt - off[p];
         const Metrics m = sep_metrics(b);
-        sweep_x_lanes<2, SCHEME, MIX, ROUTE>(b.U, b.R, b.g, ph, m, local * 63, b.g.n[1] * (b.g.n[0] + 1), first, flags,
-                                             ROUTE ? b.mask[0] : nullptr, sm[wv]);
+        const int64_t totalJ = b.g.n[1] * (b.g.n[0] + 1);
+        // a tile is kXlPerTile consecutive 63-interface runs of the problem
+        for (int k = 0; k < kXlPerTile; ++k) {
+            const int64_t J0 = (local * kXlPerTile + k) * 63;
+            if (J0 + 1 >= totalJ) break;  // wave-uniform
+            sweep_x_lanes<2, SCHEME, MIX, ROUTE>(b.U, b.R, b.g, ph, m, J0, totalJ, first, flags,
+                                                 ROUTE ? b.mask[0] : nullptr, sm[wv]);
+        }
     }
 }
 
@@ -173,17 +194,12 @@ template <int DIR>
 __global__ void __launch_bounds__(256)
 k_b_sensor(const BProb *__restrict__ pr, const BState *__restrict__ st, const int64_t *__restrict__ off, int P,
            int64_t total, Phys ph, const uint16_t *__restrict__ w, float zcut) {
-    __shared__ uint16_t xs[4][64 * 16], hs[4][64 * 32];
-    __shared__ float w3s[33];
-    if (threadIdx.x < 33) w3s[threadIdx.x] = bf2f(w[oW3 + threadIdx.x]);
-    __syncthreads();
-    const int wv = threadIdx.x >> 6;
     for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int p = find_prob(off, P, tile);
         if (!st[p].active) continue;
         const BProb &b = pr[p];
         const int64_t t = (tile - off[p]) * kPT + threadIdx.x;
-        sensor_item<2, DIR>(b.U, b.g, ph, w, zcut, b.mask[DIR], t, xs[wv], hs[wv], w3s);
+        sensor_item<2, DIR>(b.U, b.g, ph, w, zcut, b.mask[DIR], t);
     }
 }
 

@@ -120,6 +120,8 @@ struct BProb {             // one problem, device resident
     int64_t seg[3], nseg[3], wpl[3];   // sweep tiling per direction (marching sweeps)
 };
 
+constexpr int kXlPerTile = 4;  // 63-interface runs per tile of the batched x sweep
+
 struct BState {            // per-problem time state, device resident
     double t, dt, tend;
     unsigned long long smax;

@@ -200,11 +200,7 @@ __global__ void k_mlp_fwd_fp32(const float *__restrict__ X, int64_t n, const uin
 // ------------------------------------------------------ MFMA inference
 __global__ void __launch_bounds__(256)
 k_mlp_fwd_mfma(const float *__restrict__ X, int64_t n, const uint16_t *__restrict__ w, float *__restrict__ z) {
-    __shared__ uint16_t xs[4][64 * 16], hs[4][64 * 32];
-    __shared__ float w3s[33];
-    if (threadIdx.x < 33) w3s[threadIdx.x] = bf2f(w[oW3 + threadIdx.x]);
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t sc = s < n ? s : n - 1;
     float x[kIn];
@@ -212,7 +208,7 @@ k_mlp_fwd_mfma(const float *__restrict__ X, int64_t n, const uint16_t *__restric
     for (int k = 0; k < kIn; ++k) x[k] = X[sc * kIn + k];
     MlpFrag F;
     load_frag(w, lane, F);
-    const float zz = mlp_mfma(x, F, xs[wv], hs[wv], w3s, lane);
+    const float zz = mlp_mfma(x, F, lane);
     if (s < n) z[s] = zz;
 }
 
@@ -222,13 +218,8 @@ template <int ND, int DIR>
 __global__ void __launch_bounds__(256)
 k_sensor(const double *__restrict__ U, Grid g, Phys ph, const uint16_t *__restrict__ w, float zcut,
          uint8_t *__restrict__ mask) {
-    __shared__ uint16_t xs[4][64 * 16], hs[4][64 * 32];
-    __shared__ float w3s[33];
-    if (threadIdx.x < 33) w3s[threadIdx.x] = bf2f(w[oW3 + threadIdx.x]);
-    __syncthreads();
-    const int wv = threadIdx.x >> 6;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    sensor_item<ND, DIR>(U, g, ph, w, zcut, mask, t, xs[wv], hs[wv], w3s);
+    sensor_item<ND, DIR>(U, g, ph, w, zcut, mask, t);
 }
 
 template <int ND>
@@ -248,10 +239,6 @@ template <int ND, int DIR>
 __global__ void __launch_bounds__(256)
 k_sensor_line(const double *__restrict__ U, Grid g, Phys ph, const uint16_t *__restrict__ w, float zcut,
               uint8_t *__restrict__ mask, int64_t seg, int64_t nseg) {
-    __shared__ uint16_t xs[4][64 * 16], hs[4][64 * 32];
-    __shared__ float w3s[33];
-    if (threadIdx.x < 33) w3s[threadIdx.x] = bf2f(w[oW3 + threadIdx.x]);
-    __syncthreads();
     constexpr int O1 = DIR == 0 ? 1 : 0;
     constexpr int O2 = DIR == 2 ? 1 : 2;
     const int64_t lines = g.n[O1] * g.n[O2];
@@ -262,10 +249,10 @@ k_sensor_line(const double *__restrict__ U, Grid g, Phys ph, const uint16_t *__r
     const int64_t line0 = (gw - sg * wpl) << 6;
     const int64_t NI = g.n[DIR] + 1;
     const int64_t iq0 = sg * seg, iq1 = iq0 + seg < NI ? iq0 + seg : NI;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     MlpFrag F;
     load_frag(w, lane, F);
-    sensor_line<ND, DIR>(U, g, ph, F, zcut, mask, line0, iq0, iq1, xs[wv], hs[wv], w3s);
+    sensor_line<ND, DIR>(U, g, ph, F, zcut, mask, line0, iq0, iq1);
 }
 
 // x direction, rows of >= 64 interfaces: 64 interfaces per wave with the
@@ -274,18 +261,14 @@ template <int ND>
 __global__ void __launch_bounds__(256)
 k_sensor_xl(const double *__restrict__ U, Grid g, Phys ph, const uint16_t *__restrict__ w, float zcut,
             uint8_t *__restrict__ mask, int64_t totalJ) {
-    __shared__ uint16_t xs[4][64 * 16], hs[4][64 * 32];
-    __shared__ float w3s[33];
     __shared__ SxLds<ND> sp[4];
-    if (threadIdx.x < 33) w3s[threadIdx.x] = bf2f(w[oW3 + threadIdx.x]);
-    __syncthreads();
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t J0 = gw * 64;
     if (J0 >= totalJ) return;  // wave-uniform
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     MlpFrag F;
     load_frag(w, lane, F);
-    sensor_x_lanes<ND>(U, g, ph, F, zcut, mask, J0, totalJ, sp[wv], xs[wv], hs[wv], w3s);
+    sensor_x_lanes<ND>(U, g, ph, F, zcut, mask, J0, totalJ, sp[wv]);
 }
 
 template <int ND>

@@ -147,11 +147,21 @@ __host__ __device__ inline IfaceGrid iface_grid(const Grid &g, int d) {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-// per-lane operand fragments of v_mfma_f32_32x32x16_bf16:
-// B (K x N = 16 x 32): lane l holds column l % 32, rows 8 (l / 32) .. + 7
+// Network on the matrix cores, v_mfma_f32_32x32x16_bf16, computed transposed
+// (hidden units as rows, 32 samples of the wave as columns) so that each
+// layer's accumulators are the next layer's operands without leaving the
+// registers.  Operand layouts (lane l, h = l / 32): A holds row l % 32 at
+// K = 8h .. 8h+7; B holds column l % 32 at K = 8h .. 8h+7; D register r holds
+// row 8 (r / 4) + 4h + r % 4 of column l % 32.  The second layer sums over
+// the hidden units in the order the first layer's D registers hold them
+// (a permutation of the summation index, applied to W2 as well).
+__device__ __forceinline__ int drow(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
 struct MlpFrag {
-    bf16x8 w1, w2a, w2b;
-    float b1, b2;
+    bf16x8 w1;        // W1^T rows: W1[8h + i][l % 32]
+    bf16x8 w2[2];     // W2^T rows, summation index in D-register order
+    float b1[16], b2[16], w3[16];  // per D register of this lane half
+    float b3;
 };
 
 __device__ __forceinline__ bf16x8 pack8(const uint16_t (&u)[8]) {
@@ -161,79 +171,85 @@ __device__ __forceinline__ bf16x8 pack8(const uint16_t (&u)[8]) {
 }
 
 __device__ __forceinline__ void load_frag(const uint16_t *__restrict__ w, int lane, MlpFrag &F) {
-    const int j = lane & 31, kh = 8 * (lane >> 5);
+    const int j = lane & 31, h = lane >> 5;
     uint16_t u[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) u[i] = (kh + i < kIn) ? w[oW1 + (kh + i) * kH + j] : (uint16_t)0;
+    for (int i = 0; i < 8; ++i) u[i] = (8 * h + i < kIn) ? w[oW1 + (8 * h + i) * kH + j] : (uint16_t)0;
     F.w1 = pack8(u);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) u[i] = w[oW2 + (kh + i) * kH + j];
-    F.w2a = pack8(u);
+    for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) u[i] = w[oW2 + (16 + kh + i) * kH + j];
-    F.w2b = pack8(u);
-    F.b1 = bf2f(w[oB1 + j]);
-    F.b2 = bf2f(w[oB2 + j]);
+        for (int i = 0; i < 8; ++i) u[i] = w[oW2 + drow(8 * ks + i, h) * kH + j];
+        F.w2[ks] = pack8(u);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        F.b1[r] = bf2f(w[oB1 + drow(r, h)]);
+        F.b2[r] = bf2f(w[oB2 + drow(r, h)]);
+        F.w3[r] = bf2f(w[oW3 + drow(r, h)]);
+    }
+    F.b3 = bf2f(w[oB3]);
 }
 
+// LDS writes of this wave visible to its other lanes
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ int bf16pair(float a, float b) { return (int)f2bf(a) | ((int)f2bf(b) << 16); }
+
 // logit of the lane's own sample; every lane of the wave must call it.
-// xs: 64 x 16 bf16 scratch, hs: 64 x 32 bf16 scratch (per wave, LDS);
-// w3s: w3[0..31], b3 as floats (LDS).  Inputs and hidden activations are
-// rounded to bf16 (the A operands), accumulation is FP32.
-__device__ __forceinline__ float mlp_mfma(const float (&x)[kIn], const MlpFrag &F, uint16_t *xs, uint16_t *hs,
-                                          const float *w3s, int lane) {
+// Inputs and hidden activations are rounded to bfloat16 (the operands),
+// accumulation is FP32.
+__device__ __forceinline__ float mlp_mfma(const float (&x)[kIn], const MlpFrag &F, int lane) {
 #pragma clang fp contract(off)
+    const int h = lane >> 5;
+    // columns of tile t are the samples of lanes 32 t .. 32 t + 31: a lane
+    // supplies its own features 8h .. 8h+7 to its own tile and receives
+    // those of lane l ^ 32 for the other tile
+    int own[4], give[4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) xs[lane * 16 + k] = k < kIn ? f2bf(x[k]) : (uint16_t)0;
-    wave_sync();
-    const int r32 = lane & 31, kh = 8 * (lane >> 5), c = lane & 31;
-    f32x16 acc[2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-        bf16x8 a;
-        __builtin_memcpy(&a, xs + (rb * 32 + r32) * 16 + kh, sizeof a);
-        f32x16 zero = {0};
-        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, F.w1, zero, 0, 0, 0);
+    for (int q = 0; q < 4; ++q) {
+        const int k0 = 2 * q, k1 = 2 * q + 1;
+        const float lo0 = x[k0], lo1 = x[k1];
+        const float hi0 = 8 + k0 < kIn ? x[(8 + k0) % kIn] : 0.0f, hi1 = 8 + k1 < kIn ? x[(8 + k1) % kIn] : 0.0f;
+        own[q] = h == 0 ? bf16pair(lo0, lo1) : bf16pair(hi0, hi1);
+        give[q] = h == 0 ? bf16pair(hi0, hi1) : bf16pair(lo0, lo1);
     }
-    // D layout: register r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+    int b0[4], b1[4];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            hs[row * 32 + c] = f2bf(fmaxf(acc[rb][r] + F.b1, 0.0f));
-        }
-    wave_sync();
-    f32x16 acc2[2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-        bf16x8 a0, a1;
-        __builtin_memcpy(&a0, hs + (rb * 32 + r32) * 32 + kh, sizeof a0);
-        __builtin_memcpy(&a1, hs + (rb * 32 + r32) * 32 + 16 + kh, sizeof a1);
-        f32x16 zero = {0};
-        acc2[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, F.w2a, zero, 0, 0, 0);
-        acc2[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, F.w2b, acc2[rb], 0, 0, 0);
+    for (int q = 0; q < 4; ++q) {
+        const int got = __shfl_xor(give[q], 32, 64);
+        b0[q] = h == 0 ? own[q] : got;
+        b1[q] = h == 0 ? got : own[q];
     }
-    wave_sync();
+    bf16x8 B[2];
+    __builtin_memcpy(&B[0], b0, sizeof(bf16x8));
+    __builtin_memcpy(&B[1], b1, sizeof(bf16x8));
+    float part[2];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int t = 0; t < 2; ++t) {
+        const f32x16 zero = {0};
+        const f32x16 d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.w1, B[t], zero, 0, 0, 0);
+        uint16_t a0[8], a1[8];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            hs[row * 32 + c] = f2bf(fmaxf(acc2[rb][r] + F.b2, 0.0f));
+        for (int r = 0; r < 8; ++r) {
+            a0[r] = f2bf(fmaxf(d1[r] + F.b1[r], 0.0f));
+            a1[r] = f2bf(fmaxf(d1[8 + r] + F.b1[8 + r], 0.0f));
         }
-    wave_sync();
-    float z = w3s[32];
+        f32x16 d2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.w2[0], pack8(a0), zero, 0, 0, 0);
+        d2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.w2[1], pack8(a1), d2, 0, 0, 0);
+        float p = 0.0f;
 #pragma unroll
-    for (int j = 0; j < kH; ++j) z += bf2f(hs[lane * 32 + j]) * w3s[j];
-    wave_sync();  // scratch reused by the next call
-    return z;
+        for (int r = 0; r < 16; ++r) p += bf2f(f2bf(fmaxf(d2[r] + F.b2[r], 0.0f))) * F.w3[r];
+        part[t] = p;
+    }
+    // both halves of a column hold half of the output sum
+    const float mine = h == 0 ? part[0] : part[1];
+    const float other = __shfl_xor(h == 0 ? part[1] : part[0], 32, 64);
+    return F.b3 + (mine + other);
 }
 
 // routing decision of interface t (clamped to total - 1) of direction DIR;
@@ -241,7 +257,7 @@ __device__ __forceinline__ float mlp_mfma(const float (&x)[kIn], const MlpFrag &
 template <int ND, int DIR>
 __device__ __forceinline__ void sensor_item(const double *__restrict__ U, const Grid &g, const Phys &ph,
                                             const uint16_t *__restrict__ w, float zcut, uint8_t *__restrict__ mask,
-                                            int64_t t, uint16_t *xs, uint16_t *hs, const float *w3s) {
+                                            int64_t t) {
     const IfaceGrid I = iface_grid(g, DIR);
     const int lane = threadIdx.x & 63;
     const int64_t tc = t < I.total ? t : I.total - 1;
@@ -256,7 +272,7 @@ __device__ __forceinline__ void sensor_item(const double *__restrict__ U, const 
     features<ND, DIR>(U, e0, st, cs, ph, f);
     MlpFrag F;
     load_frag(w, lane, F);
-    const float z = mlp_mfma(f, F, xs, hs, w3s, lane);
+    const float z = mlp_mfma(f, F, lane);
     if (t < I.total) mask[t] = z >= zcut ? 1 : 0;
 }
 
@@ -269,7 +285,7 @@ __device__ __forceinline__ void sensor_item(const double *__restrict__ U, const 
 template <int ND, int DIR>
 __device__ __forceinline__ void sensor_line(const double *__restrict__ U, const Grid &g, const Phys &ph,
                                             const MlpFrag &F, float zcut, uint8_t *__restrict__ mask, int64_t line0,
-                                            int64_t iq0, int64_t iq1, uint16_t *xs, uint16_t *hs, const float *w3s) {
+                                            int64_t iq0, int64_t iq1) {
     constexpr int O1 = DIR == 0 ? 1 : 0;
     constexpr int O2 = DIR == 2 ? 1 : 2;
     const int lane = threadIdx.x & 63;
@@ -314,7 +330,7 @@ __device__ __forceinline__ void sensor_line(const double *__restrict__ U, const 
         }
         float f[kIn];
         sfeatures<ND>(P[2], P[3], T, lr, lp, ph, f);
-        const float z = mlp_mfma(f, F, xs, hs, w3s, lane);
+        const float z = mlp_mfma(f, F, lane);
         if (active) mask[mbase + iq * mst] = z >= zcut ? 1 : 0;
     }
 }
@@ -335,8 +351,7 @@ struct SxLds {
 template <int ND>
 __device__ __forceinline__ void sensor_x_lanes(const double *__restrict__ U, const Grid &g, const Phys &ph,
                                                const MlpFrag &F, float zcut, uint8_t *__restrict__ mask, int64_t J0,
-                                               int64_t totalJ, SxLds<ND> &sp, uint16_t *xs, uint16_t *hs,
-                                               const float *w3s) {
+                                               int64_t totalJ, SxLds<ND> &sp) {
     const int lane = threadIdx.x & 63;
     const int64_t N = g.n[0], NI = N + 1, n1 = g.n[1], cs = g.enpts;
     const int64_t J = J0 + lane;
@@ -383,7 +398,7 @@ __device__ __forceinline__ void sensor_x_lanes(const double *__restrict__ U, con
     for (int m = 0; m < 3; ++m) sjump<ND>(P[m + 1], P[m + 2], lr[m], lp[m]);
     float f[kIn];
     sfeatures<ND>(P[2], P[3], T, lr, lp, ph, f);
-    const float z = mlp_mfma(f, F, xs, hs, w3s, lane);
+    const float z = mlp_mfma(f, F, lane);
     if (valid) mask[J] = z >= zcut ? 1 : 0;
     wave_sync();  // the staging buffer is reused by the next call
 }
