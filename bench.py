@@ -503,6 +503,8 @@ def main():
         "hbm_compulsory_frac": round(npts * 3 * args.steps * cost.compulsory_bytes_per_point(3) / wall / 1e9
                                      / cost.PEAK_HBM_GBS, 4),
         "copy_ceiling_GBs": round(copy_gbs, 1),
+        "hbm_compulsory_frac_of_copy_ceiling": round(npts * 3 * args.steps * cost.compulsory_bytes_per_point(3)
+                                                     / wall / 1e9 / copy_gbs, 4),
         "roofline": roofline,
         "kernels": breakdown,
     }

@@ -15,10 +15,11 @@ constexpr int kNP = 1441;
 constexpr int kNPad = 1442;  // partial record: 1441 gradients + loss
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((unsigned)b) << 16); }
-__device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even
-    unsigned u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+__device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even (v_cvt_pk_bf16_f32)
+    const __bf16 b = (__bf16)x;
+    uint16_t u;
+    __builtin_memcpy(&u, &b, sizeof u);
+    return u;
 }
 
 // ------------------------------------------------------------ features
