@@ -89,7 +89,7 @@ typedef struct osbli_params {
     int32_t scheme;            /* enum osbli_scheme */
     double Ts_over_Tref;       /* Sutherland constant T_s / T_ref */
     double teno_CT;            /* TENO cut-off C_T */
-    double eps;                /* epsilon of the nonlinear weights (1e-16) */
+    double eps;                /* epsilon of the nonlinear weights (1e-16; accepted range [1e-40, 1]) */
     int32_t roe_avg;           /* 1: Roe average, 0: arithmetic mean of u, H */
     int32_t form;              /* enum osbli_form */
     int32_t sensor;            /* 1: learned-sensor routing (TENO5, separable mesh) */

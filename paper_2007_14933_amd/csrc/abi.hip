@@ -121,7 +121,7 @@ int make_grid(const osbli_params *p, Grid &g, char *buf, size_t nb) {
         snprintf(buf, nb, "teno_CT must lie in (0, 1/3)");
         return -1;
     }
-    if (!(p->eps > 0.0)) { snprintf(buf, nb, "eps must be positive"); return -1; }
+    if (!(p->eps >= 1e-40 && p->eps <= 1.0)) { snprintf(buf, nb, "eps must lie in [1e-40, 1]"); return -1; }
     return 0;
 }
 

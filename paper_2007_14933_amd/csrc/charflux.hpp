@@ -43,16 +43,21 @@ __device__ __forceinline__ void finish_point(const Phys &ph, Pt<ND> &w, bool &ba
 // tau_5 = |beta_0 - beta_2|; WENO-Z alpha_r = d_r (1 + (tau/(beta_r+eps))^2);
 // TENO gamma_r = (1 + tau/(beta_r+eps))^6, stencil r cut when
 // gamma_r / sum(gamma) < C_T (evaluated as gamma_r < C_T * sum), weights
-// d_r delta_r / sum(d delta).  The three ratios tau/(beta_r+eps) share one
-// reciprocal of the product of the denominators; TENO's normalisation is a
-// reciprocal of one of seven sums of optimal weights, skipped when no
-// stencil is cut (sum = 1).
-template <int SCHEME>
-__device__ __forceinline__ double recon5(double fm2, double fm1, double f0, double fp1, double fp2,
-                                         double CT, double eps, bool *kept = nullptr) {
-    const double q0 = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
-    const double q1 = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
-    const double q2 = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
+// d_r delta_r / sum(d delta).  The reconstruction is taken in two parts so
+// that the two of one LLF split share a single division: the candidate
+// values and the indicators (R5), then the weights given
+// t = tau / prod_r(beta_r+eps).  TENO's normalisation divides by one of
+// seven sums of optimal weights and is skipped when no stencil is cut
+// (sum = 1).
+struct R5 {
+    double q0, q1, q2, tau, e0, e1, e2;
+};
+
+__device__ __forceinline__ R5 recon5_ind(double fm2, double fm1, double f0, double fp1, double fp2, double eps) {
+    R5 r;
+    r.q0 = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
+    r.q1 = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
+    r.q2 = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
     double s, t;
     s = f0 - 2.0 * fp1 + fp2;
     t = 3.0 * f0 - 4.0 * fp1 + fp2;
@@ -63,16 +68,21 @@ __device__ __forceinline__ double recon5(double fm2, double fm1, double f0, doub
     s = fm2 - 2.0 * fm1 + f0;
     t = fm2 - 4.0 * fm1 + 3.0 * f0;
     const double b2 = (13.0 / 12.0) * s * s + 0.25 * t * t;
-    const double tau = fabs(b0 - b2);
-    const double e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
-    const double e01 = e0 * e1;
-    const double tinv = tau / (e01 * e2);
-    const double x0 = (e1 * e2) * tinv, x1 = (e0 * e2) * tinv, x2 = e01 * tinv;
+    r.tau = fabs(b0 - b2);
+    r.e0 = b0 + eps;
+    r.e1 = b1 + eps;
+    r.e2 = b2 + eps;
+    return r;
+}
+
+template <int SCHEME>
+__device__ __forceinline__ double recon5_fin(const R5 &r, double tinv, double CT, bool *kept) {
+    const double x0 = (r.e1 * r.e2) * tinv, x1 = (r.e0 * r.e2) * tinv, x2 = (r.e0 * r.e1) * tinv;
     if (SCHEME == OSBLI_WENOZ5) {
         const double a0 = 0.3 * (1.0 + x0 * x0);
         const double a1 = 0.6 * (1.0 + x1 * x1);
         const double a2 = 0.1 * (1.0 + x2 * x2);
-        return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+        return (a0 * r.q0 + a1 * r.q1 + a2 * r.q2) / (a0 + a1 + a2);
     } else {
         double c0 = 1.0 + x0, c1 = 1.0 + x1, c2 = 1.0 + x2;
         c0 = c0 * c0 * c0;
@@ -84,7 +94,7 @@ __device__ __forceinline__ double recon5(double fm2, double fm1, double f0, doub
         const double w0 = k0 ? 0.3 : 0.0;
         const double w1 = k1 ? 0.6 : 0.0;
         const double w2 = k2 ? 0.1 : 0.0;
-        const double num = w0 * q0 + w1 * q1 + w2 * q2;
+        const double num = w0 * r.q0 + w1 * r.q1 + w2 * r.q2;
         if (kept) *kept = *kept && k0 && k1 && k2;
         if (k0 && k1 && k2) return num;
         return num / (w0 + w1 + w2);
@@ -93,7 +103,13 @@ __device__ __forceinline__ double recon5(double fm2, double fm1, double f0, doub
 
 // LLF split of one characteristic field over the six points and the two
 // reconstructions: ghat = recon+(g+_{i-2..i+2}) + recon-(g-_{i+3..i-1}).
-template <int SCHEME>
+// SHARED: one division serves both sides: with D+- = prod_r(beta_r+eps),
+// tau+/D+ = tau+ D- / (D+ D-) and likewise for the other side (D+ D- >=
+// eps^6, which the accepted range of eps keeps a normal number).  This
+// saves five divisions per interface but keeps both sides' indicators live
+// at once, which the marching sweeps can afford and the lane-per-interface
+// sweep cannot (it spills), so that one divides per side.
+template <int SCHEME, bool SHARED>
 __device__ __forceinline__ double split_recon(const double (&V)[6], const double (&g)[6], double alpha,
                                               const Phys &ph, bool *kept = nullptr) {
     double gp[6], gm[6];
@@ -102,13 +118,24 @@ __device__ __forceinline__ double split_recon(const double (&V)[6], const double
         gp[k] = 0.5 * (g[k] + alpha * V[k]);
         gm[k] = 0.5 * (g[k] - alpha * V[k]);
     }
-    return recon5<SCHEME>(gp[0], gp[1], gp[2], gp[3], gp[4], ph.CT, ph.eps, kept) +
-           recon5<SCHEME>(gm[5], gm[4], gm[3], gm[2], gm[1], ph.CT, ph.eps, kept);
+    if (SHARED) {
+        const R5 a = recon5_ind(gp[0], gp[1], gp[2], gp[3], gp[4], ph.eps);
+        const R5 b = recon5_ind(gm[5], gm[4], gm[3], gm[2], gm[1], ph.eps);
+        const double da = (a.e0 * a.e1) * a.e2, db = (b.e0 * b.e1) * b.e2;
+        const double inv = 1.0 / (da * db);
+        return recon5_fin<SCHEME>(a, (a.tau * db) * inv, ph.CT, kept) +
+               recon5_fin<SCHEME>(b, (b.tau * da) * inv, ph.CT, kept);
+    } else {
+        const R5 a = recon5_ind(gp[0], gp[1], gp[2], gp[3], gp[4], ph.eps);
+        const double ha = recon5_fin<SCHEME>(a, a.tau / ((a.e0 * a.e1) * a.e2), ph.CT, kept);
+        const R5 b = recon5_ind(gm[5], gm[4], gm[3], gm[2], gm[1], ph.eps);
+        return ha + recon5_fin<SCHEME>(b, b.tau / ((b.e0 * b.e1) * b.e2), ph.CT, kept);
+    }
 }
 
 // Interface flux in the local frame (unit |S|).  Outputs: mass, normal
 // momentum, tangential momenta, energy.
-template <int ND, int SCHEME>
+template <int ND, int SCHEME, bool SHARED = true>
 __device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph, double &Fr, double &Fn,
                                           double (&Ft)[2], double &FE, bool *kept = nullptr) {
     constexpr int NT = ND - 1;  // tangents
@@ -158,21 +185,21 @@ __device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph,
         V[k] = 0.5 * (A[k] + B[k]);
         g[k] = unk[k] * V[k] + P[k].p * (0.5 * b * unk[k] - 0.5 * (b * un + ia));
     }
-    const double h0 = split_recon<SCHEME>(V, g, aminus, ph, kept);
+    const double h0 = split_recon<SCHEME, SHARED>(V, g, aminus, ph, kept);
     // field u_n + a
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         V[k] = 0.5 * (A[k] - B[k]);
         g[k] = unk[k] * V[k] + P[k].p * (0.5 * b * unk[k] - 0.5 * (b * un - ia));
     }
-    const double h4 = split_recon<SCHEME>(V, g, aplus, ph, kept);
+    const double h4 = split_recon<SCHEME, SHARED>(V, g, aplus, ph, kept);
     // entropy field
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         V[k] = P[k].r - A[k];
         g[k] = unk[k] * V[k] + P[k].p * (b * (un - unk[k]));
     }
-    const double h1 = split_recon<SCHEME>(V, g, a0, ph, kept);
+    const double h1 = split_recon<SCHEME, SHARED>(V, g, a0, ph, kept);
     // shear fields
     double ht[2] = {0.0, 0.0};
 #pragma unroll
@@ -182,7 +209,7 @@ __device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph,
             V[k] = P[k].mt[s] - ut[s] * P[k].r;
             g[k] = unk[k] * V[k];
         }
-        ht[s] = split_recon<SCHEME>(V, g, a0, ph, kept);
+        ht[s] = split_recon<SCHEME, SHARED>(V, g, a0, ph, kept);
     }
     // back to physical space: F = R ghat
     const double hs = h0 + h1 + h4;

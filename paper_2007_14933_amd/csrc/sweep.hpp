@@ -10,6 +10,25 @@ namespace cf {
 constexpr int kChunk = 8;   // x-points staged per cooperative load (x sweep)
 constexpr int kWaves = 4;   // waves per block
 
+// R += v (first: R = v) over the components of one node, with every load
+// issued before the first store: the stores could alias the later loads as
+// far as the compiler knows, so one load-add-store per component would wait
+// out the memory latency once per component.
+template <int NC>
+__device__ __forceinline__ void add_residual(double *__restrict__ R, int64_t nint, int64_t oi,
+                                             const double (&v)[NC], int first) {
+    if (first) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) R[c * nint + oi] = v[c];
+    } else {
+        double old[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) old[c] = R[c * nint + oi];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) R[c * nint + oi] = old[c] + v[c];
+    }
+}
+
 template <int ND, int DIR>
 struct Axes {
     static constexpr int T1 = (DIR + 1) % ND;
@@ -30,6 +49,9 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
     constexpr int NT = ND - 1;
     constexpr int O1 = DIR == 0 ? 1 : 0;
     constexpr int O2 = DIR == 2 ? 1 : 2;
+    // 1/h along the line: read only, so (with the wave-uniform segment) the
+    // per-node factor is a scalar load
+    const double *__restrict__ ih = m.invh[DIR];
     const int64_t n1 = g.n[O1], n2 = g.n[O2], N = g.n[DIR];
     const int64_t lines = n1 * n2;
     const int lane = threadIdx.x & 63;
@@ -124,6 +146,10 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
             for (int k = 0; k < 4; ++k) mw[k] = mw[k + 1];
             mw[4] = mload(f + 2);
         }
+        // the node's metric factor, loaded with the new point so that the
+        // two share one wait
+        const int64_t fs = f >= p0 ? f : p0;
+        const double sc = GEN ? m.J[base + fs * st] : ih[fs];
         if (f >= p0) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) w[k] = w[k + 1];
@@ -227,15 +253,10 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
             }
         }
         if (f >= p0 && active) {
-            const double sc = GEN ? m.J[base + f * st] : m.invh[DIR][f];
-            const int64_t oi = ibase + f * ist;
+            double v[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const double v = -sc * (F[c] - Fp[c]);
-                double *dst = R + c * g.nint + oi;
-                if (first) *dst = v;
-                else *dst += v;
-            }
+            for (int c = 0; c < NC; ++c) v[c] = -sc * (F[c] - Fp[c]);
+            add_residual<NC>(R, g.nint, ibase + f * ist, v, first);
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) Fp[c] = F[c];
@@ -258,7 +279,9 @@ k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, M
     constexpr int O2 = DIR == 2 ? 1 : 2;
     const int64_t lines = g.n[O1] * g.n[O2];
     const int64_t wpl = (lines + 63) >> 6;  // waves per segment
-    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    // wave index made explicitly uniform, so that the segment bounds and the
+    // loop over it live in scalar registers
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t sg = gw / wpl;
     if (sg >= nseg) return;  // wave-uniform
     const int64_t line0 = (gw - sg * wpl) << 6;
@@ -306,10 +329,7 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
     const int Lnext = (int)(NI - (q0 + 1));  // lane index where row0 + 1 starts (>= 64: none)
     bool bad = false;
 
-    auto stage = [&](int slot, int64_t base, int64_t pos) {
-        Pt<ND> w;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) w.U[c] = U[base + pos + c * cs];
+    auto put = [&](int slot, Pt<ND> &w) {
         finish_point<ND>(ph, w, bad);
 #pragma unroll
         for (int c = 0; c < NC; ++c) sm.pt[c][slot] = w.U[c];
@@ -317,15 +337,31 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
         sm.pt[NC + 1][slot] = w.p;
         sm.pt[NC + 2][slot] = w.a;
     };
-    stage(lane, rowb, q + 3);
+    // Every lane stages the point q + 3 of its row.  Lanes 0..4 also stage
+    // the points q0 - 2 .. q0 + 2 of lane 0's row, lanes 5..9 the points
+    // -3 .. 1 of a row starting inside the wave; the other lanes read their
+    // own point a second time (a cache hit), so that all loads of the wave
+    // are in flight together.
+    int64_t xb = rowb, xp = q + 3;
+    bool extra = false;
     if (lane < 5) {
-        // points q0 - 2 .. q0 + 2 of lane 0's row
-        stage(64 + lane, ext_index(g, 0, row0 % n1, row0 / n1), q0 - 2 + lane);
+        xb = ext_index(g, 0, row0 % n1, row0 / n1);
+        xp = q0 - 2 + lane;
+        extra = true;
     } else if (lane < 10 && Lnext < 64) {
-        // points -3 .. 1 of the row starting inside the wave
         const int64_t r1 = row0 + 1 < totalJ / NI ? row0 + 1 : row0;
-        stage(64 + lane, ext_index(g, 0, r1 % n1, r1 / n1), (int64_t)(lane - 5) - 3);
+        xb = ext_index(g, 0, r1 % n1, r1 / n1);
+        xp = (int64_t)(lane - 5) - 3;
+        extra = true;
     }
+    Pt<ND> w0, w1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        w0.U[c] = U[rowb + q + 3 + c * cs];
+        w1.U[c] = U[xb + xp + c * cs];
+    }
+    put(lane, w0);
+    if (extra) put(64 + lane, w1);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -360,7 +396,7 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
         else cheap_flux<ND>(P, ph, Fr, Fn, Ft, FE);
     } else {
         if (MIX) char_flux_mixed<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
-        else char_flux<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
+        else char_flux<ND, SCHEME, false>(P, ph, Fr, Fn, Ft, FE);
     }
     double F[NC];
     F[0] = Fr;
@@ -377,13 +413,10 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
     if (valid && lane >= 1 && q >= 0 && lane != Lnext) {
         const double sc = m.invh[0][q];
         const int64_t oi = (row % n1) * g.is[1] + (row / n1) * g.is[2] + q;
+        double v[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double v = -sc * (F[c] - sm.fl[c][lane - 1]);
-            double *dst = R + c * g.nint + oi;
-            if (first) *dst = v;
-            else *dst += v;
-        }
+        for (int c = 0; c < NC; ++c) v[c] = -sc * (F[c] - sm.fl[c][lane - 1]);
+        add_residual<NC>(R, g.nint, oi, v, first);
     }
     if (bad) atomicOr(flags, kFlagNonPhys);
 }

@@ -65,6 +65,8 @@ def test_workspace_sizes(lib):
     (lambda p: setattr(p, "gamma", 1.0), "gamma"),
     (lambda p: setattr(p, "teno_CT", 0.5), "C_T"),
     (lambda p: setattr(p, "form", 9), "form"),
+    (lambda p: setattr(p, "eps", 1e-60), "eps below the range whose sixth power stays normal"),
+    (lambda p: setattr(p, "eps", 0.0), "eps zero"),
 ])
 def test_invalid_parameters_rejected_without_device(lib, mutate, why):
     p = B.make_params(I.tgv(8))
