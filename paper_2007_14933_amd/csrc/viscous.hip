@@ -30,10 +30,43 @@ __device__ __forceinline__ double dline(const At &at, int64_t p, int64_t N, bool
     return (3.0 * at(N - 5) - 16.0 * at(N - 4) + 36.0 * at(N - 3) - 48.0 * at(N - 2) + 25.0 * at(N - 1)) / 12.0;
 }
 
-// pointwise kernels: blocks of 64 x 4 threads over (i, j), grid.z over k
+// pointwise kernels: blocks of 64 x 4 threads over (i, j) of one k plane
 constexpr int kBX = 64, kBY = 4;
 
-__device__ __forceinline__ bool node_of_thread(const Grid &g, int64_t (&idx)[3]) {
+// Tile placement: workgroups go to the eight XCDs (each with its own L2) in
+// turn, so a 1D grid of 8 * per blocks is used and the linear block id b is
+// remapped to the tile (b % 8) * per + b / 8: each XCD then owns one
+// contiguous run of tiles (x fastest, then y, then z), and the stencil
+// neighbours that adjacent tiles share are read through one L2.
+constexpr int kXcds = 8;
+
+struct NodeTiles {
+    int tx, ty, nt, per;  // tiles along x, along y, in all; tiles per XCD
+};
+
+inline NodeTiles node_tiles(const Grid &g) {
+    NodeTiles T;
+    T.tx = (int)((g.n[0] + kBX - 1) / kBX);
+    T.ty = (int)((g.n[1] + kBY - 1) / kBY);
+    T.nt = T.tx * T.ty * (int)g.n[2];
+    T.per = (T.nt + kXcds - 1) / kXcds;
+    return T;
+}
+
+inline dim3 node_launch(const NodeTiles &T) { return dim3((unsigned)(T.per * kXcds)); }
+
+__device__ __forceinline__ bool node_of_thread(const Grid &g, const NodeTiles &T, int64_t (&idx)[3]) {
+    const int L = (int)(blockIdx.x % kXcds) * T.per + (int)(blockIdx.x / kXcds);
+    if (L >= T.nt) return false;
+    const int bx = L % T.tx, by = (L / T.tx) % T.ty;
+    idx[0] = (int64_t)bx * kBX + threadIdx.x;
+    idx[1] = (int64_t)by * kBY + threadIdx.y;
+    idx[2] = L / (T.tx * T.ty);
+    return idx[0] < g.n[0] && idx[1] < g.n[1];
+}
+
+// the plain 3D grid: blockIdx (x, y) over the plane's tiles, blockIdx.z the plane
+__device__ __forceinline__ bool node_of_plane_thread(const Grid &g, int64_t (&idx)[3]) {
     idx[0] = (int64_t)blockIdx.x * kBX + threadIdx.x;
     idx[1] = (int64_t)blockIdx.y * kBY + threadIdx.y;
     idx[2] = blockIdx.z;
@@ -159,10 +192,10 @@ __device__ __forceinline__ void visc_store(const double (&phi0)[ND + 1], const d
 
 template <int ND, bool GEN>
 __global__ void __launch_bounds__(256)
-k_visc_flux(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys ph, Metrics m) {
+k_visc_flux(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys ph, Metrics m, NodeTiles T) {
     constexpr int NV = ND + 1;
     int64_t idx[3];
-    if (!node_of_thread(g, idx)) return;
+    if (!node_of_thread(g, T, idx)) return;
     const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
     const int64_t e0 = ext_index(g, idx[0], idx[1], idx[2]);
     const int64_t cs = g.enpts;
@@ -183,15 +216,22 @@ k_visc_flux(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys p
 constexpr int kZX = 64, kZY = 8, kZC = 32;
 constexpr int kHX = kZX + 4, kHY = kZY + 4;
 
+// Tiles are placed on the XCDs as the node tiles are (one contiguous run of
+// tiles per XCD), so that the halo columns shared by neighbouring tiles are
+// read through one L2.
 __global__ void __launch_bounds__(kZX * kZY, 4)
-k_visc_flux_zm(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys ph, Metrics m) {
+k_visc_flux_zm(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys ph, Metrics m, int tx_n,
+               int ty_n, int ntiles, int per) {
     constexpr int NV = 4;
     __shared__ double tile[2][NV][kHY][kHX];
+    const int L = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    if (L >= ntiles) return;  // block-uniform
+    const int bx = L % tx_n, by = (L / tx_n) % ty_n, bz = L / (tx_n * ty_n);
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kZX + tx;
-    const int64_t x0 = (int64_t)blockIdx.x * kZX, y0 = (int64_t)blockIdx.y * kZY;
+    const int64_t x0 = (int64_t)bx * kZX, y0 = (int64_t)by * kZY;
     const int64_t x = x0 + tx, y = y0 + ty;
     const int64_t Nx = g.n[0], Ny = g.n[1], Nz = g.n[2];
-    const int64_t z0 = (int64_t)blockIdx.z * kZC;
+    const int64_t z0 = (int64_t)bz * kZC;
     const int64_t z1 = z0 + kZC < Nz ? z0 + kZC : Nz;
     const bool own = x < Nx && y < Ny;
     const int64_t xc = x < Nx ? x : Nx - 1, yc = y < Ny ? y : Ny - 1;
@@ -264,7 +304,7 @@ k_finish(const double *Racc, const double *__restrict__ G, double *Rout, Grid g,
     constexpr int NC = ND + 2;
     constexpr int NV = ND + 1;
     int64_t idx[3];
-    if (!node_of_thread(g, idx)) return;
+    if (!node_of_plane_thread(g, idx)) return;
     const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
     double R[NC];
 #pragma unroll
@@ -345,6 +385,9 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int n) {
 template <int ND, bool GEN>
 hipError_t finish_nd(const Grid &g, const Phys &ph, const Metrics &m, const double *Racc, const double *G,
                      double *Rout, int stage, double dt, double *U, double *dU, int mode, hipStream_t s) {
+    // plane-major order on every XCD: the finish reads its z neighbours'
+    // fluxes best when all XCDs advance through the planes together (the
+    // per-XCD runs of node_tiles measured slower here)
     const dim3 nb = node_grid(g), bs(kBX, kBY);
     if (ph.viscous) {
         if (mode == 0)
@@ -368,21 +411,24 @@ hipError_t finish_nd(const Grid &g, const Phys &ph, const Metrics &m, const doub
 
 hipError_t launch_viscous_fluxes(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *G,
                                  hipStream_t s) {
-    const dim3 nb = node_grid(g), bs(kBX, kBY);
+    const NodeTiles T = node_tiles(g);
+    const dim3 nb = node_launch(T), bs(kBX, kBY);
     const bool gen = m.general != 0;
     switch (g.nd) {
-        case 1: hipLaunchKernelGGL((k_visc_flux<1, false>), nb, bs, 0, s, U, G, g, ph, m); break;
+        case 1: hipLaunchKernelGGL((k_visc_flux<1, false>), nb, bs, 0, s, U, G, g, ph, m, T); break;
         case 2:
-            if (gen) hipLaunchKernelGGL((k_visc_flux<2, true>), nb, bs, 0, s, U, G, g, ph, m);
-            else hipLaunchKernelGGL((k_visc_flux<2, false>), nb, bs, 0, s, U, G, g, ph, m);
+            if (gen) hipLaunchKernelGGL((k_visc_flux<2, true>), nb, bs, 0, s, U, G, g, ph, m, T);
+            else hipLaunchKernelGGL((k_visc_flux<2, false>), nb, bs, 0, s, U, G, g, ph, m, T);
             break;
         default:
             if (gen) {
-                hipLaunchKernelGGL((k_visc_flux<3, true>), nb, bs, 0, s, U, G, g, ph, m);
+                hipLaunchKernelGGL((k_visc_flux<3, true>), nb, bs, 0, s, U, G, g, ph, m, T);
             } else {
-                const dim3 zb((unsigned)((g.n[0] + kZX - 1) / kZX), (unsigned)((g.n[1] + kZY - 1) / kZY),
-                              (unsigned)((g.n[2] + kZC - 1) / kZC));
-                hipLaunchKernelGGL(k_visc_flux_zm, zb, dim3(kZX, kZY), 0, s, U, G, g, ph, m);
+                const int tx_n = (int)((g.n[0] + kZX - 1) / kZX), ty_n = (int)((g.n[1] + kZY - 1) / kZY);
+                const int ntiles = tx_n * ty_n * (int)((g.n[2] + kZC - 1) / kZC);
+                const int per = (ntiles + kXcds - 1) / kXcds;
+                hipLaunchKernelGGL(k_visc_flux_zm, dim3((unsigned)(per * kXcds)), dim3(kZX, kZY), 0, s, U, G, g, ph,
+                                   m, tx_n, ty_n, ntiles, per);
             }
     }
     return hipGetLastError();
