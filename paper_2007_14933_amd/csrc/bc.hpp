@@ -43,20 +43,33 @@ __device__ __forceinline__ void ghost_fill(double *__restrict__ U, const Grid &g
     const int64_t cs = g.enpts;
     const int64_t sg = side ? -1 : 1;
     const int64_t st = g.es[dir];
+    // Periodic and extrapolated ghosts: every source value is read before the
+    // first ghost is written (sources are nodes inside the line, ghosts lie
+    // outside it, so the two sets are disjoint); interleaved copies would
+    // wait out the memory latency once per value.
     if (kind == OSBLI_PERIODIC) {
+        double v[kGhost][NC];
+#pragma unroll
+        for (int m = 1; m <= kGhost; ++m) {
+            const int64_t es = ew - sg * m * st + sg * N * st;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[m - 1][c] = U[es + c * cs];
+        }
 #pragma unroll
         for (int m = 1; m <= kGhost; ++m) {
             const int64_t eg = ew - sg * m * st;
-            const int64_t es = eg + sg * N * st;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) U[eg + c * cs] = U[es + c * cs];
+            for (int c = 0; c < NC; ++c) U[eg + c * cs] = v[m - 1][c];
         }
     } else if (kind == OSBLI_EXTRAPOLATE) {
+        double v[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = U[ew + c * cs];
 #pragma unroll
         for (int m = 1; m <= kGhost; ++m) {
             const int64_t eg = ew - sg * m * st;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) U[eg + c * cs] = U[ew + c * cs];
+            for (int c = 0; c < NC; ++c) U[eg + c * cs] = v[c];
         }
     } else {
         double uw[3], u1[3];

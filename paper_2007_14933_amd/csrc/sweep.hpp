@@ -150,10 +150,17 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
         // two share one wait
         const int64_t fs = f >= p0 ? f : p0;
         const double sc = GEN ? m.J[base + fs * st] : ih[fs];
+        double rold[NC];
         if (f >= p0) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) w[k] = w[k + 1];
             fetch(f + 3, w[5]);
+            // this node's residual so far, requested now and used after the
+            // flux: its memory latency hides behind the flux arithmetic
+            if (!first) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) rold[c] = R[c * g.nint + ibase + f * ist];
+            }
             if (GEN) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
@@ -256,7 +263,13 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
             double v[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) v[c] = -sc * (F[c] - Fp[c]);
-            add_residual<NC>(R, g.nint, ibase + f * ist, v, first);
+            if (first) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) R[c * g.nint + ibase + f * ist] = v[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) R[c * g.nint + ibase + f * ist] = rold[c] + v[c];
+            }
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c) Fp[c] = F[c];
