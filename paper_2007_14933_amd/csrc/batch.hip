@@ -119,6 +119,7 @@ __global__ void __launch_bounds__(256, 2)
 k_b_sweep(const BProb *__restrict__ pr, const BState *__restrict__ st, const int64_t *__restrict__ off, int P,
           int64_t total, Phys ph, int first, unsigned *flags) {
     __shared__ double sbuf[DIR == 0 ? kWaves : 1][4][kChunk][64];
+    __shared__ double abuf[DIR == 0 ? 1 : kWaves][2][5][64];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * kWaves;
     for (int64_t wt = (int64_t)blockIdx.x * kWaves + wv; wt < total; wt += nw) {
@@ -129,8 +130,18 @@ k_b_sweep(const BProb *__restrict__ pr, const BState *__restrict__ st, const int
         const int64_t sg = local / b.wpl[DIR];
         const int64_t line0 = (local - sg * b.wpl[DIR]) << 6;
         const Metrics m = sep_metrics(b);
-        sweep_wave<2, DIR, SCHEME, false, MIX, ROUTE>(b.U, b.R, b.g, ph, m, b.seg[DIR], sg, line0, first, flags,
-                                                      ROUTE ? b.mask[DIR] : nullptr, sbuf[DIR == 0 ? wv : 0]);
+        const uint8_t *mk = ROUTE ? b.mask[DIR] : nullptr;
+        if constexpr (DIR != 0) {
+            if ((line0 % b.g.n[0]) + 64 <= b.g.n[0] && line0 + 64 <= b.g.n[0] * b.g.n[2])  // 64 consecutive x nodes
+                sweep_wave<2, DIR, SCHEME, false, MIX, ROUTE, true>(b.U, b.R, b.g, ph, m, b.seg[DIR], sg, line0,
+                                                                    first, flags, mk, sbuf[0], abuf[wv]);
+            else
+                sweep_wave<2, DIR, SCHEME, false, MIX, ROUTE, false>(b.U, b.R, b.g, ph, m, b.seg[DIR], sg, line0,
+                                                                     first, flags, mk, sbuf[0], abuf[wv]);
+        } else {
+            sweep_wave<2, DIR, SCHEME, false, MIX, ROUTE, false>(b.U, b.R, b.g, ph, m, b.seg[DIR], sg, line0, first,
+                                                                 flags, mk, sbuf[wv], abuf[0]);
+        }
     }
 }
 

@@ -38,13 +38,19 @@ struct Axes {
 template <int ND>
 using SweepLds = double[ND + 2][kChunk][64];
 
+// ahead-load buffer of one wave of a y or z sweep: two slots of one point's
+// NC component rows (plus a spare row for odd NC)
+template <int ND>
+using AheadLds = double[2][ND + 3][64];
+
 // The work of one wave: lines line0 .. line0+63 (clamped), segment sg of
-// length seg along DIR.  sbuf: this wave's staging buffer (x sweep only).
-template <int ND, int DIR, int SCHEME, bool GEN, bool MIX, bool ROUTE>
+// length seg along DIR.  sbuf: this wave's staging buffer (x sweep only);
+// ab: this wave's ahead-load buffer (y and z sweeps).
+template <int ND, int DIR, int SCHEME, bool GEN, bool MIX, bool ROUTE, bool AHEAD>
 __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double *__restrict__ R, const Grid &g,
                                            const Phys &ph, const Metrics &m, int64_t seg, int64_t sg, int64_t line0,
                                            int first, unsigned *flags, const uint8_t *__restrict__ mask,
-                                           SweepLds<ND> &sb) {
+                                           SweepLds<ND> &sb, AheadLds<ND> &ab) {
     constexpr int NC = ND + 2;
     constexpr int NT = ND - 1;
     constexpr int O1 = DIR == 0 ? 1 : 0;
@@ -70,6 +76,44 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
     const int64_t ibase = int_index(g, q[0], q[1], q[2]);
     const int64_t ist = g.is[DIR];
     bool bad = false;
+
+    // Ahead-loading (AHEAD: y and z sweeps of separable meshes, for waves
+    // whose 64 lines are 64 consecutive nodes of one x row, so that each
+    // component of a point is one contiguous 512-byte row): the point needed
+    // by the next step is copied from HBM straight into LDS while this step
+    // computes (global-to-LDS loads, 16 bytes per lane: lanes 0..31 carry one
+    // component row, lanes 32..63 the next), and the step after reads it from
+    // LDS; without this the march waits out one HBM latency per step.  The
+    // caller picks the variant per wave; the two are separate code, so
+    // neither pays the other's registers.
+    static_assert(!AHEAD || (DIR != 0 && !GEN), "ahead-loading is for y and z sweeps of separable meshes");
+    constexpr bool ahead = AHEAD;
+    int64_t base0 = 0;
+    if (ahead) {
+        int64_t q0[3];
+        q0[DIR] = 0;
+        q0[O1] = line0 % n1;
+        q0[O2] = line0 / n1;
+        base0 = ext_index(g, q0[0], q0[1], q0[2]);  // lane l's line starts at base0 + l
+    }
+    auto load_ahead = [&](int64_t qp, int slot) {
+        const int half = lane >> 5;
+        const int64_t d = 2 * (lane & 31);
+#pragma unroll
+        for (int i = 0; i < (NC + 1) / 2; ++i) {
+            const int c = 2 * i + half < NC ? 2 * i + half : NC - 1;
+            __builtin_amdgcn_global_load_lds((const void *)(U + base0 + qp * st + c * cs + d),
+                                             (__attribute__((address_space(3))) void *)&ab[slot][2 * i][0], 16,
+                                             0, 0);
+        }
+    };
+    auto read_ahead = [&](int slot, Pt<ND> &w) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the slot's global-to-LDS load has landed
+        __builtin_amdgcn_sched_barrier(0);   // and no LDS read is scheduled above that wait
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w.U[c] = ab[slot][c][lane];
+        finish_point<ND>(ph, w, bad);
+    };
 
     int64_t cbase = p0 - 3 - kChunk;  // first point held in the chunk buffer
     // point q's conserved state into w (from LDS along x, directly otherwise)
@@ -107,6 +151,7 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
     Pt<ND> w[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) fetch(p0 - 3 + k, w[k]);
+    if (ahead && p0 < p1) load_ahead(p0 + 3, (int)((p0 + 3) & 1));
 
     // general meshes: node area vectors S_DIR at f-1 .. f+2 for interface f+1/2
     double Sw[4][3];
@@ -146,15 +191,16 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
             for (int k = 0; k < 4; ++k) mw[k] = mw[k + 1];
             mw[4] = mload(f + 2);
         }
-        // the node's metric factor, loaded with the new point so that the
-        // two share one wait
-        const int64_t fs = f >= p0 ? f : p0;
-        const double sc = GEN ? m.J[base + fs * st] : ih[fs];
         double rold[NC];
         if (f >= p0) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) w[k] = w[k + 1];
-            fetch(f + 3, w[5]);
+            if (ahead) {
+                read_ahead((int)((f + 3) & 1), w[5]);
+                if (f + 1 < p1) load_ahead(f + 4, (int)((f + 4) & 1));
+            } else {
+                fetch(f + 3, w[5]);
+            }
             // this node's residual so far, requested now and used after the
             // flux: its memory latency hides behind the flux arithmetic
             if (!first) {
@@ -170,6 +216,10 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
                 for (int c = 0; c < ND; ++c) Sw[3][c] = m.S[(DIR * ND + c) * cs + base + (f + 2) * st];
             }
         }
+        // the node's metric factor, requested after the new point (whose wait
+        // would otherwise cover it too) and used with the residual
+        const int64_t fs = f >= p0 ? f : p0;
+        const double sc = GEN ? m.J[base + fs * st] : ih[fs];
         Loc<ND> P[6];
         double F[NC];
         double Smag = 1.0;
@@ -288,6 +338,7 @@ __global__ void __launch_bounds__(256, GEN ? 1 : 2)
 k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t seg,
         int64_t nseg, int first, unsigned *flags, const uint8_t *__restrict__ mask) {
     __shared__ double sbuf[DIR == 0 ? kWaves : 1][ND + 2][kChunk][64];
+    __shared__ double abuf[DIR == 0 || GEN ? 1 : kWaves][2][ND + 3][64];
     constexpr int O1 = DIR == 0 ? 1 : 0;
     constexpr int O2 = DIR == 2 ? 1 : 2;
     const int64_t lines = g.n[O1] * g.n[O2];
@@ -298,8 +349,19 @@ k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, M
     const int64_t sg = gw / wpl;
     if (sg >= nseg) return;  // wave-uniform
     const int64_t line0 = (gw - sg * wpl) << 6;
-    sweep_wave<ND, DIR, SCHEME, GEN, MIX, ROUTE>(U, R, g, ph, m, seg, sg, line0, first, flags, mask,
-                                                 sbuf[DIR == 0 ? (threadIdx.x >> 6) : 0]);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if constexpr (DIR != 0 && !GEN) {
+        const int64_t n1 = g.n[O1];
+        if ((line0 % n1) + 64 <= n1 && line0 + 64 <= lines)  // wave-uniform: 64 consecutive x nodes
+            sweep_wave<ND, DIR, SCHEME, GEN, MIX, ROUTE, true>(U, R, g, ph, m, seg, sg, line0, first, flags, mask,
+                                                               sbuf[0], abuf[wv]);
+        else
+            sweep_wave<ND, DIR, SCHEME, GEN, MIX, ROUTE, false>(U, R, g, ph, m, seg, sg, line0, first, flags, mask,
+                                                                sbuf[0], abuf[wv]);
+    } else {
+        sweep_wave<ND, DIR, SCHEME, GEN, MIX, ROUTE, false>(U, R, g, ph, m, seg, sg, line0, first, flags, mask,
+                                                            sbuf[DIR == 0 ? wv : 0], abuf[0]);
+    }
 }
 
 // ---------------------------------------------------------------------------
