@@ -133,8 +133,10 @@ int osbli_residual(osbli_ctx *ctx, const double *U, double *R, void *stream);
 /* One Runge-Kutta substage (section 2.7, three stages, 2N form):
  *   dU <- A_s dU + dt R(U),  U <- U + B_s dU,
  * with (A, B) = ((0, -5/9, -153/128), (1/3, 15/16, 8/15)); stage 0 ignores
- * the incoming dU.  Does not apply boundary conditions.  U (ghosted layout)
- * and dU (interior layout) must not alias. */
+ * the incoming dU, and stage 2 does not store it (the register is not read
+ * again before the next stage 0), so dU holds the stage-1 value after a
+ * whole step.  Does not apply boundary conditions.  U (ghosted layout) and
+ * dU (interior layout) must not alias. */
 int osbli_rk_substep(osbli_ctx *ctx, int stage, double dt, double *U, double *dU, void *stream);
 
 /* dt = cfl / max over interior nodes of

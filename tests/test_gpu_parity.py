@@ -178,3 +178,40 @@ def test_x_sweep_lanes_equal_marching(name, form):
         err = np.abs(Ra - Ro).max(axis=tuple(range(1, Ra.ndim))) / scale
         say("   residual |diff| / flux scale:", err)
         assert err.max() <= TOL_ONE, err
+
+
+def test_rk_substages_and_register_contract():
+    """Each of the three low-storage substages against the oracle's (U after
+    every stage, dU after stages 0 and 1), and the documented register
+    contract: stage 2 leaves dU as stage 1 stored it."""
+    prob = I.tgv(20)
+    say("[gpu parity rk stages]", prob.name, prob.n)
+    from paper_2007_14933_amd.solver import Solver
+    s = Solver(prob)
+    S, J = O.metrics(prob)
+    Uo = prob.U0.copy()
+    dUo = np.zeros(O.int_shape(prob))
+    s.apply_bc()
+    Uo = O.apply_bc(prob, Uo)
+    dt = O.compute_dt(prob, S, J, Uo, 0.5)
+    dU1 = None
+    for stage in range(3):
+        # dU = A dU + dt R: its rounding is that of R, relative to the flux scale
+        scale = dt * flux_scale(prob, Uo, J, S)
+        s.substep(stage, dt)
+        O.rk_substep(prob, S, J, stage, dt, Uo, dUo)
+        Ug = s.state()
+        err = normwise_rel(O.interior(prob, Ug), O.interior(prob, Uo))
+        dUg = s.dU.cpu().numpy()
+        say("   stage %d: U normwise rel diff %s" % (stage, err))
+        assert err.max() <= TOL_ONE, (stage, err)
+        if stage < 2:
+            derr = np.abs(dUg - dUo).max(axis=(1, 2, 3)) / scale
+            say("   stage %d: dU |diff| / (dt flux scale) %s" % (stage, derr))
+            assert derr.max() <= 2 * TOL_ONE, (stage, derr)
+            dU1 = dUg.copy()
+        else:
+            assert np.array_equal(dUg, dU1)
+        s.apply_bc()
+        Uo = O.apply_bc(prob, Uo)
+    s.check()
