@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256, 3)
 k_b_sweep_xl(const BProb *__restrict__ pr, const BState *__restrict__ st, const int64_t *__restrict__ off, int P,
              int64_t total, Phys ph, int first, unsigned *flags) {
     __shared__ XlLds<2> sm[kWaves];
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * kWaves;
     for (int64_t wt = (int64_t)blockIdx.x * kWaves + wv; wt < total; wt += nw) {
         const int p = find_prob(off, P, wt);

@@ -396,12 +396,29 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
     const int64_t J = J0 + lane;
     const bool valid = J < totalJ;
     const int64_t Jc = valid ? J : totalJ - 1;
-    const int64_t row = Jc / NI;
-    const int64_t q = Jc - row * NI - 1;
-    const int64_t rowb = ext_index(g, 0, row % n1, row / n1);
     // wave-uniform: lane 0's row and interface, and the first lane of the next row
-    const int64_t row0 = J0 / NI, q0 = J0 - row0 * NI - 1;
+    // (scalar divisions, in 32 bits whenever the interface count allows)
+    const bool narrow = totalJ < 0x7fffffff;
+    auto sdiv = [narrow](int64_t a, int64_t b) -> int64_t {
+        return narrow ? (int64_t)((uint32_t)a / (uint32_t)b) : a / b;
+    };
+    const int64_t row0 = sdiv(J0, NI), q0 = J0 - row0 * NI - 1;
     const int Lnext = (int)(NI - (q0 + 1));  // lane index where row0 + 1 starts (>= 64: none)
+    // The lane's row and interface without a per-lane division: a wave spans
+    // at most two rows (NI >= 64), row0 and row0 + 1, whose (y, z) are
+    // scalars; lanes past the last interface take the last one.
+    const int64_t z0 = sdiv(row0, n1), y0 = row0 - z0 * n1;
+    const int64_t y1 = y0 + 1 < n1 ? y0 + 1 : 0, z1 = y0 + 1 < n1 ? z0 : z0 + 1;
+    const int64_t rows = n1 * g.n[2];  // totalJ = rows * NI
+    const bool nxt = lane >= Lnext;
+    int64_t yl = nxt ? y1 : y0, zl = nxt ? z1 : z0;
+    int64_t q = nxt ? (int64_t)(lane - Lnext) - 1 : q0 + lane;
+    if (!valid) {
+        yl = n1 - 1;
+        zl = g.n[2] - 1;
+        q = N - 1;
+    }
+    const int64_t rowb = ext_index(g, 0, yl, zl);
     bool bad = false;
 
     auto put = [&](int slot, Pt<ND> &w) {
@@ -420,12 +437,12 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
     int64_t xb = rowb, xp = q + 3;
     bool extra = false;
     if (lane < 5) {
-        xb = ext_index(g, 0, row0 % n1, row0 / n1);
+        xb = ext_index(g, 0, y0, z0);
         xp = q0 - 2 + lane;
         extra = true;
     } else if (lane < 10 && Lnext < 64) {
-        const int64_t r1 = row0 + 1 < totalJ / NI ? row0 + 1 : row0;
-        xb = ext_index(g, 0, r1 % n1, r1 / n1);
+        const bool has1 = row0 + 1 < rows;
+        xb = ext_index(g, 0, has1 ? y1 : y0, has1 ? z1 : z0);
         xp = (int64_t)(lane - 5) - 3;
         extra = true;
     }
@@ -487,7 +504,7 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
     // node q: its left interface belongs to lane - 1 of the same row
     if (valid && lane >= 1 && q >= 0 && lane != Lnext) {
         const double sc = m.invh[0][q];
-        const int64_t oi = (row % n1) * g.is[1] + (row / n1) * g.is[2] + q;
+        const int64_t oi = yl * g.is[1] + zl * g.is[2] + q;
         double v[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c] = -sc * (F[c] - sm.fl[c][lane - 1]);
@@ -501,7 +518,7 @@ __global__ void __launch_bounds__(64 * kWaves, 3)
 k_sweep_xl(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t totalJ,
            int first, unsigned *flags, const uint8_t *__restrict__ mask) {
     __shared__ XlLds<ND> sm[kWaves];
-    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t J0 = gw * 63;
     if (J0 + 1 >= totalJ) return;  // wave-uniform: no node left
     sweep_x_lanes<ND, SCHEME, MIX, ROUTE>(U, R, g, ph, m, J0, totalJ, first, flags, mask, sm[threadIdx.x >> 6]);
