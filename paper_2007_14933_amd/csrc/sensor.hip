@@ -262,10 +262,11 @@ __global__ void __launch_bounds__(256)
 k_sensor_xl(const double *__restrict__ U, Grid g, Phys ph, const uint16_t *__restrict__ w, float zcut,
             uint8_t *__restrict__ mask, int64_t totalJ) {
     __shared__ SxLds<ND> sp[4];
-    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
     const int64_t J0 = gw * 64;
     if (J0 >= totalJ) return;  // wave-uniform
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     MlpFrag F;
     load_frag(w, lane, F);
     sensor_x_lanes<ND>(U, g, ph, F, zcut, mask, J0, totalJ, sp[wv]);

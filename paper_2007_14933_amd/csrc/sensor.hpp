@@ -357,25 +357,39 @@ __device__ __forceinline__ void sensor_x_lanes(const double *__restrict__ U, con
     const int64_t N = g.n[0], NI = N + 1, n1 = g.n[1], cs = g.enpts;
     const int64_t J = J0 + lane;
     const bool valid = J < totalJ;
-    const int64_t Jc = valid ? J : totalJ - 1;
-    const int64_t row = Jc / NI;
-    const int64_t q = Jc - row * NI - 1;
-    const int64_t row0 = J0 / NI, q0 = J0 - row0 * NI - 1;
+    // lane 0's row and interface (wave-uniform), then each lane's row without
+    // a per-lane division: a wave spans at most two rows (NI >= 64), whose
+    // (y, z) are scalars; lanes past the last interface take the last one
+    const bool narrow = totalJ < 0x7fffffff;
+    auto sdiv = [narrow](int64_t a, int64_t b) -> int64_t {
+        return narrow ? (int64_t)((uint32_t)a / (uint32_t)b) : a / b;
+    };
+    const int64_t row0 = sdiv(J0, NI), q0 = J0 - row0 * NI - 1;
     const int Lnext = (int)(NI - (q0 + 1));  // first lane of row0 + 1 (>= 64: none)
-    auto stage = [&](int slot, int64_t r, int64_t pos) {
+    const int64_t z0 = sdiv(row0, n1), y0 = row0 - z0 * n1;
+    const int64_t y1 = y0 + 1 < n1 ? y0 + 1 : 0, z1 = y0 + 1 < n1 ? z0 : z0 + 1;
+    const bool has1 = row0 + 1 < n1 * g.n[2];
+    const bool nxt = lane >= Lnext;
+    int64_t yl = nxt ? y1 : y0, zl = nxt ? z1 : z0;
+    int64_t q = nxt ? (int64_t)(lane - Lnext) - 1 : q0 + lane;
+    if (!valid) {
+        yl = n1 - 1;
+        zl = g.n[2] - 1;
+        q = N - 1;
+    }
+    auto stage = [&](int slot, int64_t y, int64_t z, int64_t pos) {
         SPoint<ND> o;
-        spoint<ND, 0>(U, ext_index(g, 0, r % n1, r / n1) + pos, cs, ph, o);
+        spoint<ND, 0>(U, ext_index(g, 0, y, z) + pos, cs, ph, o);
         sp.v[0][slot] = o.r;
         sp.v[1][slot] = o.p;
 #pragma unroll
         for (int s = 0; s < ND - 1; ++s) sp.v[2 + s][slot] = o.vt[s];
     };
-    stage(lane, row, q + 3);
+    stage(lane, yl, zl, q + 3);
     if (lane < 5) {
-        stage(64 + lane, row0, q0 - 2 + lane);
+        stage(64 + lane, y0, z0, q0 - 2 + lane);
     } else if (lane < 10 && Lnext < 64) {
-        const int64_t r1 = row0 + 1 < totalJ / NI ? row0 + 1 : row0;
-        stage(64 + lane, r1, (int64_t)(lane - 5) - 3);
+        stage(64 + lane, has1 ? y1 : y0, has1 ? z1 : z0, (int64_t)(lane - 5) - 3);
     }
     wave_sync();
     const bool inrow0 = lane < Lnext;
