@@ -333,8 +333,12 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
 // line0 + l.  Along y and z the lanes' loads are contiguous in x; along x
 // the lines are strided, so the wave stages chunks of kChunk points of its 64
 // rows through LDS with contiguous loads and each lane reads its own row back.
+// One wave per SIMD for general meshes and for the mixed-precision routed
+// variant (both flux paths plus the FP64 reference in one loop): at two
+// waves they spill, which cost more (1.29 vs 0.93 ms at 256^3) than the
+// lost occupancy.
 template <int ND, int DIR, int SCHEME, bool GEN, bool MIX, bool ROUTE>
-__global__ void __launch_bounds__(256, GEN ? 1 : 2)
+__global__ void __launch_bounds__(256, GEN || (MIX && ROUTE) ? 1 : 2)
 k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t seg,
         int64_t nseg, int first, unsigned *flags, const uint8_t *__restrict__ mask) {
     __shared__ double sbuf[DIR == 0 ? kWaves : 1][ND + 2][kChunk][64];
