@@ -344,6 +344,136 @@ k_finish(const double *Racc, const double *__restrict__ G, double *Rout, Grid g,
     }
 }
 
+// The same finish for 3D separable meshes, RK update only, marching along z:
+// a block owns a kBX x kBY tile of columns and kFZ planes; each thread keeps
+// its column's G_z at z-2 .. z+2 in registers, so G_z is read once per node
+// instead of once per stencil use (the z neighbours' fluxes are otherwise
+// re-read from HBM: the plane-by-plane working set overflows the L2).  The
+// x and the y neighbours' fluxes are requested a direction at a time, then
+// the node's residual, register and state together.  Nodes
+// within two of a non-periodic end take that direction's closure from direct
+// loads; the arithmetic per node is that of k_finish.
+constexpr int kFZ = 16;
+
+__global__ void __launch_bounds__(kBX * kBY)
+k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid g, Metrics m, int stage, double dt,
+            double *__restrict__ U, double *__restrict__ dU) {
+    constexpr int NC = 5, NV = 4;
+    const int64_t x = (int64_t)blockIdx.x * kBX + threadIdx.x;
+    const int64_t y = (int64_t)blockIdx.y * kBY + threadIdx.y;
+    const int64_t Nx = g.n[0], Ny = g.n[1], Nz = g.n[2];
+    if (x >= Nx || y >= Ny) return;  // no block-wide synchronisation below
+    const int64_t z0 = (int64_t)blockIdx.z * kFZ;
+    const int64_t z1 = z0 + kFZ < Nz ? z0 + kFZ : Nz;
+    const bool perx = g.periodic[0] != 0, pery = g.periodic[1] != 0, perz = g.periodic[2] != 0;
+    const bool intx = perx || (x >= 2 && x <= Nx - 3);
+    const bool inty = pery || (y >= 2 && y <= Ny - 3);
+    const int64_t sy = g.is[1], sz = g.is[2];
+    const int64_t col = x + y * sy;  // interior index of (x, y, 0)
+    const double scx = m.invh[0][x], scy = m.invh[1][y];
+    auto wrap = [](int64_t q, int64_t N, bool per) -> int64_t {
+        if (per) return q < 0 ? q + N : (q >= N ? q - N : q);
+        return q < 0 ? 0 : (q >= N ? N - 1 : q);  // clamped: such values are never used
+    };
+    // neighbour offsets in x and y (p-2, p-1, p+1, p+2), wrapped where periodic
+    int64_t ox[4], oy[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int d = k < 2 ? k - 2 : k - 1;
+        ox[k] = wrap(x + d, Nx, perx) - x;
+        oy[k] = (wrap(y + d, Ny, pery) - y) * sy;
+    }
+    const double *Gx = G, *Gy = G + NV * g.nint, *Gz = G + 2 * NV * g.nint;
+    double gz[5][NV];  // G_z of this column at z-2 .. z+2
+#pragma unroll
+    for (int k = 1; k < 5; ++k) {
+        const int64_t zp = wrap(z0 - 3 + k, Nz, perz);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gz[k][v] = Gz[v * g.nint + col + zp * sz];
+    }
+#pragma unroll 1
+    for (int64_t z = z0; z < z1; ++z) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) gz[k][v] = gz[k + 1][v];
+        const int64_t ci = col + z * sz;
+        const int64_t e0 = ext_index(g, x, y, z);
+        const int64_t zn = wrap(z + 2, Nz, perz);
+        // the fluxes this node needs: G_z from the window, then the x and the
+        // y neighbours, four loads per flux component requested together
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gz[4][v] = Gz[v * g.nint + col + zn * sz];
+        double acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        // x, y, z in the order of k_finish
+        if (intx) {
+            double a[NV][4];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) a[v][k] = Gx[v * g.nint + ci + ox[k]];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                acc[v] += scx * ((2.0 / 3.0) * (a[v][2] - a[v][1]) - (1.0 / 12.0) * (a[v][3] - a[v][0]));
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double *Gv = Gx + v * g.nint + (ci - x);
+                auto at = [&](int64_t q) { return Gv[q]; };
+                acc[v] += scx * dline(at, x, Nx, false);
+            }
+        }
+        if (inty) {
+            double a[NV][4];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) a[v][k] = Gy[v * g.nint + ci + oy[k]];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                acc[v] += scy * ((2.0 / 3.0) * (a[v][2] - a[v][1]) - (1.0 / 12.0) * (a[v][3] - a[v][0]));
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double *Gv = Gy + v * g.nint + (ci - y * sy);
+                auto at = [&](int64_t q) { return Gv[q * sy]; };
+                acc[v] += scy * dline(at, y, Ny, false);
+            }
+        }
+        const double scz = m.invh[2][z];
+        if (perz || (z >= 2 && z <= Nz - 3)) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                acc[v] += scz * ((2.0 / 3.0) * (gz[3][v] - gz[1][v]) - (1.0 / 12.0) * (gz[4][v] - gz[0][v]));
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double *Gv = Gz + v * g.nint + col;
+                auto at = [&](int64_t q) { return Gv[q * sz]; };
+                acc[v] += scz * dline(at, z, Nz, false);
+            }
+        }
+        // then the node's residual, register and state, requested together
+        double R[NC], d0[NC], u0[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) R[c] = Racc[c * g.nint + ci];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) d0[c] = stage == 0 ? 0.0 : dU[c * g.nint + ci];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) u0[c] = U[c * g.enpts + e0];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) R[1 + v] += acc[v];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double du = (stage == 0 ? 0.0 : rk_A(stage) * d0[c]) + dt * R[c];
+            if (stage != 2) dU[c * g.nint + ci] = du;
+            U[c * g.enpts + e0] = u0[c] + rk_B(stage) * du;
+        }
+    }
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -389,6 +519,11 @@ hipError_t finish_nd(const Grid &g, const Phys &ph, const Metrics &m, const doub
     // fluxes best when all XCDs advance through the planes together (the
     // per-XCD runs of node_tiles measured slower here)
     const dim3 nb = node_grid(g), bs(kBX, kBY);
+    if (ND == 3 && !GEN && ph.viscous && mode == 1) {
+        const dim3 zb(nb.x, nb.y, (unsigned)((g.n[2] + kFZ - 1) / kFZ));
+        hipLaunchKernelGGL(k_finish_zm, zb, bs, 0, s, Racc, G, g, m, stage, dt, U, dU);
+        return hipGetLastError();
+    }
     if (ph.viscous) {
         if (mode == 0)
             hipLaunchKernelGGL((k_finish<ND, GEN, true, 0>), nb, bs, 0, s, Racc, G, Rout, g, ph, m,
