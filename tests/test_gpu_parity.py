@@ -50,6 +50,10 @@ def cases():
     c["wall_24x20x16_isothermal_sutherland"] = (wf, dict(nsteps=100))
     ch = I.laminar_channel(16, 33)
     c["channel_16x33_walls"] = (ch.with_(body_force=0.0), dict(nsteps=100))
+    # every direction non-periodic: the closure branches of the viscous
+    # fluxes and of the z-marching finish in x, y and z
+    sm = I.smooth_random(3, (22, 9, 13), seed=5, amp=0.05, Re=300.0, M=0.5)
+    c["smooth3d_22x9x13_viscous_extrapolated"] = (sm.with_(bc=((I.EXTRAPOLATE,) * 2,) * 3), dict(nsteps=30))
     X3, Y3, Z3 = wavy3d()
     base = I.smooth_random(3, (12, 10, 14), seed=7, amp=0.1, Re=200.0, M=0.6)
     c["wavy3d_12x10x14_viscous_general"] = (base.with_(coords1d=None, coords_full=(X3, Y3, Z3)), dict(nsteps=60))
