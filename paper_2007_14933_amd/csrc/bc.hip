@@ -47,9 +47,65 @@ __global__ void k_ghosts(double *__restrict__ U, Grid g, Phys ph, int dir, int k
     ghost_fill<ND>(U, g, ph, dir, kind0, kind1, t);
 }
 
+// All directions periodic: every ghost node (edges and corners included)
+// copies the interior node its wrapped coordinates name, in one launch (the
+// three direction passes compose to the same copies).  Items enumerate the
+// ghost region as z-ghost planes (full x, y extent), then y-ghost rows of
+// interior planes (full x extent), then x-ghost points of interior rows.
+template <int ND>
+__global__ void k_ghosts_periodic(double *__restrict__ U, Grid g, int64_t c1, int64_t c2, int64_t total) {
+    constexpr int NC = ND + 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int64_t ex = g.e[0], ey = g.e[1];
+    int64_t a[3];  // extended coordinates of the ghost node
+    if (t < c1) {
+        const int64_t pl = t / (ex * ey), r = t - pl * ex * ey;
+        a[0] = r % ex;
+        a[1] = r / ex;
+        a[2] = pl < g.h[2] ? pl : g.n[2] + pl;
+    } else if (t < c1 + c2) {
+        const int64_t u = t - c1, rg = 2 * g.h[1];
+        a[0] = u % ex;
+        const int64_t r = u / ex, jg = r % rg;
+        a[1] = jg < g.h[1] ? jg : g.n[1] + jg;
+        a[2] = r / rg + g.h[2];
+    } else {
+        const int64_t u = t - c1 - c2, rg = 2 * g.h[0];
+        const int64_t ig = u % rg, r = u / rg;
+        a[0] = ig < g.h[0] ? ig : g.n[0] + ig;
+        a[1] = r % g.n[1] + g.h[1];
+        a[2] = r / g.n[1] + g.h[2];
+    }
+    int64_t b[3];  // extended coordinates of the source
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t q = a[d] - g.h[d];
+        b[d] = (q < 0 ? q + g.n[d] : (q >= g.n[d] ? q - g.n[d] : q)) + g.h[d];
+    }
+    const int64_t dst = a[0] + a[1] * g.es[1] + a[2] * g.es[2];
+    const int64_t src = b[0] + b[1] * g.es[1] + b[2] * g.es[2];
+    double v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = U[src + c * g.enpts];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) U[dst + c * g.enpts] = v[c];
+}
+
 template <int ND>
 hipError_t bc_nd(const Grid &g, const Phys &ph, const osbli_params &p, double *U, hipStream_t s) {
     const int bs = 256;
+    bool allper = true;
+    for (int d = 0; d < ND; ++d) allper = allper && p.bc_kind[d][0] == OSBLI_PERIODIC && p.bc_kind[d][1] == OSBLI_PERIODIC;
+    if (allper) {
+        const int64_t c1 = 2 * g.h[2] * g.e[0] * g.e[1];
+        const int64_t c2 = g.n[2] * 2 * g.h[1] * g.e[0];
+        const int64_t c3 = g.n[2] * g.n[1] * 2 * g.h[0];
+        const int64_t total = c1 + c2 + c3;
+        hipLaunchKernelGGL((k_ghosts_periodic<ND>), dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, U, g,
+                           c1, c2, total);
+        return hipGetLastError();
+    }
     for (int d = 0; d < ND; ++d)
         for (int side = 0; side < 2; ++side) {
             const int kind = p.bc_kind[d][side];
