@@ -354,13 +354,14 @@ k_finish(const double *Racc, const double *__restrict__ G, double *Rout, Grid g,
 // within two of a non-periodic end take that direction's closure from direct
 // loads; the arithmetic per node is that of k_finish.
 constexpr int kFZ = 16;
+constexpr int kFX = 64, kFY = 4;  // columns per block
 
-__global__ void __launch_bounds__(kBX * kBY)
+__global__ void __launch_bounds__(kFX * kFY)
 k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid g, Metrics m, int stage, double dt,
             double *__restrict__ U, double *__restrict__ dU) {
     constexpr int NC = 5, NV = 4;
-    const int64_t x = (int64_t)blockIdx.x * kBX + threadIdx.x;
-    const int64_t y = (int64_t)blockIdx.y * kBY + threadIdx.y;
+    const int64_t x = (int64_t)blockIdx.x * kFX + threadIdx.x;
+    const int64_t y = (int64_t)blockIdx.y * kFY + threadIdx.y;
     const int64_t Nx = g.n[0], Ny = g.n[1], Nz = g.n[2];
     if (x >= Nx || y >= Ny) return;  // no block-wide synchronisation below
     const int64_t z0 = (int64_t)blockIdx.z * kFZ;
@@ -520,8 +521,9 @@ hipError_t finish_nd(const Grid &g, const Phys &ph, const Metrics &m, const doub
     // per-XCD runs of node_tiles measured slower here)
     const dim3 nb = node_grid(g), bs(kBX, kBY);
     if (ND == 3 && !GEN && ph.viscous && mode == 1) {
-        const dim3 zb(nb.x, nb.y, (unsigned)((g.n[2] + kFZ - 1) / kFZ));
-        hipLaunchKernelGGL(k_finish_zm, zb, bs, 0, s, Racc, G, g, m, stage, dt, U, dU);
+        const dim3 zb((unsigned)((g.n[0] + kFX - 1) / kFX), (unsigned)((g.n[1] + kFY - 1) / kFY),
+                      (unsigned)((g.n[2] + kFZ - 1) / kFZ));
+        hipLaunchKernelGGL(k_finish_zm, zb, dim3(kFX, kFY), 0, s, Racc, G, g, m, stage, dt, U, dU);
         return hipGetLastError();
     }
     if (ph.viscous) {
