@@ -1,5 +1,5 @@
 """The precision form (FP32 reconstruction and flux evaluation on FP64
-deviations; FP64 state, RK accumulation, metrics, dt) judged against the FP64
+deviations; FP64 state, RK accumulation, metrics, dt) checked against the FP64
 oracle: density and energy errors are stated per case and bounded."""
 import numpy as np
 import pytest
