@@ -198,6 +198,14 @@ int osbli_sensor_update(osbli_ctx *ctx, const double *U, void *stream);
  * and the total number of interfaces.  Synchronising. */
 int osbli_sensor_stats(osbli_ctx *ctx, int64_t *smooth, int64_t *total);
 
+/* Copy the routing mask of direction dir as left by the last refresh
+ * (one byte per interface, 1 = the network calls it smooth, before the
+ * dilation that the sweep applies) into the caller's device buffer dst, in
+ * x-fastest order of the direction's interface grid (extent n_dir + 1 along
+ * dir).  OSBLI_ENOSPACE if cap is below the direction's interface count.
+ * Stream-ordered. */
+int osbli_sensor_masks(osbli_ctx *ctx, int dir, uint8_t *dst, int64_t cap, void *stream);
+
 /* Interfaces of all directions: sum_d (n_d + 1) prod_{e != d} n_e. */
 int osbli_interface_count(osbli_ctx *ctx, int64_t *count);
 

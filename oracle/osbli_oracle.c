@@ -1101,10 +1101,7 @@ void orc_cheap_flux(const orc_params *P, int d, const double *Uk, const double *
  *     1/4 (a-c)^2 of rho/rho_bar + p/p_bar + (u.t_s)/a_bar summed over the
  *     tangents, on the substencils {i-2..i}, {i-1..i+1}, {i..i+2},
  *     {i+1..i+3}, divided by their sum (+1e-20, so variations at rounding
- *     level read as a uniform state).  B is quadratic, so each variable's
- *     indicator is evaluated on the unscaled values and multiplied by the
- *     inverse square of its scale: 1/rho_bar^2, 1/p_bar^2 and
- *     1/a_bar^2 = rho_bar / (gamma p_bar);
+ *     level read as a uniform state), with a_bar = sqrt(gamma p_bar/rho_bar);
  *   f4..f6: jumps J = |rho_{k+1} - rho_k| / (rho_{k+1} + rho_k) over (i-1,i),
  *     (i,i+1), (i+1,i+2), log-normalised as log10(1 + 1e6 J)/6;  f7..f9: the
  *     same for p.
@@ -1128,26 +1125,26 @@ void orc_features(const orc_params *P, int d, const double *Uk, const double *S,
     prim_t w[6];
     for (int k = 0; k < 6; k++) to_prim(P, nd, Uk + k * nc, &w[k]);
     const double rb = 0.5 * (w[2].rho + w[3].rho), pb = 0.5 * (w[2].p + w[3].p);
-    const double sr = 1.0 / (rb * rb), sp = 1.0 / (pb * pb), sv = rb / (P->gamma * pb);
+    const double ab = sqrt(P->gamma * pb / rb);
+    /* the normalised variables, then the indicators of their substencils */
     double r[6], q[6], vt[2][6];
     for (int k = 0; k < 6; k++) {
-        r[k] = w[k].rho;
-        q[k] = w[k].p;
+        r[k] = w[k].rho / rb;
+        q[k] = w[k].p / pb;
         for (int s = 0; s < nd - 1; s++) {
             double ut = 0.0;
             for (int m = 0; m < nd; m++) ut += w[k].u[m] * t[s][m];
-            vt[s][k] = ut;
+            vt[s][k] = ut / ab;
         }
     }
     double beta[4], sum = 0.0;
     for (int m = 0; m < 4; m++) {
-        double b = sr * js3(r, m) + sp * js3(q, m);
-        for (int s = 0; s < nd - 1; s++) b += sv * js3(vt[s], m);
+        double b = js3(r, m) + js3(q, m);
+        for (int s = 0; s < nd - 1; s++) b += js3(vt[s], m);
         beta[m] = b;
         sum += b;
     }
-    const double inv = 1.0 / (sum + 1e-20);
-    for (int m = 0; m < 4; m++) feat[m] = beta[m] * inv;
+    for (int m = 0; m < 4; m++) feat[m] = beta[m] / (sum + 1e-20);
     for (int m = 0; m < 3; m++) {
         double jr = fabs(w[m + 2].rho - w[m + 1].rho) / (w[m + 2].rho + w[m + 1].rho);
         double jp = fabs(w[m + 2].p - w[m + 1].p) / (w[m + 2].p + w[m + 1].p);

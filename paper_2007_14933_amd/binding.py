@@ -62,6 +62,7 @@ _SIGS = {
     "osbli_sensor_set_weights": (C.c_int, [_VP, _VP, C.c_int, C.c_double, C.c_int, C.c_int, _VP]),
     "osbli_sensor_update": (C.c_int, [_VP, _VP, _VP]),
     "osbli_sensor_stats": (C.c_int, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "osbli_sensor_masks": (C.c_int, [_VP, C.c_int, _VP, C.c_int64, _VP]),
     "osbli_interface_count": (C.c_int, [_VP, C.POINTER(C.c_int64)]),
     "osbli_collect_labels": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int64, C.POINTER(C.c_int64), _VP]),
     "osbli_mlp_workspace_bytes": (C.c_size_t, [C.c_int64]),

@@ -476,6 +476,18 @@ int osbli_sensor_stats(osbli_ctx *c, int64_t *smooth, int64_t *total) {
     return OSBLI_OK;
 }
 
+int osbli_sensor_masks(osbli_ctx *c, int dir, uint8_t *dst, int64_t cap, void *stream) {
+    if (!c || !dst) return set_err(c, OSBLI_EINVAL, "null argument");
+    if (!c->p.sensor || !c->sensor_ready) return set_err(c, OSBLI_EINVAL, "sensor weights not set");
+    if (dir < 0 || dir >= c->g.nd) return set_err(c, OSBLI_EINVAL, "direction %d out of range", dir);
+    const int64_t n = iface_count(c->g, dir);
+    if (cap < n) return set_err(c, OSBLI_ENOSPACE, "mask buffer holds %lld, need %lld", (long long)cap, (long long)n);
+    hipStream_t s = as_stream(stream);
+    c->last = s;
+    HIP_TRY(c, hipMemcpyAsync(dst, c->mask[dir], (size_t)n, hipMemcpyDeviceToDevice, s));
+    return OSBLI_OK;
+}
+
 int osbli_interface_count(osbli_ctx *c, int64_t *count) {
     if (!c || !count) return set_err(c, OSBLI_EINVAL, "null argument");
     int64_t tot = 0;

@@ -136,6 +136,16 @@ class Solver:
         B.check(self.lib.osbli_sensor_stats(self.ctx, C.byref(sm), C.byref(tot)), self.ctx)
         return sm.value, tot.value
 
+    def sensor_masks(self, d):
+        """Direction d's routing mask of the last refresh (numpy uint8, x-fastest
+        over the interface grid, extent n_d + 1 along d)."""
+        n = [self.prob.n[e] if e < self.prob.ndim else 1 for e in range(3)]
+        n[d] += 1
+        out = torch.empty(n[0] * n[1] * n[2], dtype=torch.uint8, device=self.device)
+        B.check(self.lib.osbli_sensor_masks(self.ctx, int(d), _ptr(out), out.numel(), self._s()), self.ctx)
+        torch.cuda.synchronize(self.device)
+        return out.cpu().numpy()
+
     # ---- time loop (section 2.7 ordering: residual, update, BCs) ----
     def step(self, dt):
         for s in range(3):

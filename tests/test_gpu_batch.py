@@ -66,6 +66,44 @@ def test_batch_equals_solo(form, scheme, sensor):
     compare(b, probs, **kw)
 
 
+# rows of 64 and more interfaces: the batched x sweep runs with lanes along
+# x, and the first wave of every row of the batched y sweep loads ahead into
+# LDS; the others march
+ORACLE_SIZES = (64, 100, 40, 72)
+ORACLE_T_ENDS = (0.02, 0.012, 0.03, 0.016)
+
+
+@pytest.mark.parametrize("form,scheme", [(0, I.TENO5), (0, I.WENOZ5), (1, I.TENO5)])
+def test_batch_against_oracle(form, scheme):
+    """Every batched problem against the FP64 oracle run of the same problem
+    to its own end time: plain FP64 at the run-parity bar (max normwise
+    relative difference <= 1e-11), the precision form at the bounds of its
+    oracle tests (relative L1 of density <= 1e-4, energy <= 3e-4)."""
+    from oracle import oracle as O
+    from parity_util import normwise_rel, oracle_run
+    from paper_2007_14933_amd.batch import Batch
+    probs = ensemble(ORACLE_SIZES, 21, ORACLE_T_ENDS, scheme)
+    say("[gpu batch vs oracle] form %d scheme %d sizes %s" % (form, scheme, ORACLE_SIZES))
+    b = Batch(probs, cfl=0.5, form=form)
+    b.run(poll=5)
+    b.check()
+    t_b, act, nact = b.status()
+    assert nact == 0
+    for p, prob in enumerate(probs):
+        Uo, to = oracle_run(prob, 10 ** 6, cfl=0.5, t_end=prob.t_end)
+        a, ref = O.interior(prob, b.state(p)), O.interior(prob, Uo)
+        if form == 0:
+            err = normwise_rel(a, ref)
+            say("   problem %d N=%d t=%.6g (oracle %.6g) normwise rel diff %s" % (p, prob.n[0], t_b[p], to, err))
+            assert abs(t_b[p] - to) <= 1e-12 * to
+            assert err.max() <= 1e-11, err
+        else:
+            l1 = [np.abs(a[c] - ref[c]).mean() / np.abs(ref[c]).mean() for c in (0, prob.nc - 1)]
+            say("   problem %d N=%d t=%.6g (oracle %.6g) rel L1 rho %.3e rhoE %.3e" % (p, prob.n[0], t_b[p], to, *l1))
+            assert abs(t_b[p] - to) <= 1e-4 * to
+            assert l1[0] <= 1e-4 and l1[1] <= 3e-4, l1
+
+
 def test_batch_tiles_and_direct_launches_do_not_change_results():
     from paper_2007_14933_amd.batch import Batch
     probs = ensemble(SIZES, 12, T_ENDS)

@@ -57,6 +57,21 @@ def cases():
     X3, Y3, Z3 = wavy3d()
     base = I.smooth_random(3, (12, 10, 14), seed=7, amp=0.1, Re=200.0, M=0.6)
     c["wavy3d_12x10x14_viscous_general"] = (base.with_(coords1d=None, coords_full=(X3, Y3, Z3)), dict(nsteps=60))
+    # the general 3D curvilinear path with every face non-periodic (one-sided
+    # metric closures, extrapolated ghosts)
+    c["wavy3d_12x10x14_viscous_general_extrapolated"] = (
+        base.with_(coords1d=None, coords_full=(X3, Y3, Z3), bc=((I.EXTRAPOLATE,) * 2,) * 3), dict(nsteps=30))
+    # 64^3: every y / z sweep wave loads its next point ahead into LDS (rows
+    # of 64 consecutive x nodes), the x sweep runs with lanes along x, and the
+    # z-marching viscous and finish passes span several z segments
+    c["tgv64_viscous"] = (I.tgv(64), dict(nsteps=100))
+    # nz = 70: the z-marching viscous (32-plane) and finish (16-plane) tiles
+    # start segments inside the grid and end on a ragged one, periodic in z
+    # and with one-sided closures in z
+    sz = I.smooth_random(3, (12, 9, 70), seed=9, amp=0.05, Re=300.0, M=0.5)
+    c["smooth3d_12x9x70_viscous_periodic"] = (sz, dict(nsteps=40))
+    c["smooth3d_12x9x70_viscous_extrapolated_z"] = (
+        sz.with_(bc=((I.PERIODIC,) * 2, (I.PERIODIC,) * 2, (I.EXTRAPOLATE,) * 2)), dict(nsteps=40))
     return c
 
 
