@@ -90,6 +90,21 @@ def test_run_parity(name):
     assert np.all(np.isfinite(err)) and err.max() <= TOL_RUN, err
 
 
+def metric_sensitivity(prob, U, R, scale, draws=3, seed=1):
+    """Largest change of the oracle's residual, relative to the flux scale,
+    when every coordinate is perturbed by about one ulp (relative 2.2e-16)."""
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for _ in range(draws):
+        X = tuple(None if c is None else c * (1.0 + 2.2e-16 * rng.standard_normal(c.shape))
+                  for c in prob.coords_full)
+        p2 = prob.with_(coords_full=X)
+        S2, J2 = O.metrics(p2)
+        R2 = O.residual(p2, S2, J2, U)
+        worst = max(worst, float((np.abs(R2 - R).max(axis=(1, 2, 3)) / scale).max()))
+    return worst
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_residual_bc_dt_parity(name):
     """One ghost fill, one residual and one dt on a perturbed state."""
@@ -116,8 +131,15 @@ def test_residual_bc_dt_parity(name):
     Ro = O.residual(prob, S, J, Uo)
     scale = flux_scale(prob, Uo, J, S)
     err = np.abs(Rg - Ro).max(axis=(1, 2, 3)) / scale
-    say("   residual |diff| / flux scale:", err)
-    assert err.max() <= TOL_ONE, err
+    tol = TOL_ONE
+    if prob.coords_full is not None and any(b[0] != I.PERIODIC for b in prob.bc[: prob.ndim]):
+        # one-sided metric closures (coefficients up to 48/12, nested twice in
+        # the conservative area vectors) amplify the rounding of the
+        # coordinates: the bar is the oracle's own response to a one-ulp
+        # relative perturbation of the coordinates, with a margin of 4
+        tol = max(TOL_ONE, 4.0 * metric_sensitivity(prob, Uo, Ro, scale))
+    say("   residual |diff| / flux scale:", err, "bar %.2e" % tol)
+    assert err.max() <= tol, err
     dtg = s.compute_dt(0.5)
     dto = O.compute_dt(prob, S, J, Uo, 0.5)
     assert abs(dtg - dto) <= 1e-14 * dto

@@ -37,6 +37,17 @@ def state_after(prob, nsteps):
     return O.apply_bc(prob, U)
 
 
+def feature_sensitivity(prob, d, Uk, S, fo, draws=4, seed=3):
+    """Largest change of the oracle's features when the stencil states are
+    perturbed by about one ulp (relative 2.2e-16)."""
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for _ in range(draws):
+        f2, _ = O.features(prob, d, Uk * (1.0 + 2.2e-16 * rng.standard_normal(Uk.shape)), S)
+        worst = max(worst, float(np.abs(f2 - fo).max()))
+    return worst
+
+
 @pytest.mark.parametrize("case", ["riemann2d_48", "smooth3d_10"])
 def test_features_and_labels_match_oracle(case):
     import torch
@@ -55,16 +66,26 @@ def test_features_and_labels_match_oracle(case):
     f, l = f.cpu().numpy(), l.cpu().numpy()
     off = 0
     nbad = 0
+    nnoise = 0
     for d in range(prob.ndim):
         st = iface_stencils(prob, U, d)
         for t in range(len(st)):
             S = np.eye(3)[d][: prob.ndim]
             fo, lo = O.features(prob, d, st[t], S)
-            # same FP64 operations, rounded to float32
-            assert np.abs(f[off + t] - fo).max() <= 1e-6, (d, t, f[off + t], fo)
+            # FP64 features rounded to float32; where the stencil is uniform
+            # to within rounding the indicators are rounding noise, so the
+            # bar there is the oracle's own response to one-ulp relative
+            # perturbations of the stencil states (margin 8)
+            diff = np.abs(f[off + t] - fo).max()
+            if diff > 1e-6:
+                sens = feature_sensitivity(prob, d, st[t], S, fo)
+                nnoise += 1
+                assert diff <= 1e-6 + 8.0 * sens, (d, t, f[off + t], fo, sens)
+            assert np.all(np.isfinite(f[off + t])) and f[off + t][:4].sum() <= 1.0 + 1e-6
             nbad += int(l[off + t] != lo)
         off += len(st)
-    say("   interfaces %d, label disagreements %d, smooth fraction %.3f" % (off, nbad, l.mean()))
+    say("   interfaces %d, label disagreements %d, smooth fraction %.3f, features at rounding-noise level %d"
+        % (off, nbad, l.mean(), nnoise))
     assert off == len(l) and nbad == 0
     del torch
 
