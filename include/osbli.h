@@ -139,6 +139,26 @@ int osbli_residual(osbli_ctx *ctx, const double *U, double *R, void *stream);
  * dU (interior layout) must not alias. */
 int osbli_rk_substep(osbli_ctx *ctx, int stage, double dt, double *U, double *dU, void *stream);
 
+/* Allocation-free variant of osbli_rk_substep, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, launches and results as
+ * osbli_rk_substep; the per-substage scratch (residual accumulator, and the
+ * viscous fluxes when Re > 0) lives in one library-owned static device array
+ * of osbli_noalloc_scratch_bytes() = 64 MiB per GPU instead of the context's
+ * workspace: 8 nc n bytes plus, when viscous, 8 ndim (ndim + 1) n bytes
+ * (n interior nodes, each part rounded up to 256) must fit, e.g. a viscous
+ * 3D grid of up to about 4.9e5 nodes, an inviscid 2D grid of up to about
+ * 2.0e6.  Larger grids return OSBLI_ENOSPACE before any launch.  The call
+ * allocates nothing (no hipMalloc / hipFree, no profiling events).  Every
+ * call on a GPU shares that GPU's one array and leaves its contents behind:
+ * calls that overlap on one GPU (several streams or threads) race, so
+ * callers serialise them.  OSBLI_EDEVICE if the array's device address
+ * could not be resolved when the context was set up. */
+int osbli_rk_substep_noalloc(osbli_ctx *ctx, int stage, double dt, double *U, double *dU, void *stream);
+
+/* Size in bytes of the scratch array of osbli_rk_substep_noalloc. */
+size_t osbli_noalloc_scratch_bytes(void);
+
 /* dt = cfl / max over interior nodes of
  *   sum_d J|S_d| (|u.n_d| + a) + 2 nu_eff sum_d (J|S_d|)^2,
  * nu_eff = max(4/3, gamma/Pr) mu/(rho Re) when viscous.  Deterministic

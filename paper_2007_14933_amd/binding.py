@@ -53,6 +53,8 @@ _SIGS = {
     "osbli_apply_bc": (C.c_int, [_VP, _VP, _VP]),
     "osbli_residual": (C.c_int, [_VP, _VP, _VP, _VP]),
     "osbli_rk_substep": (C.c_int, [_VP, C.c_int, C.c_double, _VP, _VP, _VP]),
+    "osbli_rk_substep_noalloc": (C.c_int, [_VP, C.c_int, C.c_double, _VP, _VP, _VP]),
+    "osbli_noalloc_scratch_bytes": (C.c_size_t, []),
     "osbli_compute_dt": (C.c_int, [_VP, _VP, C.c_double, _DP, _VP]),
     "osbli_check": (C.c_int, [_VP]),
     "osbli_last_error": (C.c_char_p, [_VP]),

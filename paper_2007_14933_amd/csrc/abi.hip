@@ -4,12 +4,47 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "internal.hpp"
 
 using namespace osbli;
+
+// Scratch of the allocation-free substep (osbli_rk_substep_noalloc): the
+// residual accumulator and the viscous fluxes of one grid, in one file-scope
+// device array that every GPU the library runs on holds until the process
+// ends.  Host code never passes the array's name to a kernel: its device
+// address is resolved once per device (hipGetSymbolAddress, that device
+// current) when a context is set up on it, and kept in scratch_ptr.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+hipError_t scratch_err[kMaxDevices] = {};
+
+// the scratch address on device dev (which must be current); nullptr on failure
+void *resolve_scratch(int dev, hipError_t *err) {
+    *err = hipSuccess;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev] && scratch_err[dev] == hipSuccess) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) scratch_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        else scratch_ptr[dev] = p;
+    }
+    *err = scratch_err[dev];
+    return scratch_ptr[dev];
+}
+}  // namespace
 
 // optional HIP-event timing of each kernel class on the launch stream
 struct Prof {
@@ -41,6 +76,8 @@ struct osbli_ctx {
     int64_t seg[3];        // sweep segment lengths (0: the default rule)
     hipStream_t last;
     int device;
+    char *scratch;         // this device's scratch array (allocation-free substep), or null
+    hipError_t scratch_err;
     char err[320];
 };
 
@@ -288,6 +325,9 @@ int osbli_init_grid(osbli_ctx **out, const osbli_params *p, const double *x, con
     for (int d = 0; d < p->ndim; ++d)
         if (!X[d]) return set_err(c, OSBLI_EINVAL, "coordinates of direction %d missing", d);
     HIP_TRY(c, hipGetDevice(&c->device));
+    // the allocation-free substep's scratch on this device (a failure here
+    // only disables that entry point)
+    c->scratch = static_cast<char *>(resolve_scratch(c->device, &c->scratch_err));
     hipStream_t s = as_stream(stream);
     c->last = s;
     c->ws = static_cast<char *>(workspace);
@@ -385,6 +425,39 @@ int osbli_rk_substep(osbli_ctx *c, int stage, double dt, double *U, double *dU, 
         Timed t(c, OSBLI_K_FINISH, s);
         HIP_TRY(c, launch_finish(c->g, c->ph, c->m, c->Racc, c->G, nullptr, stage, dt, U, dU, 1, s));
     }
+    return OSBLI_OK;
+}
+
+size_t osbli_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int osbli_rk_substep_noalloc(osbli_ctx *c, int stage, double dt, double *U, double *dU, void *stream) {
+    if (!c || !U || !dU) return set_err(c, OSBLI_EINVAL, "null argument");
+    if (stage < 0 || stage > 2) return set_err(c, OSBLI_EINVAL, "stage must be 0..2");
+    if ((void *)U == (void *)dU) return set_err(c, OSBLI_EINVAL, "dU aliases U");
+    const size_t racc = align256(sizeof(double) * c->g.nc * c->g.nint);
+    const size_t gsz = c->ph.viscous ? align256(sizeof(double) * c->g.nd * (c->g.nd + 1) * c->g.nint) : 0;
+    if (racc + gsz > kScratchBytes)
+        return set_err(c, OSBLI_ENOSPACE, "grid needs %zu bytes of scratch; the allocation-free substep holds %zu",
+                       racc + gsz, kScratchBytes);
+    if (!c->scratch)
+        return set_err(c, OSBLI_EDEVICE, "scratch address of device %d unavailable: %s", c->device,
+                       hipGetErrorString(c->scratch_err));
+    double *Racc = reinterpret_cast<double *>(c->scratch);
+    double *G = reinterpret_cast<double *>(c->scratch + racc);
+    hipStream_t s = as_stream(stream);
+    c->last = s;
+    // the same launches as osbli_rk_substep, with the accumulator (stored,
+    // not accumulated, by the first sweep) and the viscous fluxes (every
+    // interior node written) in the scratch array; no profiling events
+    const bool route = c->p.sensor && c->sensor_ready;
+    if (route && (stage == 0 || c->sensor_every))
+        for (int d = 0; d < c->g.nd; ++d)
+            HIP_TRY(c, launch_sensor(c->g, c->ph, U, d, c->wts, c->zcut, c->mask[d], s));
+    if (c->ph.viscous) HIP_TRY(c, launch_viscous_fluxes(c->g, c->ph, c->m, U, G, s));
+    for (int d = 0; d < c->g.nd; ++d)
+        HIP_TRY(c, launch_convective(c->g, c->ph, c->m, U, Racc, c->flags, d, d == 0, route ? c->mask[d] : nullptr,
+                                     c->seg[d], s));
+    HIP_TRY(c, launch_finish(c->g, c->ph, c->m, Racc, G, nullptr, stage, dt, U, dU, 1, s));
     return OSBLI_OK;
 }
 
