@@ -45,7 +45,7 @@ class Params(C.Structure):
         ("gamma", C.c_double), ("Re", C.c_double), ("Pr", C.c_double), ("Minf", C.c_double),
         ("sutherland", C.c_int32), ("scheme", C.c_int32),
         ("Ts_over_Tref", C.c_double), ("teno_CT", C.c_double), ("eps", C.c_double),
-        ("roe_avg", C.c_int32), ("pad1", C.c_int32),
+        ("roe_avg", C.c_int32), ("rk", C.c_int32),
         ("bc", (C.c_int32 * 2) * 3),
         ("wall_T", (C.c_double * 2) * 3),
         ("period", C.c_double * 3),
@@ -75,6 +75,9 @@ def _load():
                 "orc_run": (C.c_int, [P, _D, _D, _D, _D, C.c_int64, C.c_double, C.c_double,
                                       C.c_double, _D]),
                 "orc_recon5": (C.c_double, [C.c_int, C.c_double, C.c_double, _D, _I]),
+                "orc_recon": (C.c_double, [C.c_int, C.c_double, C.c_double, _D, _I]),
+                "orc_rk_coeffs": (None, [P, _D, _D, _I]),
+                "orc_smoothness6": (C.c_double, [_D, _D]),
                 "orc_smoothness5": (None, [_D, _D]),
                 "orc_iface_flux": (None, [P, C.c_int, _D, _D, _D, _I]),
                 "orc_phys_flux": (None, [P, _D, _D, _D]),
@@ -120,6 +123,7 @@ def params(prob) -> Params:
     p.teno_CT = float(prob.teno_CT)
     p.eps = float(prob.eps)
     p.roe_avg = int(prob.roe_avg)
+    p.rk = int(getattr(prob, "rk", 0))
     p.body_force = float(getattr(prob, "body_force", 0.0))
     return p
 
@@ -206,6 +210,33 @@ def recon5(scheme, CT, eps, f):
     return v, dl
 
 
+def recon(scheme, CT, eps, f):
+    """Reconstruction at x_{i+1/2} from f_{i-2..i+3} (six values); four
+    cut-off flags (1 for stencils a scheme does not have)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    assert f.size == 6
+    dl = np.zeros(4, dtype=np.intc)
+    v = _load().orc_recon(int(scheme), float(CT), float(eps), _dp(f), _ip(dl))
+    return v, dl
+
+
+def smoothness6(f):
+    """TENO6 indicators beta_0..beta_3 and tau_6 of f_{i-2..i+3}."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    b = np.zeros(4)
+    tau = _load().orc_smoothness6(_dp(f), _dp(b))
+    return b, tau
+
+
+def rk_coeffs(prob):
+    """(A, B) of the problem's low-storage RK scheme."""
+    A = np.zeros(5)
+    B = np.zeros(5)
+    ns = np.zeros(1, dtype=np.intc)
+    _load().orc_rk_coeffs(C.byref(params(prob)), _dp(A), _dp(B), _ip(ns))
+    return A[: ns[0]], B[: ns[0]]
+
+
 def smoothness5(f):
     f = np.ascontiguousarray(f, dtype=np.float64)
     b = np.zeros(3)
@@ -220,9 +251,9 @@ def iface_flux(prob, d, Uk, S):
     S3 = np.zeros(3)
     S3[: prob.ndim] = np.asarray(S, dtype=np.float64)[: prob.ndim]
     F = np.zeros(nc)
-    dl = np.zeros(nc * 2 * 3, dtype=np.intc)
+    dl = np.zeros(nc * 2 * 4, dtype=np.intc)
     _load().orc_iface_flux(C.byref(params(prob)), int(d), _dp(Uk), _dp(S3), _dp(F), _ip(dl))
-    return F, dl.reshape(nc, 2, 3)
+    return F, dl.reshape(nc, 2, 4)
 
 
 def phys_flux(prob, U, nv):

@@ -39,8 +39,9 @@
 #define NGHOST 3
 #define NCMAX 5
 
-enum { BC_PERIODIC = 0, BC_EXTRAPOLATE = 1, BC_ISOTHERMAL = 2, BC_ADIABATIC = 3 };
-enum { SCHEME_WENOZ5 = 0, SCHEME_TENO5 = 1 };
+enum { BC_PERIODIC = 0, BC_EXTRAPOLATE = 1, BC_ISOTHERMAL = 2, BC_ADIABATIC = 3, BC_DIRICHLET = 4 };
+enum { SCHEME_WENOZ5 = 0, SCHEME_TENO5 = 1, SCHEME_TENO6 = 2, SCHEME_WENOJS5 = 3, SCHEME_WENOZ3 = 4 };
+enum { RK3_WILLIAMSON = 0, RK3_SSP = 1, RK4_CK = 2 };
 
 typedef struct {
     int32_t ndim;
@@ -53,7 +54,7 @@ typedef struct {
     double teno_CT;
     double eps;                   /* epsilon of the nonlinear weights */
     int32_t roe_avg;              /* 1: Roe average, 0: arithmetic mean */
-    int32_t pad1;
+    int32_t rk;                   /* RK3_WILLIAMSON, RK3_SSP or RK4_CK */
     int32_t bc[3][2];
     double wall_T[3][2];
     double period[3];
@@ -293,6 +294,131 @@ static double recon5(int scheme, double CT, double eps, const double *f, int *de
     return w[0] * q[0] + w[1] * q[1] + w[2] * q[2];
 }
 
+/* ------------------------------------------------------ TENO6 (per scalar) --
+ * Sixth-order TENO (section 2.5 with K = 6): four candidate stencils, the
+ * three three-point ones of the fifth-order scheme, S_0 = {i..i+2},
+ * S_1 = {i-1..i+1}, S_2 = {i-2..i}, and the four-point S_3 = {i..i+3}, so the
+ * reconstruction at x_{i+1/2} reads f_{i-2..i+3} (f[0..5]).
+ * S_3's value is the cell-average reconstruction of its cubic,
+ *   (1/4) f_i + (13/12) f_{i+1} - (5/12) f_{i+2} + (1/12) f_{i+3},
+ * and its indicator is the Jiang-Shu integral (eq. smoothness_indicator)
+ * of that cubic over cell i, which works out to
+ *   beta_3 = (1/36)(-11 f_i + 18 f_{i+1} - 9 f_{i+2} + 2 f_{i+3})^2
+ *          + (13/12)(2 f_i - 5 f_{i+1} + 4 f_{i+2} - f_{i+3})^2
+ *          + (781/720)(-f_i + 3 f_{i+1} - 3 f_{i+2} + f_{i+3})^2.
+ * tau_6 = |beta_3 - (beta_0 + beta_2 + 4 beta_1)/6| (eq. tau_5, second
+ * line; beta_1 is the central stencil's).  gamma_r = (1 + tau_6/(beta_r +
+ * eps))^6 (eq. TENO_weights, C = 1, q = 6), chi_r = gamma_r / sum gamma,
+ * delta_r = 0 if chi_r < C_T (eq. cutoff_eqn), omega_r = d_r delta_r /
+ * sum d delta.
+ * Reading (the optimal weights are not printed): d = (3/10, 9/20, 1/20, 1/5),
+ * the unique weights whose combination of the four candidates is the
+ * sixth-order reconstruction (1, -8, 37, 37, -8, 1)/60 on i-2..i+3.  Four
+ * stencils can never all be cut (max chi >= 1/4 > C_T).
+ */
+/* the four indicators and tau_6 of f_{i-2..i+3} */
+static double smoothness6(const double *f, double *beta)
+{
+    const double f0 = f[2], fp1 = f[3], fp2 = f[4], fp3 = f[5];
+    smoothness5(f, beta);
+    const double a = -11.0 * f0 + 18.0 * fp1 - 9.0 * fp2 + 2.0 * fp3;
+    const double b = 2.0 * f0 - 5.0 * fp1 + 4.0 * fp2 - fp3;
+    const double c = -f0 + 3.0 * fp1 - 3.0 * fp2 + fp3;
+    beta[3] = (1.0 / 36.0) * a * a + (13.0 / 12.0) * b * b + (781.0 / 720.0) * c * c;
+    return fabs(beta[3] - (beta[0] + beta[2] + 4.0 * beta[1]) / 6.0);
+}
+
+static double recon_teno6(double CT, double eps, const double *f, int *delta)
+{
+    const double fm2 = f[0], fm1 = f[1], f0 = f[2], fp1 = f[3], fp2 = f[4], fp3 = f[5];
+    double q[4], beta[4];
+    q[0] = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
+    q[1] = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
+    q[2] = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
+    q[3] = 0.25 * f0 + (13.0 / 12.0) * fp1 - (5.0 / 12.0) * fp2 + (1.0 / 12.0) * fp3;
+    const double tau = smoothness6(f, beta);
+    const double dr[4] = {3.0 / 10.0, 9.0 / 20.0, 1.0 / 20.0, 1.0 / 5.0};
+    double g[4], sum = 0.0;
+    for (int r = 0; r < 4; r++) {
+        double c = 1.0 + tau / (beta[r] + eps);
+        double c3 = c * c * c;
+        g[r] = c3 * c3;
+        sum += g[r];
+    }
+    int dl[4];
+    double sd = 0.0;
+    for (int r = 0; r < 4; r++) {
+        double chi = g[r] / sum;
+        dl[r] = chi < CT ? 0 : 1;
+        sd += dr[r] * dl[r];
+    }
+    double v = 0.0;
+    for (int r = 0; r < 4; r++) v += (dr[r] * dl[r] / sd) * q[r];
+    if (delta) for (int r = 0; r < 4; r++) delta[r] = dl[r];
+    return v;
+}
+
+/* ---------------------------------------------- WENO-JS5 (per scalar) --
+ * The original weights (eqs. omega and alpha): alpha_r = d_r / (eps +
+ * beta_r)^p with p = 2, omega = alpha / sum alpha; the same candidates,
+ * indicators and optimal weights as the fifth-order WENO-Z.  The paper sets
+ * eps = 1e-6 for this scheme; eps is the caller's. */
+static double recon_wenojs5(double eps, const double *f)
+{
+    const double fm2 = f[0], fm1 = f[1], f0 = f[2], fp1 = f[3], fp2 = f[4];
+    double q[3], beta[3], a[3], sum = 0.0;
+    q[0] = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
+    q[1] = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
+    q[2] = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
+    smoothness5(f, beta);
+    const double dr[3] = {3.0 / 10.0, 3.0 / 5.0, 1.0 / 10.0};
+    for (int r = 0; r < 3; r++) {
+        double e = eps + beta[r];
+        a[r] = dr[r] / (e * e);
+        sum += a[r];
+    }
+    return (a[0] / sum) * q[0] + (a[1] / sum) * q[1] + (a[2] / sum) * q[2];
+}
+
+/* ---------------------------------------------- WENO-3Z (per scalar) --
+ * Third-order WENO-Z (k = 2, section 2.4; the order used in section 5.2):
+ * candidates S_0 = {i, i+1}, S_1 = {i-1, i} (eq. eno_rhs with r = 0, 1):
+ * q_0 = (f_i + f_{i+1})/2, q_1 = (3 f_i - f_{i-1})/2; indicators of their
+ * linear polynomials (eq. smoothness_indicator): beta_0 = (f_{i+1} - f_i)^2,
+ * beta_1 = (f_i - f_{i-1})^2; optimal weights (2/3, 1/3), whose combination
+ * is the third-order (-1/6, 5/6, 1/3) on i-1..i+1; alpha_r = d_r (1 +
+ * (tau/(beta_r + eps))^2) (eq. wenoz_weights).  Reading: tau_3 = |beta_0 -
+ * beta_1| (the paper prints only the fifth-order tau).  Reads f[1..3]. */
+static double recon_wenoz3(double eps, const double *f)
+{
+    const double fm1 = f[1], f0 = f[2], fp1 = f[3];
+    const double q0 = 0.5 * f0 + 0.5 * fp1, q1 = -0.5 * fm1 + 1.5 * f0;
+    const double b0 = (fp1 - f0) * (fp1 - f0), b1 = (f0 - fm1) * (f0 - fm1);
+    const double tau = fabs(b0 - b1);
+    const double x0 = tau / (b0 + eps), x1 = tau / (b1 + eps);
+    const double a0 = (2.0 / 3.0) * (1.0 + x0 * x0), a1 = (1.0 / 3.0) * (1.0 + x1 * x1);
+    const double sum = a0 + a1;
+    return (a0 / sum) * q0 + (a1 / sum) * q1;
+}
+
+/* Reconstruction of the scheme at x_{i+1/2} from f[0..5] = f_{i-2..i+3}
+ * (the fifth-order schemes read f[0..4], WENO-3Z f[1..3]).  delta (may be
+ * NULL) receives four cut-off flags; stencils a scheme does not have, and
+ * every stencil of a WENO scheme, read 1. */
+static double recon(int scheme, double CT, double eps, const double *f, int *delta)
+{
+    int dl[4] = {1, 1, 1, 1};
+    double v;
+    switch (scheme) {
+    case SCHEME_TENO6: v = recon_teno6(CT, eps, f, dl); break;
+    case SCHEME_WENOJS5: v = recon_wenojs5(eps, f); break;
+    case SCHEME_WENOZ3: v = recon_wenoz3(eps, f); break;
+    default: v = recon5(scheme, CT, eps, f, dl); break;
+    }
+    if (delta) for (int r = 0; r < 4; r++) delta[r] = dl[r];
+    return v;
+}
+
 /* --------------------------------------------- characteristic LLF flux --
  * One half node x_{i+1/2} in direction d (section 2.2, enumerated algorithm):
  *   n = S/|S| with S the half-node area vector; for k = i-2..i+3:
@@ -300,10 +426,11 @@ static double recon5(int scheme, double CT, double eps, const double *f, int *de
  *   stencil points (reading of "local stencil points k", pointwise
  *   eigenvalues, the averaged state's own eigenvalue not included);
  *   g^{+-}_k = (g_k +- alpha_j V_k)/2 (eq. lax_scalar per field);
- *   ghat^+ from g^+_{i-2..i+2}, ghat^- from the mirror image
- *   g^-_{i+3..i-1}; F = |S| R (ghat^+ + ghat^-).
+ *   ghat^+ from g^+_{i-2..i+3}, ghat^- from the mirror image
+ *   g^-_{i+3..i-2} (the fifth-order schemes use the first five of each,
+ *   g^+_{i-2..i+2} and g^-_{i+3..i-1}); F = |S| R (ghat^+ + ghat^-).
  * Uk holds the six stencil states, Uk[k*nc + c].  delta (may be NULL)
- * receives the TENO flags as delta[(j*2 + side)*3 + r], side 0 = plus.
+ * receives the TENO flags as delta[(j*2 + side)*4 + r], side 0 = plus.
  */
 static void iface_flux(const orc_params *P, int d, const double *Uk, const double *S,
                        double *F, int *delta)
@@ -346,15 +473,15 @@ static void iface_flux(const orc_params *P, int d, const double *Uk, const doubl
     for (int j = 0; j < nc; j++) {
         double alpha = 0.0;
         for (int k = 0; k < 6; k++) alpha = fmax(alpha, fabs(lam[k][j]));
-        double gp[5], gm[5];
-        for (int m = 0; m < 5; m++) {
+        double gp[6], gm[6];
+        for (int m = 0; m < 6; m++) {
             gp[m] = 0.5 * (G[m][j] + alpha * V[m][j]);          /* k = i-2+m   */
             gm[m] = 0.5 * (G[5 - m][j] - alpha * V[5 - m][j]);  /* k = i+3-m   */
         }
-        int *dp = delta ? delta + (j * 2 + 0) * 3 : NULL;
-        int *dm = delta ? delta + (j * 2 + 1) * 3 : NULL;
-        ghat[j] = recon5(P->scheme, P->teno_CT, P->eps, gp, dp)
-                + recon5(P->scheme, P->teno_CT, P->eps, gm, dm);
+        int *dp = delta ? delta + (j * 2 + 0) * 4 : NULL;
+        int *dm = delta ? delta + (j * 2 + 1) * 4 : NULL;
+        ghat[j] = recon(P->scheme, P->teno_CT, P->eps, gp, dp)
+                + recon(P->scheme, P->teno_CT, P->eps, gm, dm);
     }
     for (int c = 0; c < nc; c++) {
         double s = 0.0;
@@ -589,7 +716,9 @@ static void half_area(const grid_t *g, const double *S, int d, int64_t e, double
  * Section 3.1 (boundary and initial conditions): BCs per (direction, side),
  * enforced through three ghost nodes.
  *   periodic: copy; extrapolation (reading: zero-gradient copy of the
- *   boundary node);
+ *   boundary node); Dirichlet (the Shu-Osher case of section 5.2): the
+ *   ghost values are the boundary data, set with the initial state and
+ *   left unchanged;
  *   isothermal wall (eq. wall_energy, eq. halo_density and the momentum
  *   reflection): wall node momentum = 0, rho E_w = rho_w T_w/(M^2 gamma
  *   (gamma-1)) with rho_w floating; p_w = rho_w T_w/(gamma M^2) (reading);
@@ -671,6 +800,9 @@ void orc_apply_bc(const orc_params *P, double *U)
                                 for (int c = 0; c < nc; c++) U[c * g.npts + eg] = U[c * g.npts + es];
                             } else if (kind == BC_EXTRAPOLATE) {
                                 for (int c = 0; c < nc; c++) U[c * g.npts + eg] = U[c * g.npts + ew];
+                            } else if (kind == BC_DIRICHLET) {
+                                /* boundary data: the ghost values the state
+                                 * was given, never overwritten */
                             } else {
                                 double Tw, T1, ui[3], Ti;
                                 node_T(P, nd, U, ew, g.npts, &Tw, NULL);
@@ -842,19 +974,94 @@ int orc_residual(const orc_params *P, const double *S, const double *J, const do
 
 /* --------------------------------------------------------- time stepping --
  * Low-storage Runge-Kutta in Williamson's 2N form (section 2.7):
- *   dU^(s) = A_s dU^(s-1) + dt R(U^(s-1)),  U^(s) = U^(s-1) + B_s dU^(s).
- * The coefficients are not printed (cited to Carpenter & Kennedy); reading:
- * the three-stage third-order 2N scheme A = (0, -5/9, -153/128),
- * B = (1/3, 15/16, 8/15).  Stage 0 does not read dU.
+ *   dU^(s) = A_s dU^(s-1) + dt R(U^(s-1)),  U^(s) = U^(s-1) + B_s dU^(s),
+ * A_1 = 0 (stage 0 does not read dU).  The coefficients are not printed;
+ * they are cited to Carpenter & Kennedy (third and fourth order) and to
+ * Gottlieb (the strong-stability-preserving third-order version).  Readings:
+ *   RK3_WILLIAMSON: the three-stage third-order 2N scheme
+ *       A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15);
+ *   RK4_CK: Carpenter & Kennedy's five-stage fourth-order 2N scheme (their
+ *       published rational coefficients, below);
+ *   RK3_SSP: the three-stage third-order 2N scheme of Gottlieb & Shu with
+ *       c_2 = B_1 = 0.924574 (the member of the one-parameter 2N family that
+ *       they found to be strong-stability preserving); the other four
+ *       coefficients follow from c_2 by the third-order conditions and the
+ *       2N structure (ssp_rk3 below).
  */
-static const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
-static const double RK_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+static const double RK3W_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+static const double RK3W_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+static const double RK4CK_A[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                                  -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+static const double RK4CK_B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                                  1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                                  2277821191437.0 / 14882151754819.0};
+
+/* The 2N third-order family given c_2.  With k_s = dt R(U^(s-1)), the 2N
+ * update is the explicit RK scheme with a_21 = B_1, a_31 = B_1 + B_2 A_2,
+ * a_32 = B_2, b_1 = a_31 + B_3 A_3 A_2, b_2 = B_2 + B_3 A_3, b_3 = B_3.
+ * Third order fixes, for nodes c_2 and c_3 = a_31 + a_32,
+ *   b_3 = (1/3 - c_2/2) / (c_3 (c_3 - c_2)),  b_2 = (1/3 - c_3/2) / (c_2 (c_2 - c_3)),
+ *   a_32 = 1 / (6 b_3 c_2),  b_1 = 1 - b_2 - b_3,
+ * and the 2N structure then gives B_2 = a_32, A_2 = (c_3 - a_32 - c_2)/a_32,
+ * B_3 = b_3, A_3 = (b_2 - B_2)/B_3, and leaves one condition on c_3:
+ *   resid(c_3) = b_1 - (c_2 + B_2 A_2 + B_3 A_3 A_2) = 0. */
+static double ssp_resid(double c2, double c3, double *A, double *B)
+{
+    const double b3 = (1.0 / 3.0 - c2 / 2.0) / (c3 * (c3 - c2));
+    const double b2 = (1.0 / 3.0 - c3 / 2.0) / (c2 * (c2 - c3));
+    const double a32 = 1.0 / (6.0 * b3 * c2);
+    const double b1 = 1.0 - b2 - b3;
+    A[0] = 0.0;
+    B[0] = c2;
+    B[1] = a32;
+    A[1] = (c3 - a32 - c2) / a32;
+    B[2] = b3;
+    A[2] = (b2 - B[1]) / B[2];
+    return b1 - (B[0] + B[1] * A[1] + B[2] * A[2] * A[1]);
+}
+
+/* c_3 by bisection on [0.2, 0.6], where resid changes sign once for
+ * c_2 = 0.924574 (c_3 = 0.37346...); 200 halvings reach the double
+ * closest to the root. */
+static void ssp_rk3(double *A, double *B)
+{
+    const double c2 = 0.924574;
+    double lo = 0.2, hi = 0.6;
+    double flo = ssp_resid(c2, lo, A, B);
+    for (int it = 0; it < 200; it++) {
+        const double mid = 0.5 * (lo + hi);
+        const double fm = ssp_resid(c2, mid, A, B);
+        if ((fm < 0.0) == (flo < 0.0)) { lo = mid; flo = fm; } else { hi = mid; }
+    }
+    ssp_resid(c2, 0.5 * (lo + hi), A, B);
+}
+
+static int rk_stages(const orc_params *P) { return P->rk == RK4_CK ? 5 : 3; }
+
+static void rk_coeffs(const orc_params *P, double *A, double *B)
+{
+    if (P->rk == RK4_CK) {
+        for (int s = 0; s < 5; s++) { A[s] = RK4CK_A[s]; B[s] = RK4CK_B[s]; }
+    } else if (P->rk == RK3_SSP) {
+        ssp_rk3(A, B);
+    } else {
+        for (int s = 0; s < 3; s++) { A[s] = RK3W_A[s]; B[s] = RK3W_B[s]; }
+    }
+}
+
+void orc_rk_coeffs(const orc_params *P, double *A, double *B, int *nstages)
+{
+    rk_coeffs(P, A, B);
+    *nstages = rk_stages(P);
+}
 
 int orc_rk_update(const orc_params *P, int stage, double dt, const double *R, double *U, double *dU)
 {
     grid_t g;
     grid_make(P, &g);
     const int64_t ni = g.nint;
+    double RK_A[5], RK_B[5];
+    rk_coeffs(P, RK_A, RK_B);
     for (int c = 0; c < g.nc; c++)
         for (int64_t k = 0; k < g.n[2]; k++)
             for (int64_t j = 0; j < g.n[1]; j++)
@@ -924,7 +1131,7 @@ double orc_compute_dt(const orc_params *P, const double *S, const double *J, con
 }
 
 /* Whole run: BCs at t = 0, then per step dt (fixed, or from CFL, clipped to
- * t_end), three substeps each followed by the BCs. */
+ * t_end), the scheme's substeps (three or five) each followed by the BCs. */
 int orc_run(const orc_params *P, const double *S, const double *J, double *U, double *dU,
             int64_t nsteps, double cfl, double dt_fixed, double t_end, double *t_out)
 {
@@ -934,7 +1141,7 @@ int orc_run(const orc_params *P, const double *S, const double *J, double *U, do
         if (t_end > 0.0 && t >= t_end) break;
         double dt = dt_fixed > 0.0 ? dt_fixed : orc_compute_dt(P, S, J, U, cfl);
         if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
-        for (int s = 0; s < 3; s++) {
+        for (int s = 0; s < rk_stages(P); s++) {
             orc_rk_substep(P, S, J, s, dt, U, dU);
             orc_apply_bc(P, U);
         }
@@ -947,6 +1154,13 @@ int orc_run(const orc_params *P, const double *S, const double *J, double *U, do
 /* ------------------------------------------------ exported unit pieces -- */
 
 void orc_smoothness5(const double *f, double *beta) { smoothness5(f, beta); }
+
+double orc_recon(int scheme, double CT, double eps, const double *f, int *delta)
+{
+    return recon(scheme, CT, eps, f, delta);
+}
+
+double orc_smoothness6(const double *f, double *beta) { return smoothness6(f, beta); }
 
 double orc_recon5(int scheme, double CT, double eps, const double *f, int *delta)
 {
@@ -1152,11 +1366,11 @@ void orc_features(const orc_params *P, int d, const double *Uk, const double *S,
         feat[7 + m] = log10(1.0 + 1e6 * jp) / 6.0;
     }
     if (label) {
-        int dl[NCMAX * 2 * 3];
+        int dl[NCMAX * 2 * 4];
         double F[NCMAX];
         iface_flux(P, d, Uk, S, F, dl);
         int all = 1;
-        for (int i = 0; i < nc * 2 * 3; i++) all &= dl[i];
+        for (int i = 0; i < nc * 2 * 4; i++) all &= dl[i];
         *label = all;
     }
 }

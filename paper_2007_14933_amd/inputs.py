@@ -18,9 +18,14 @@ from typing import Optional, Tuple
 
 import numpy as np
 
-PERIODIC, EXTRAPOLATE, ISOTHERMAL, ADIABATIC = 0, 1, 2, 3
-WENOZ5, TENO5 = 0, 1
+PERIODIC, EXTRAPOLATE, ISOTHERMAL, ADIABATIC, DIRICHLET = 0, 1, 2, 3, 4
+WENOZ5, TENO5, TENO6, WENOJS5, WENOZ3 = 0, 1, 2, 3, 4
+RK3, RK3_SSP, RK4 = 0, 1, 2       # low-storage Runge-Kutta schemes (3, 3 and 5 substages)
 NGHOST = 3
+
+
+def rk_stages(rk):
+    return 5 if rk == RK4 else 3
 
 
 @dataclass
@@ -38,6 +43,7 @@ class Problem:
     teno_CT: float = 1e-5
     eps: float = 1e-16
     roe_avg: int = 1
+    rk: int = RK3
     bc: Tuple = ((PERIODIC, PERIODIC),) * 3
     wall_T: Tuple = ((1.0, 1.0),) * 3
     period: Tuple[float, float, float] = (0.0, 0.0, 0.0)
@@ -138,6 +144,32 @@ def sod(N=400, scheme=WENOZ5, t_end=0.2, cfl=0.5):
                    t_end=t_end, nsteps=10 ** 9)
 
 
+# ----------------------------------------------------- 1D Shu-Osher
+def shu_osher(N=320, scheme=WENOZ5, t_end=1.8, dt=2e-4):
+    """Shock / density-wave interaction: a Mach-3 shock at x = -4 moving into
+    rho = 1 + 0.2 sin(5x) on [-5, 5], N cell-centred points, Dirichlet ends
+    (ghost nodes hold the initial states: the post-shock state on the left,
+    the undisturbed wave on the right), inviscid, fixed dt.  The printed
+    right state (u, p) = (1, 0) is read as the standard (0, 1): p = 0 is not
+    a gas state, and the standard set-up is a shock running into fluid at
+    rest."""
+    g = 1.4
+    h = 10.0 / N
+    xe = -5.0 + (np.arange(-NGHOST, N + NGHOST) + 0.5) * h   # nodes incl. ghosts
+    left = xe < -4.0
+    rho = np.where(left, 3.857143, 1.0 + 0.2 * np.sin(5.0 * xe))
+    u = np.where(left, 2.629369, 0.0)
+    p = np.where(left, 10.33333, 1.0)
+    U = np.zeros(ext_shape(1, (N, 1, 1)))
+    for c, a in enumerate(conserved(g, rho, [u], p)):
+        U[c, 0, 0, :] = a
+    x = xe[NGHOST:-NGHOST].copy()
+    return Problem(name="shuosher%d" % N, ndim=1, n=(N, 1, 1), gamma=g, Re=0.0, scheme=scheme,
+                   bc=((DIRICHLET, DIRICHLET), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)),
+                   period=(10.0, 0.0, 0.0), coords1d=(x, None, None), U0=U, t_end=t_end,
+                   dt_fixed=dt, nsteps=int(round(t_end / dt)))
+
+
 # ----------------------------------------------------- 3D Taylor-Green vortex
 def tgv(N=256, Re=1600.0, M=0.1, Pr=0.71, scheme=TENO5, nsteps=200, cfl=0.5):
     """Taylor-Green vortex on the periodic box [0, 2 pi)^3: u = sin x cos y cos z,
@@ -185,7 +217,20 @@ def density_wave(N=32, mesh="sinusoidal", scheme=WENOZ5, t=0.0, u=1.0, v=-0.5):
                    coords_full=coords_full, U0=U)
 
 
+def density_wave_1d(N=32, scheme=WENOZ5, u=1.0, rk=RK3):
+    """One-dimensional travelling density wave rho = 1 + 0.2 sin(pi (x - u t)),
+    u = 1, p = 1, periodic on [0, 2)."""
+    g = 1.4
+    x = 2.0 * np.arange(N) / N
+    rho = 1.0 + 0.2 * np.sin(math.pi * x)
+    U = _state(1, (N, 1, 1), [a.reshape(1, 1, N) for a in conserved(g, rho, [u + 0 * x], 1.0 + 0 * x)])
+    return Problem(name="dwave1d_%d" % N, ndim=1, n=(N, 1, 1), gamma=g, Re=0.0, scheme=scheme, rk=rk,
+                   period=(2.0, 0.0, 0.0), coords1d=(x, None, None), U0=U, meta={"u": u})
+
+
 def exact_density_wave(prob, t, u=1.0, v=-0.5):
+    if prob.ndim == 1:
+        return 1.0 + 0.2 * np.sin(math.pi * (prob.coords[0] - t * prob.meta.get("u", u)))
     X, Y = prob.coords[0], prob.coords[1]
     return 1.0 + 0.2 * np.sin(math.pi * (X + Y - t * (u + v)))
 

@@ -1,0 +1,390 @@
+"""Pins of the oracle's further schemes against what the paper and the
+mathematics fix: sixth-order TENO (section 2.5, K = 6), the original WENO
+weights (section 2.3, eqs. omega and alpha), third-order WENO-Z (the orders of
+section 5.2), the strong-stability-preserving and fourth-order low-storage
+Runge-Kutta schemes (section 2.7), and the Dirichlet ends of the Shu-Osher
+case (section 5.2).  Each pin is independent of the oracle's own formulas:
+polynomial exactness, the integral definition of the indicators, exact
+rational cut-off decisions, order conditions of the Butcher tableau, the
+Rankine-Hugoniot relations, convergence orders."""
+import math
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2007_14933_amd import inputs as I
+
+
+def cell_avg_weights(left, npts):
+    """Weights on f_{left..left+npts-1} of the reconstruction h(x_{i+1/2}) for
+    every polynomial h of degree < npts whose cell averages are the f_j (unit
+    cells, cell i = [-1/2, 1/2]); from exactness on monomials."""
+    xs = np.arange(left, left + npts, dtype=float)
+    A = np.zeros((npts, npts))
+    b = np.zeros(npts)
+    for p in range(npts):
+        for m, xj in enumerate(xs):
+            A[p, m] = ((xj + 0.5) ** (p + 1) - (xj - 0.5) ** (p + 1)) / (p + 1)
+        b[p] = 0.5 ** p
+    return np.linalg.solve(A, b)
+
+
+def sin_cell_averages(x0, h, left, npts):
+    x = x0 + h * np.arange(left, left + npts)
+    return (np.cos(x - h / 2) - np.cos(x + h / 2)) / h
+
+
+# ------------------------------------------------------------------ TENO6
+def test_teno6_indicators_match_their_integral_definition():
+    """beta_r = sum_l int_{cell i} (q_r^{(l)})^2 for the interpolating
+    polynomial q_r of each candidate (eq. smoothness_indicator): the three
+    quadratics and the cubic on {i..i+3}, by exact polynomial algebra."""
+    rng = np.random.default_rng(21)
+    stencils = [(0, 3), (-1, 3), (-2, 3), (0, 4)]     # (first offset from i, points)
+    for _ in range(40):
+        f = rng.normal(size=6)                        # f_{i-2..i+3}
+        beta, _ = O.smoothness6(f)
+        for r, (left, npts) in enumerate(stencils):
+            centres = np.arange(left, left + npts, dtype=float)
+            vals = f[2 + left: 2 + left + npts]
+            # polynomial sum c_m x^m with the given cell averages
+            A = np.array([[((xc + 0.5) ** (m + 1) - (xc - 0.5) ** (m + 1)) / (m + 1) for m in range(npts)]
+                          for xc in centres])
+            poly = np.polynomial.Polynomial(np.linalg.solve(A, vals))
+            ref, d = 0.0, poly
+            for _l in range(1, npts):
+                d = d.deriv()
+                ip = (d * d).integ()
+                ref += ip(0.5) - ip(-0.5)
+            assert abs(beta[r] - ref) <= 1e-11 * (1 + ref), (r, beta[r], ref)
+
+
+def test_teno6_linear_limit_is_the_sixth_order_reconstruction():
+    """All four stencils kept: the optimal weights combine the candidates into
+    the six-point reconstruction that is exact for polynomials of degree <= 5
+    (derived here from exactness, (1, -8, 37, 37, -8, 1)/60)."""
+    w = cell_avg_weights(-2, 6)
+    assert np.allclose(w * 60, [1, -8, 37, 37, -8, 1], atol=1e-11)
+    h = 0.05
+    for x0 in np.linspace(0.0, 1.0, 13):
+        f = np.exp(0.3 * (x0 + h * np.arange(-2, 4))) + 0.2
+        v, dl = O.recon(I.TENO6, 1e-5, 1e-16, f)
+        assert list(dl) == [1, 1, 1, 1]
+        assert abs(v - w @ f) <= 2e-15 * np.abs(f).max()
+
+
+def test_teno6_sixth_order_on_smooth_data():
+    errs = []
+    for h in (0.2, 0.1, 0.05):
+        f = sin_cell_averages(0.37, h, -2, 6)
+        v, _ = O.recon(I.TENO6, 1e-5, 1e-16, f)
+        errs.append(abs(v - math.sin(0.37 + h / 2)))
+    assert math.log2(errs[0] / errs[1]) > 5.5 and math.log2(errs[1] / errs[2]) > 5.5, errs
+
+
+def test_teno6_global_indicator_weights_the_central_stencil():
+    """tau_6 = |beta_3 - (beta_0 + beta_2 + 4 beta_1)/6| with beta_1 the
+    central stencil's: on smooth data it falls at higher order than any
+    other weighting of the three-point indicators (those leave an
+    h^4 f' f''' term), so tau_6 / beta -> 0 and TENO keeps every stencil."""
+    for x0 in (0.37, 1.1):
+        t, wrong = [], []
+        for h in (0.1, 0.05, 0.025):
+            f = sin_cell_averages(x0, h, -2, 6)
+            beta, tau = O.smoothness6(f)
+            t.append(tau)
+            wrong.append(abs(beta[3] - (beta[1] + beta[2] + 4 * beta[0]) / 6))
+        o = [math.log2(t[i] / t[i + 1]) for i in range(2)]
+        ow = [math.log2(wrong[i] / wrong[i + 1]) for i in range(2)]
+        assert min(o) > 4.8 and max(ow) < 4.3, (o, ow)
+
+
+@pytest.mark.parametrize("jump,delta", [(1, [0, 1, 1, 0]), (2, [1, 1, 1, 0]), (0, [0, 0, 1, 0])])
+def test_teno6_cuts_the_stencils_that_cross_a_jump(jump, delta):
+    """f = 0 up to node i + jump, 1 beyond: exactly the candidates containing
+    both sides are removed and the kept ones reproduce the constant 0."""
+    f = np.array([0.0 if k - 2 <= jump else 1.0 for k in range(6)])
+    v, dl = O.recon(I.TENO6, 1e-5, 1e-16, f)
+    assert list(dl) == delta and v == 0.0
+
+
+def _teno6_decisions(f, q, C, CT=Fr(1, 100000), eps=Fr(1e-16)):
+    """Cut-off decisions in exact rational arithmetic from the indicators'
+    closed forms (pinned above against their integral definition)."""
+    fm2, fm1, f0, fp1, fp2, fp3 = [Fr(v) for v in f]
+    b0 = Fr(13, 12) * (f0 - 2 * fp1 + fp2) ** 2 + Fr(1, 4) * (3 * f0 - 4 * fp1 + fp2) ** 2
+    b1 = Fr(13, 12) * (fm1 - 2 * f0 + fp1) ** 2 + Fr(1, 4) * (fm1 - fp1) ** 2
+    b2 = Fr(13, 12) * (fm2 - 2 * fm1 + f0) ** 2 + Fr(1, 4) * (fm2 - 4 * fm1 + 3 * f0) ** 2
+    a, b, c = -11 * f0 + 18 * fp1 - 9 * fp2 + 2 * fp3, 2 * f0 - 5 * fp1 + 4 * fp2 - fp3, -f0 + 3 * fp1 - 3 * fp2 + fp3
+    b3 = a * a / 36 + Fr(13, 12) * b * b + Fr(781, 720) * c * c
+    betas = [b0, b1, b2, b3]
+    tau = abs(b3 - (b0 + b2 + 4 * b1) / 6)
+    g = [(C + tau / (br + eps)) ** q for br in betas]
+    s = sum(g)
+    return [0 if gr / s < CT else 1 for gr in g]
+
+
+def test_teno6_exponent_q6_and_C1():
+    """Integer data whose cut-off decisions change between q = 5, 6, 7 and
+    between C = 0, 1, 2 (eq. TENO_weights prints C = 1, q = 6): the oracle
+    takes the (6, 1) decisions, and its value is the kept candidates with
+    the renormalised optimal weights."""
+    data = [[0, 1, -5, -4, 1, 0], [2, -6, 6, 2, -2, 4], [-5, 3, -3, -5, -2, -5], [-1, 5, -5, -2, 5, 4]]
+    d = [Fr(3, 10), Fr(9, 20), Fr(1, 20), Fr(1, 5)]
+    distinguished = set()
+    for f in data:
+        ref = _teno6_decisions(f, 6, 1)
+        for alt in ((5, 1), (7, 1), (6, 0), (6, 2)):
+            if _teno6_decisions(f, *alt) != ref:
+                distinguished.add(alt)
+        v, dl = O.recon(I.TENO6, 1e-5, 1e-16, np.array(f, dtype=float))
+        assert list(dl) == ref, (f, list(dl), ref)
+        fm2, fm1, f0, fp1, fp2, fp3 = [Fr(x) for x in f]
+        q = [f0 / 3 + 5 * fp1 / 6 - fp2 / 6, -fm1 / 6 + 5 * f0 / 6 + fp1 / 3,
+             fm2 / 3 - 7 * fm1 / 6 + 11 * f0 / 6, f0 / 4 + 13 * fp1 / 12 - 5 * fp2 / 12 + fp3 / 12]
+        exact = sum(d[r] * ref[r] * q[r] for r in range(4)) / sum(d[r] * ref[r] for r in range(4))
+        assert abs(v - float(exact)) <= 1e-14 * (1 + abs(float(exact)))
+    assert distinguished == {(5, 1), (7, 1), (6, 0), (6, 2)}
+
+
+@pytest.mark.parametrize("scheme,eps", [(I.TENO6, 1e-16), (I.WENOJS5, 1e-6), (I.WENOZ3, 1e-16)])
+def test_recon_odd_scale_shift(scheme, eps):
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        f = rng.normal(size=6)
+        v, d1 = O.recon(scheme, 1e-5, eps, f)
+        vm, d2 = O.recon(scheme, 1e-5, eps, -f)
+        assert vm == -v and list(d1) == list(d2)
+        vs, _ = O.recon(scheme, 1e-5, eps, f + 0.75)
+        assert abs(vs - (v + 0.75)) <= 1e-12 * (1 + np.abs(f).max())
+        if scheme != I.WENOJS5:   # the JS weights are not scale invariant (eps is absolute)
+            v4, _ = O.recon(scheme, 1e-5, eps, 4.0 * f)
+            assert abs(v4 - 4.0 * v) <= 1e-13 * np.abs(f).max() * 4
+
+
+# --------------------------------------------------------------- WENO-JS5
+def test_wenojs5_weights_at_a_jump_in_closed_form():
+    """f = (0, 0, 0, 0, 1): beta_1 = beta_2 = 0, beta_0 = 13/12 + 1/4 = 4/3, so
+    with alpha_r = d_r / (eps + beta_r)^2 (p = 2) the value is
+    -(1/6) omega_0, omega_0 = alpha_0 / sum alpha, eps = 1e-6 (the paper's
+    value for this scheme): about -4e-14 (with p = 1 it would be -3e-8)."""
+    eps = Fr(1e-6)
+    a0 = Fr(3, 10) / (eps + Fr(4, 3)) ** 2
+    a1 = Fr(3, 5) / eps ** 2
+    a2 = Fr(1, 10) / eps ** 2
+    exact = -Fr(1, 6) * a0 / (a0 + a1 + a2)
+    v, dl = O.recon(I.WENOJS5, 0.0, 1e-6, np.array([0.0, 0.0, 0.0, 0.0, 1.0, 0.0]))
+    assert abs(v - float(exact)) <= 1e-12 * abs(float(exact)) and list(dl) == [1, 1, 1, 1]
+
+
+def test_wenojs5_fifth_order_on_smooth_data():
+    w = cell_avg_weights(-2, 5)
+    for x0 in (0.37, 1.0):
+        errs = []
+        for h in (0.1, 0.05, 0.025):
+            f = sin_cell_averages(x0, h, -2, 6)
+            v, _ = O.recon(I.WENOJS5, 0.0, 1e-6, f)
+            errs.append(abs(v - math.sin(x0 + h / 2)))
+            # close to the linear scheme (omega -> d)
+            assert abs(v - w @ f[:5]) <= 50 * errs[-1] + 1e-15
+        assert math.log2(errs[0] / errs[1]) > 4.5 and math.log2(errs[1] / errs[2]) > 4.5, errs
+
+
+# ---------------------------------------------------------------- WENO-3Z
+def test_wenoz3_linear_limit_and_order():
+    """Equal indicators (f_{i-1} = f_{i+1}) give tau_3 = 0 and the optimal
+    weights: the third-order reconstruction on i-1..i+1, derived from
+    exactness; away from critical points the scheme is third order."""
+    w = cell_avg_weights(-1, 3)
+    assert np.allclose(w * 6, [-1, 5, 2], atol=1e-12)
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        a, b = rng.normal(size=2)
+        f = np.array([7.0, a, b, a, -3.0, 9.0])
+        v, _ = O.recon(I.WENOZ3, 0.0, 1e-16, f)
+        assert abs(v - w @ f[1:4]) <= 1e-14 * (1 + abs(a) + abs(b))
+    errs = []
+    for h in (0.05, 0.025, 0.0125):
+        v, _ = O.recon(I.WENOZ3, 0.0, 1e-16, sin_cell_averages(0.37, h, -2, 6))
+        errs.append(abs(v - math.sin(0.37 + h / 2)))
+    assert math.log2(errs[0] / errs[1]) > 2.8 and math.log2(errs[1] / errs[2]) > 2.8, errs
+
+
+def test_wenoz3_is_essentially_non_oscillatory_at_a_jump():
+    v, _ = O.recon(I.WENOZ3, 0.0, 1e-16, np.array([5.0, 0.0, 0.0, 1.0, 1.0, 1.0]))
+    assert 0.0 <= v < 1e-20
+    v, _ = O.recon(I.WENOZ3, 0.0, 1e-16, np.array([5.0, 0.0, 1.0, 1.0, 1.0, 1.0]))
+    assert abs(v - 1.0) < 1e-15
+
+
+# -------------------------------------------------- solver: spatial order
+@pytest.mark.parametrize("scheme,eps,order", [(I.TENO6, 1e-16, 5.5), (I.WENOJS5, 1e-6, 4.5),
+                                              (I.WENOZ3, 1e-16, 1.9)])
+def test_density_wave_1d_convergence(scheme, eps, order):
+    """The travelling density wave in 1D (periodic, dt small enough that the
+    time error is negligible): L1 error order on N = 40, 80, 160.  WENO-3Z
+    is limited to second order by the wave's critical points (the known
+    behaviour of third-order WENO there), the others reach their formal
+    orders."""
+    e = []
+    for N in (40, 80, 160):
+        p = I.density_wave_1d(N, scheme=scheme).with_(eps=eps)
+        S, J = O.metrics(p)
+        U = p.U0.copy()
+        O.run(p, S, J, U, 10 ** 6, dt_fixed=2e-4, t_end=0.2)
+        e.append(np.abs(O.interior(p, U)[0].ravel() - I.exact_density_wave(p, 0.2).ravel()).mean())
+    o = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert min(o) >= order, (o, e)
+
+
+# ----------------------------------------------------------- Runge-Kutta
+def butcher_from_2n(A, B):
+    """Explicit Butcher tableau (a, b, c) of the 2N scheme
+    dU_s = A_s dU_{s-1} + k_s, U_s = U_{s-1} + B_s dU_s, k_s = dt R(U_{s-1})."""
+    s = len(A)
+    D = np.zeros((s, s))       # dU_s = sum_j D[s, j] k_j
+    Um = np.zeros((s + 1, s))  # U_s - U_0 = sum_j Um[s, j] k_j
+    for i in range(s):
+        if i > 0:
+            D[i] = A[i] * D[i - 1]
+        D[i, i] += 1.0
+        Um[i + 1] = Um[i] + B[i] * D[i]
+    a = Um[:s].copy()
+    return a, Um[s].copy(), a.sum(axis=1)
+
+
+def order_conditions(a, b, c, order):
+    conds = [b.sum() - 1, b @ c - 1 / 2, b @ c ** 2 - 1 / 3, b @ (a @ c) - 1 / 6]
+    if order >= 4:
+        conds += [b @ c ** 3 - 1 / 4, b @ (c * (a @ c)) - 1 / 8, b @ (a @ c ** 2) - 1 / 12,
+                  b @ (a @ (a @ c)) - 1 / 24]
+    return np.abs(conds)
+
+
+@pytest.mark.parametrize("rk,order,stages", [(I.RK3, 3, 3), (I.RK3_SSP, 3, 3), (I.RK4, 4, 5)])
+def test_rk_order_conditions(rk, order, stages):
+    A, B = O.rk_coeffs(I.tgv(8).with_(rk=rk))
+    assert len(A) == stages and A[0] == 0.0
+    a, b, c = butcher_from_2n(A, B)
+    assert order_conditions(a, b, c, order).max() <= 2e-15
+    if order == 3:   # and not fourth order
+        assert b @ c ** 3 - 1 / 4 != 0.0 or b @ (a @ (a @ c)) - 1 / 24 != 0.0
+
+
+def ssp_nonneg(a, b, r):
+    """Kraaijevanger's criterion: with K = [[a, 0], [b^T, 0]], the scheme is
+    strong-stability preserving under the step restriction dt <= r dt_FE iff
+    (I + r K)^-1 K >= 0 and (I + r K)^-1 e >= 0 elementwise."""
+    s = len(b)
+    K = np.zeros((s + 1, s + 1))
+    K[:s, :s] = a
+    K[s, :s] = b
+    M = np.linalg.inv(np.eye(s + 1) + r * K)
+    return (M @ K).min() >= -1e-13 and (M @ np.ones(s + 1)).min() >= -1e-13
+
+
+def test_ssp_rk3_is_strong_stability_preserving():
+    """The reading of the SSP version: B_1 = c_2 = 0.924574, and the scheme
+    is SSP with coefficient at least 0.3 (Gottlieb and Shu give 0.32), while
+    the default third-order scheme has negative coefficients at any r > 0."""
+    A, B = O.rk_coeffs(I.tgv(8).with_(rk=I.RK3_SSP))
+    assert B[0] == 0.924574
+    a, b, _ = butcher_from_2n(A, B)
+    assert ssp_nonneg(a, b, 0.30)
+    assert not ssp_nonneg(a, b, 0.40)
+    A3, B3 = O.rk_coeffs(I.tgv(8).with_(rk=I.RK3))
+    a3, b3, _ = butcher_from_2n(A3, B3)
+    assert not ssp_nonneg(a3, b3, 0.05)
+
+
+@pytest.mark.parametrize("rk", [I.RK3_SSP, I.RK4])
+def test_rk_stability_polynomial(rk):
+    """One step of the oracle's update on u' = z u equals the stability
+    polynomial sum_k z^k b^T a^(k-1) e: 1 + z + z^2/2 + z^3/6 (+ z^4/24 +
+    gamma_5 z^5 for the five-stage scheme)."""
+    p = I.Problem(name="rk", ndim=1, n=(5, 1, 1), rk=rk)
+    A, B = O.rk_coeffs(p)
+    a, b, _ = butcher_from_2n(A, B)
+    s = len(b)
+    coef = [1.0] + [b @ np.linalg.matrix_power(a, k - 1) @ np.ones(s) for k in range(1, s + 1)]
+    ref_c = [1, 1, 1 / 2, 1 / 6, 1 / 24]
+    for k in range(min(len(coef), 4 if s == 3 else 5)):
+        assert abs(coef[k] - ref_c[k]) <= 1e-14
+    for z in (-0.7, 0.3, -2.1):
+        U = np.zeros(O.ext_shape(p))
+        U[:, :, :, 3:-3] = 1.0
+        dU = np.zeros(O.int_shape(p))
+        for st in range(s):
+            R = z * O.interior(p, U).copy()
+            O.rk_update(p, st, 1.0, np.ascontiguousarray(R), U, dU)
+        assert abs(O.interior(p, U)[0, 0, 0, 0] - sum(coef[k] * z ** k for k in range(s + 1))) < 1e-14
+
+
+@pytest.mark.parametrize("rk,order", [(I.RK3, 3.0), (I.RK3_SSP, 3.0), (I.RK4, 4.0)])
+def test_rk_temporal_convergence(rk, order):
+    """Fixed grid (1D density wave, N = 40, WENO-Z5), dt halved twice against
+    a 4000-step reference: the time error falls at the scheme's order."""
+    p = I.density_wave_1d(40, scheme=I.WENOZ5, rk=rk)
+    S, J = O.metrics(p)
+
+    def run(n):
+        U = p.U0.copy()
+        O.run(p, S, J, U, 10 ** 6, dt_fixed=0.5 / n, t_end=0.5)
+        return O.interior(p, U)[0].ravel()
+    ref = run(4000)
+    e = [np.abs(run(n) - ref).max() for n in (20, 40, 80)]
+    o = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert min(o) >= order - 0.1, (o, e)
+
+
+# -------------------------------------------------------- Shu-Osher, Dirichlet
+def test_shu_osher_left_state_is_a_mach3_shock_into_the_read_right_state():
+    """The printed left state is the post-shock state of a Mach-3 shock
+    running into (rho, u, p) = (1, 0, 1) (Rankine-Hugoniot), which pins the
+    reading of the garbled right state (u, p) = (1, 0) as (0, 1)."""
+    g, M = 1.4, 3.0
+    r2 = (g + 1) * M * M / ((g - 1) * M * M + 2)
+    p2 = 1 + 2 * g / (g + 1) * (M * M - 1)
+    us = M * math.sqrt(g)                 # shock speed into rho = p = 1 at rest
+    u2 = us * (1 - 1 / r2)
+    p = I.shu_osher(320)
+    U = O.interior(p, p.U0)
+    rho, u = U[0, 0, 0, 0], U[1, 0, 0, 0] / U[0, 0, 0, 0]
+    pr = (g - 1) * (U[2, 0, 0, 0] - 0.5 * rho * u * u)
+    assert abs(rho - r2) < 5e-7 and abs(u - u2) < 5e-7 and abs(pr - p2) < 5e-6, (rho, u, pr, r2, u2, p2)
+
+
+def test_dirichlet_ghosts_are_left_unchanged():
+    p = I.shu_osher(64)
+    U = p.U0.copy()
+    U[:, :, :, 3:-3] *= 1.1      # the interior moves, the boundary data must not
+    out = O.apply_bc(p, U.copy())
+    assert np.array_equal(out[..., :3], p.U0[..., :3]) and np.array_equal(out[..., -3:], p.U0[..., -3:])
+
+
+def test_shu_osher_higher_order_resolves_the_entropy_waves():
+    """Section 5.2's comparison on N = 320 to t = 1.8 (dt 2e-4): the shock
+    sits where a Mach-3 shock started at x = -4 lands (x ~ 2.4), and in the
+    high-frequency region behind it (0.5 < x < 2.2) WENO-5Z lies much closer
+    than WENO-3Z to a fine WENO-5Z solution (N = 960, averaged to the coarse
+    cells)."""
+    sols = {}
+    for sc, N in ((I.WENOZ3, 320), (I.WENOZ5, 320), (I.WENOZ5, 960)):
+        p = I.shu_osher(N, scheme=sc)
+        S, J = O.metrics(p)
+        U = p.U0.copy()
+        t = O.run(p, S, J, U, p.nsteps, dt_fixed=p.dt_fixed)
+        assert abs(t - 1.8) < 1e-9
+        rho = O.interior(p, U)[0].ravel()
+        x = p.coords1d[0]
+        k = int(np.argmax(np.abs(np.diff(rho))))
+        assert 2.3 < 0.5 * (x[k] + x[k + 1]) < 2.5
+        sols[(sc, N)] = rho
+    fine = sols[(I.WENOZ5, 960)].reshape(320, 3).mean(axis=1)
+    x = I.shu_osher(320).coords1d[0]
+    hf = (x > 0.5) & (x < 2.2)
+    e3 = np.abs(sols[(I.WENOZ3, 320)] - fine)[hf].mean()
+    e5 = np.abs(sols[(I.WENOZ5, 320)] - fine)[hf].mean()
+    assert e5 < 0.5 * e3, (e3, e5)
