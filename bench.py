@@ -26,6 +26,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
+def log(*a):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,7 +465,9 @@ def main():
 
     n = args.n
     prob = inputs.tgv(n)
+    log("copy ceiling")
     copy_gbs = copy_ceiling()
+    log("TGV %d^3 plain FP64, %d warm-up + %d timed steps" % (n, args.warmup, args.steps))
     npts = n ** 3
     wall, gpu_ms, prof, plain_extra = timed_run(prob, 0, args.steps, args.warmup, args.cfl, keep_rho=not args.no_forms)
     value = npts * 3 * args.steps / wall / 1e6
@@ -509,6 +516,7 @@ def main():
         "kernels": breakdown,
     }
     if not args.no_forms:
+        log("precision form on TGV")
         wm, _, pm, _ = timed_run(prob, 1, args.steps, args.warmup, args.cfl)
         vm = npts * 3 * args.steps / wm / 1e6
         sm = sum(pm["sweep_%s" % a][1] for a in "xyz") / max(1, sum(pm["sweep_%s" % a][0] for a in "xyz"))
@@ -516,14 +524,20 @@ def main():
             "value": round(vm, 3), "speedup_vs_fp64": round(vm / value, 3),
             "sweep_avg_ms": round(sm, 4),
             "error_vs_fp64": form_error(prob, 1, 10, args.cfl)}}
+        log("learned routing on TGV")
         out["forms"]["tgv_learned"] = tgv_learned(prob, args, value, plain_extra)
+        log("shock-vortex 1024x512: plain and learned forms to t = 0.4")
         out["forms"]["learned_sensor"] = sensor_form(args.cfl)
+        log("wall flow 512x256x256: plain and precision form")
         out["forms"]["wall_precision"] = wall_precision(args.cfl)
     if not args.no_batch:
+        log("batched Riemann ensemble")
         out["batch"] = batch_form(args.batch_steps, args.warmup, args.cfl, not args.no_tune, args.batch_full)
     if not args.no_cpu_baseline:
+        log("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n or n)
     if args.cpu_table:
+        log("oracle table")
         out["cpu_table"] = cpu_table()
     print(json.dumps(out), flush=True)
 
