@@ -8,14 +8,20 @@
  * curvilinear grid, and advances U with the low-storage Runge-Kutta scheme
  * of section 2.7:
  *   - convective terms: characteristic (Roe-averaged) reconstruction with
- *     local Lax-Friedrichs splitting, WENO-Z5 (section 2.4) or TENO5
- *     (section 2.5), per direction (section 2.2, enumerated algorithm);
+ *     local Lax-Friedrichs splitting, per direction (section 2.2,
+ *     enumerated algorithm): WENO-Z5 (section 2.4), TENO5 or TENO6
+ *     (section 2.5), the original WENO-JS5 weights (section 2.3) or the
+ *     third-order WENO-Z of section 5.2;
  *   - viscous and heat-flux terms (eqs. heat_flux, stress_tensor, sutherland)
  *     with the fourth-order central scheme and one-sided closures of
  *     section 2.6, in divergence form;
  *   - metrics computed once (section 2.6, last paragraph), in FP64;
  *   - boundary conditions through three ghost nodes per side (section 3.1:
- *     periodic, extrapolation, isothermal and adiabatic no-slip walls).
+ *     periodic, extrapolation, isothermal and adiabatic no-slip walls; the
+ *     Dirichlet ends of section 5.2);
+ *   - time advance: the three-stage third-order low-storage scheme, its
+ *     strong-stability-preserving version or the five-stage fourth-order
+ *     one (section 2.7).
  *
  * Conventions (all calls):
  *   - Arrays are device pointers unless stated otherwise, FP64, owned by the
@@ -57,10 +63,33 @@ enum osbli_bc {
     OSBLI_PERIODIC = 0,        /* must be set on both sides of a direction */
     OSBLI_EXTRAPOLATE = 1,     /* zero-gradient copy of the boundary node  */
     OSBLI_ISOTHERMAL_WALL = 2, /* T = wall_T[d][side] at the boundary node */
-    OSBLI_ADIABATIC_WALL = 3   /* dT/dn = 0 (fourth-order one-sided)       */
+    OSBLI_ADIABATIC_WALL = 3,  /* dT/dn = 0 (fourth-order one-sided)       */
+    OSBLI_DIRICHLET = 4        /* ghost values are boundary data: set by the
+                                  caller with the state, never overwritten */
 };
 
-enum osbli_scheme { OSBLI_WENOZ5 = 0, OSBLI_TENO5 = 1 };
+/* Reconstructions of section 2.3-2.5 (all in the characteristic LLF frame):
+ *   WENOZ5  WENO-Z, eq. wenoz_weights, tau_5 = |beta_0 - beta_2|;
+ *   TENO5   TENO with K = 5 (three stencils, tau_5);
+ *   TENO6   TENO with K = 6: the three-point stencils plus {i..i+3},
+ *           tau_6 = |beta_3 - (beta_0 + beta_2 + 4 beta_1)/6|, optimal
+ *           weights (3/10, 9/20, 1/20, 1/5) whose all-kept limit is the
+ *           sixth-order reconstruction on i-2..i+3 (teno_CT < 1/4);
+ *   WENOJS5 the original weights, eqs. omega and alpha, p = 2 (the paper's
+ *           eps for it is 1e-6; eps is the caller's);
+ *   WENOZ3  third-order WENO-Z (stencils {i, i+1}, {i-1, i}, weights
+ *           (2/3, 1/3), tau_3 = |beta_0 - beta_1|).
+ * The precision form takes WENOZ5 and TENO5; sensor routing TENO5. */
+enum osbli_scheme { OSBLI_WENOZ5 = 0, OSBLI_TENO5 = 1, OSBLI_TENO6 = 2, OSBLI_WENOJS5 = 3, OSBLI_WENOZ3 = 4 };
+
+/* Low-storage (2N) Runge-Kutta schemes of section 2.7,
+ * dU <- A_s dU + dt R(U), U <- U + B_s dU, A_0 = 0:
+ *   RK3      A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15), 3 stages;
+ *   RK3_SSP  the strong-stability-preserving third-order 2N scheme of
+ *            Gottlieb and Shu: B_0 = c_2 = 0.924574, the other four from the
+ *            third-order conditions and the 2N structure, 3 stages;
+ *   RK4      Carpenter and Kennedy's five-stage fourth-order 2N scheme. */
+enum osbli_rk { OSBLI_RK3 = 0, OSBLI_RK3_SSP = 1, OSBLI_RK4 = 2 };
 
 /* Arithmetic of the characteristic reconstruction and flux evaluation.
  * OSBLI_FORM_MIXED: per interface, the FP64 flux of node i is the
@@ -93,7 +122,7 @@ typedef struct osbli_params {
     int32_t roe_avg;           /* 1: Roe average, 0: arithmetic mean of u, H */
     int32_t form;              /* enum osbli_form */
     int32_t sensor;            /* 1: learned-sensor routing (TENO5, separable mesh) */
-    int32_t reserved;
+    int32_t rk;                /* enum osbli_rk */
     int32_t bc_kind[3][2];     /* enum osbli_bc per (direction, side) */
     double wall_T[3][2];       /* isothermal wall temperature per face */
     double period[3];          /* coordinate shift of a periodic direction */
@@ -130,14 +159,19 @@ int osbli_apply_bc(osbli_ctx *ctx, double *U, void *stream);
  * R: device, interior layout, may not alias U. */
 int osbli_residual(osbli_ctx *ctx, const double *U, double *R, void *stream);
 
-/* One Runge-Kutta substage (section 2.7, three stages, 2N form):
- *   dU <- A_s dU + dt R(U),  U <- U + B_s dU,
- * with (A, B) = ((0, -5/9, -153/128), (1/3, 15/16, 8/15)); stage 0 ignores
- * the incoming dU, and stage 2 does not store it (the register is not read
- * again before the next stage 0), so dU holds the stage-1 value after a
- * whole step.  Does not apply boundary conditions.  U (ghosted layout) and
- * dU (interior layout) must not alias. */
+/* One Runge-Kutta substage (section 2.7, 2N form) of the context's scheme
+ * (params.rk; stage 0 .. osbli_rk_stages() - 1):
+ *   dU <- A_s dU + dt R(U),  U <- U + B_s dU;
+ * stage 0 ignores the incoming dU, and the last stage does not store it (the
+ * register is not read again before the next stage 0), so dU holds the
+ * second-to-last stage's value after a whole step.  Does not apply boundary
+ * conditions.  U (ghosted layout) and dU (interior layout) must not alias. */
 int osbli_rk_substep(osbli_ctx *ctx, int stage, double dt, double *U, double *dU, void *stream);
+
+/* Number of substages per step of the context's Runge-Kutta scheme (3 or
+ * 5), and its coefficients A[s], B[s] (host arrays of at least 5). */
+int osbli_rk_stages(const osbli_ctx *ctx);
+int osbli_rk_coeffs(const osbli_ctx *ctx, double *A, double *B);
 
 /* Allocation-free variant of osbli_rk_substep, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
@@ -300,8 +334,15 @@ int osbli_batch_set_tiles(osbli_batch *batch, const int64_t *seg, void *stream);
  * stream).  Graph instantiation is the runtime's only allocation. */
 int osbli_batch_capture(osbli_batch *batch, void *stream);
 
-/* One RK3 step of every active problem: the captured graphs if any, else
- * the same kernels launched directly.  Asynchronous. */
+/* One RK3 substage (stage 0..2) of every active problem: the stage's
+ * captured graph if any, else the same kernels launched directly.  Stage 0
+ * also reduces each problem's dt (and refreshes the routing masks); stage 2
+ * advances each problem's time and retires problems that reached t_end.
+ * Stages must be issued in order 0, 1, 2.  Asynchronous. */
+int osbli_batch_substep(osbli_batch *batch, int stage, void *stream);
+
+/* One RK3 step of every active problem: osbli_batch_substep for stages 0, 1
+ * and 2.  Asynchronous. */
 int osbli_batch_step(osbli_batch *batch, void *stream);
 
 /* Per-problem time and active flag (host arrays of nprob, may be NULL) and

@@ -132,9 +132,13 @@ class Batch:
         B.check_batch(self.lib.osbli_batch_capture(self.b, self._s()), self.b)
         self.captured = True
 
+    def substep(self, stage):
+        B.check_batch(self.lib.osbli_batch_substep(self.b, int(stage), self._s()), self.b)
+
     def step(self, n=1):
         for _ in range(int(n)):
-            B.check_batch(self.lib.osbli_batch_step(self.b, self._s()), self.b)
+            for st in range(3):
+                self.substep(st)
         self.steps_done += int(n)
 
     def status(self):

@@ -15,8 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libosbli.so")
 
 OSBLI_OK, OSBLI_EINVAL, OSBLI_EDEVICE, OSBLI_ENONPHYS, OSBLI_ENOSPACE = 0, -1, -2, -3, -4
-PERIODIC, EXTRAPOLATE, ISOTHERMAL_WALL, ADIABATIC_WALL = 0, 1, 2, 3
-WENOZ5, TENO5 = 0, 1
+PERIODIC, EXTRAPOLATE, ISOTHERMAL_WALL, ADIABATIC_WALL, DIRICHLET = 0, 1, 2, 3, 4
+WENOZ5, TENO5, TENO6, WENOJS5, WENOZ3 = 0, 1, 2, 3, 4
+RK3, RK3_SSP, RK4 = 0, 1, 2
 FORM_FP64, FORM_MIXED = 0, 1
 MESH_SEPARABLE, MESH_GENERAL = 0, 1
 
@@ -34,7 +35,7 @@ class Params(C.Structure):
         ("gamma", C.c_double), ("Re", C.c_double), ("Pr", C.c_double), ("Minf", C.c_double),
         ("sutherland", C.c_int32), ("scheme", C.c_int32),
         ("Ts_over_Tref", C.c_double), ("teno_CT", C.c_double), ("eps", C.c_double),
-        ("roe_avg", C.c_int32), ("form", C.c_int32), ("sensor", C.c_int32), ("reserved", C.c_int32),
+        ("roe_avg", C.c_int32), ("form", C.c_int32), ("sensor", C.c_int32), ("rk", C.c_int32),
         ("bc_kind", (C.c_int32 * 2) * 3),
         ("wall_T", (C.c_double * 2) * 3),
         ("period", C.c_double * 3),
@@ -55,6 +56,8 @@ _SIGS = {
     "osbli_rk_substep": (C.c_int, [_VP, C.c_int, C.c_double, _VP, _VP, _VP]),
     "osbli_rk_substep_noalloc": (C.c_int, [_VP, C.c_int, C.c_double, _VP, _VP, _VP]),
     "osbli_noalloc_scratch_bytes": (C.c_size_t, []),
+    "osbli_rk_stages": (C.c_int, [_VP]),
+    "osbli_rk_coeffs": (C.c_int, [_VP, _DP, _DP]),
     "osbli_compute_dt": (C.c_int, [_VP, _VP, C.c_double, _DP, _VP]),
     "osbli_check": (C.c_int, [_VP]),
     "osbli_last_error": (C.c_char_p, [_VP]),
@@ -78,6 +81,7 @@ _SIGS = {
     "osbli_batch_set_tiles": (C.c_int, [_VP, C.POINTER(C.c_int64), _VP]),
     "osbli_batch_capture": (C.c_int, [_VP, _VP]),
     "osbli_batch_step": (C.c_int, [_VP, _VP]),
+    "osbli_batch_substep": (C.c_int, [_VP, C.c_int, _VP]),
     "osbli_batch_status": (C.c_int, [_VP, _DP, C.POINTER(C.c_int), C.POINTER(C.c_int), _VP]),
     "osbli_batch_interior_points": (C.c_int, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "osbli_batch_last_error": (C.c_char_p, [_VP]),
@@ -130,6 +134,7 @@ def make_params(prob, form=FORM_FP64, sensor=0) -> Params:
     p.teno_CT = float(prob.teno_CT)
     p.eps = float(prob.eps)
     p.roe_avg = int(prob.roe_avg)
+    p.rk = int(getattr(prob, "rk", RK3))
     p.form = int(form)
     p.sensor = int(sensor)
     return p

@@ -78,6 +78,8 @@ struct osbli_ctx {
     int device;
     char *scratch;         // this device's scratch array (allocation-free substep), or null
     hipError_t scratch_err;
+    int nstages;           // Runge-Kutta substages per step (3 or 5)
+    double rkA[5], rkB[5]; // their 2N coefficients
     char err[320];
 };
 
@@ -119,7 +121,7 @@ int make_grid(const osbli_params *p, Grid &g, char *buf, size_t nb) {
             continue;
         }
         const int k0 = p->bc_kind[d][0], k1 = p->bc_kind[d][1];
-        if (k0 < 0 || k0 > 3 || k1 < 0 || k1 > 3) { snprintf(buf, nb, "bad bc kind in direction %d", d); return -1; }
+        if (k0 < 0 || k0 > 4 || k1 < 0 || k1 > 4) { snprintf(buf, nb, "bad bc kind in direction %d", d); return -1; }
         if ((k0 == OSBLI_PERIODIC) != (k1 == OSBLI_PERIODIC)) {
             snprintf(buf, nb, "periodic must be set on both sides of direction %d", d);
             return -1;
@@ -140,8 +142,13 @@ int make_grid(const osbli_params *p, Grid &g, char *buf, size_t nb) {
     g.is[2] = g.n[0] * g.n[1];
     g.nint = g.n[0] * g.n[1] * g.n[2];
     if (!(p->gamma > 1.0)) { snprintf(buf, nb, "gamma must exceed 1"); return -1; }
-    if (p->scheme != OSBLI_WENOZ5 && p->scheme != OSBLI_TENO5) { snprintf(buf, nb, "bad scheme"); return -1; }
+    if (p->scheme < OSBLI_WENOZ5 || p->scheme > OSBLI_WENOZ3) { snprintf(buf, nb, "bad scheme"); return -1; }
+    if (p->rk < OSBLI_RK3 || p->rk > OSBLI_RK4) { snprintf(buf, nb, "bad Runge-Kutta scheme %d", p->rk); return -1; }
     if (p->form != OSBLI_FORM_FP64 && p->form != OSBLI_FORM_MIXED) { snprintf(buf, nb, "bad form %d", p->form); return -1; }
+    if (p->form == OSBLI_FORM_MIXED && p->scheme != OSBLI_WENOZ5 && p->scheme != OSBLI_TENO5) {
+        snprintf(buf, nb, "the precision form takes WENO-Z5 or TENO5");
+        return -1;
+    }
     if (p->sensor != 0 && p->sensor != 1) { snprintf(buf, nb, "bad sensor flag"); return -1; }
     if (p->sensor && (p->scheme != OSBLI_TENO5 || (p->mesh == OSBLI_MESH_GENERAL && p->ndim > 1))) {
         snprintf(buf, nb, "sensor routing needs TENO5 on a separable mesh");
@@ -156,6 +163,10 @@ int make_grid(const osbli_params *p, Grid &g, char *buf, size_t nb) {
     if (p->Re > 0.0 && !(p->Pr > 0.0)) { snprintf(buf, nb, "Pr must be positive"); return -1; }
     if (p->scheme == OSBLI_TENO5 && !(p->teno_CT > 0.0 && p->teno_CT < 1.0 / 3.0)) {
         snprintf(buf, nb, "teno_CT must lie in (0, 1/3)");
+        return -1;
+    }
+    if (p->scheme == OSBLI_TENO6 && !(p->teno_CT > 0.0 && p->teno_CT < 0.25)) {
+        snprintf(buf, nb, "teno_CT must lie in (0, 1/4) for TENO6");
         return -1;
     }
     if (!(p->eps >= 1e-40 && p->eps <= 1.0)) { snprintf(buf, nb, "eps must lie in [1e-40, 1]"); return -1; }
@@ -225,6 +236,71 @@ Phys make_phys(const osbli_params *p) {
     return ph;
 }
 
+// 2N coefficients of the context's Runge-Kutta scheme (section 2.7; the
+// coefficients are cited there, not printed).
+//   RK3:     A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15);
+//   RK4:     Carpenter and Kennedy's five-stage fourth-order scheme (their
+//            published rationals);
+//   RK3_SSP: Gottlieb and Shu's strong-stability-preserving member of the
+//            third-order 2N family, fixed by its first node c2 = B_0 =
+//            0.924574 (ssp_family below gives the rest).
+// ssp_family(c3): with nodes c2 and c3 the third-order conditions fix the
+// weights w3 = (2 - 3 c2) / (6 c3 (c3 - c2)), w2 = (2 - 3 c3) / (6 c2 (c2 -
+// c3)), w1 = 1 - w2 - w3 and a32 = 1 / (6 w3 c2); the 2N recursion then
+// needs B_1 = a32, A_1 = (c3 - c2 - a32) / a32, B_2 = w3, A_2 = (w2 - B_1) /
+// B_2, and reproduces the first weight only if
+//   w1 = c2 + B_1 A_1 + B_2 A_2 A_1,
+// which is the residual returned (its root is the scheme's c3).
+double ssp_family(double c3, double *A, double *B) {
+    const double c2 = 0.924574;
+    const double w3 = (2.0 - 3.0 * c2) / (6.0 * c3 * (c3 - c2));
+    const double w2 = (2.0 - 3.0 * c3) / (6.0 * c2 * (c2 - c3));
+    const double w1 = 1.0 - w2 - w3;
+    const double a32 = 1.0 / (6.0 * w3 * c2);
+    A[0] = 0.0;
+    B[0] = c2;
+    B[1] = a32;
+    A[1] = (c3 - c2 - a32) / a32;
+    B[2] = w3;
+    A[2] = (w2 - B[1]) / B[2];
+    return w1 - (c2 + B[1] * A[1] + B[2] * A[2] * A[1]);
+}
+
+int rk_setup(int rk, double *A, double *B) {
+    if (rk == OSBLI_RK4) {
+        const double a[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                             -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+        const double b[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                             1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                             2277821191437.0 / 14882151754819.0};
+        for (int k = 0; k < 5; ++k) {
+            A[k] = a[k];
+            B[k] = b[k];
+        }
+        return 5;
+    }
+    if (rk == OSBLI_RK3_SSP) {
+        // secant iteration for the root c3 (about 0.3735) from 0.35 and 0.40
+        double x0 = 0.35, x1 = 0.40;
+        double f0 = ssp_family(x0, A, B), f1 = ssp_family(x1, A, B);
+        for (int it = 0; it < 60 && f1 != 0.0 && x1 != x0; ++it) {
+            const double x2 = x1 - f1 * (x1 - x0) / (f1 - f0);
+            x0 = x1;
+            f0 = f1;
+            x1 = x2;
+            f1 = ssp_family(x1, A, B);
+        }
+        ssp_family(x1, A, B);
+        return 3;
+    }
+    const double a[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0}, b[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    for (int k = 0; k < 3; ++k) {
+        A[k] = a[k];
+        B[k] = b[k];
+    }
+    return 3;
+}
+
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 hipEvent_t take_event(osbli_ctx *c) {
@@ -268,6 +344,10 @@ int resolve_profile(osbli_ctx *c) {
     }
     c->prof.pending.clear();
     return OSBLI_OK;
+}
+
+RkStage stage_of(const osbli_ctx *c, int s) {
+    return RkStage{c->rkA[s], c->rkB[s], s == 0, s == c->nstages - 1};
 }
 
 // convective sweeps of every direction into R (first stores, later accumulate)
@@ -316,6 +396,7 @@ int osbli_init_grid(osbli_ctx **out, const osbli_params *p, const double *x, con
     c->p = *p;
     for (int d = p->ndim; d < 3; ++d) c->p.n[d] = 1;
     c->ph = make_phys(p);
+    c->nstages = rk_setup(p->rk, c->rkA, c->rkB);
     c->L = make_layout(p, c->g);
     if (!workspace) return set_err(c, OSBLI_EINVAL, "null workspace");
     if (ws_bytes < c->L.total)
@@ -404,14 +485,25 @@ int osbli_residual(osbli_ctx *c, const double *U, double *R, void *stream) {
     HIP_TRY(c, convective_all(c, U, R, s));
     if (c->ph.viscous) {
         Timed t(c, OSBLI_K_FINISH, s);
-        HIP_TRY(c, launch_finish(c->g, c->ph, c->m, R, c->G, R, 0, 0.0, nullptr, nullptr, 0, s));
+        HIP_TRY(c, launch_finish(c->g, c->ph, c->m, R, c->G, R, RkStage{0.0, 0.0, 1, 1}, 0.0, nullptr, nullptr, 0, s));
+    }
+    return OSBLI_OK;
+}
+
+int osbli_rk_stages(const osbli_ctx *c) { return c ? c->nstages : 0; }
+
+int osbli_rk_coeffs(const osbli_ctx *c, double *A, double *B) {
+    if (!c || !A || !B) return OSBLI_EINVAL;
+    for (int k = 0; k < c->nstages; ++k) {
+        A[k] = c->rkA[k];
+        B[k] = c->rkB[k];
     }
     return OSBLI_OK;
 }
 
 int osbli_rk_substep(osbli_ctx *c, int stage, double dt, double *U, double *dU, void *stream) {
     if (!c || !U || !dU) return set_err(c, OSBLI_EINVAL, "null argument");
-    if (stage < 0 || stage > 2) return set_err(c, OSBLI_EINVAL, "stage must be 0..2");
+    if (stage < 0 || stage >= c->nstages) return set_err(c, OSBLI_EINVAL, "stage must be 0..%d", c->nstages - 1);
     if ((void *)U == (void *)dU) return set_err(c, OSBLI_EINVAL, "dU aliases U");
     hipStream_t s = as_stream(stream);
     c->last = s;
@@ -423,7 +515,7 @@ int osbli_rk_substep(osbli_ctx *c, int stage, double dt, double *U, double *dU, 
     HIP_TRY(c, convective_all(c, U, c->Racc, s));
     {
         Timed t(c, OSBLI_K_FINISH, s);
-        HIP_TRY(c, launch_finish(c->g, c->ph, c->m, c->Racc, c->G, nullptr, stage, dt, U, dU, 1, s));
+        HIP_TRY(c, launch_finish(c->g, c->ph, c->m, c->Racc, c->G, nullptr, stage_of(c, stage), dt, U, dU, 1, s));
     }
     return OSBLI_OK;
 }
@@ -432,7 +524,7 @@ size_t osbli_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 int osbli_rk_substep_noalloc(osbli_ctx *c, int stage, double dt, double *U, double *dU, void *stream) {
     if (!c || !U || !dU) return set_err(c, OSBLI_EINVAL, "null argument");
-    if (stage < 0 || stage > 2) return set_err(c, OSBLI_EINVAL, "stage must be 0..2");
+    if (stage < 0 || stage >= c->nstages) return set_err(c, OSBLI_EINVAL, "stage must be 0..%d", c->nstages - 1);
     if ((void *)U == (void *)dU) return set_err(c, OSBLI_EINVAL, "dU aliases U");
     const size_t racc = align256(sizeof(double) * c->g.nc * c->g.nint);
     const size_t gsz = c->ph.viscous ? align256(sizeof(double) * c->g.nd * (c->g.nd + 1) * c->g.nint) : 0;
@@ -457,7 +549,7 @@ int osbli_rk_substep_noalloc(osbli_ctx *c, int stage, double dt, double *U, doub
     for (int d = 0; d < c->g.nd; ++d)
         HIP_TRY(c, launch_convective(c->g, c->ph, c->m, U, Racc, c->flags, d, d == 0, route ? c->mask[d] : nullptr,
                                      c->seg[d], s));
-    HIP_TRY(c, launch_finish(c->g, c->ph, c->m, Racc, G, nullptr, stage, dt, U, dU, 1, s));
+    HIP_TRY(c, launch_finish(c->g, c->ph, c->m, Racc, G, nullptr, stage_of(c, stage), dt, U, dU, 1, s));
     return OSBLI_OK;
 }
 
@@ -785,6 +877,10 @@ int osbli_batch_create(osbli_batch **out, osbli_ctx *const *ctxs, int P, double 
             for (int s2 = 0; s2 < 2; ++s2)
                 if (c->p.bc_kind[d][s2] != OSBLI_PERIODIC && c->p.bc_kind[d][s2] != OSBLI_EXTRAPOLATE)
                     return bset_err(b, OSBLI_EINVAL, "problem %d: batching takes periodic / extrapolation BCs", p);
+        if (c->p.scheme != OSBLI_WENOZ5 && c->p.scheme != OSBLI_TENO5)
+            return bset_err(b, OSBLI_EINVAL, "problem %d: batching takes WENO-Z5 or TENO5", p);
+        if (c->p.rk != OSBLI_RK3)
+            return bset_err(b, OSBLI_EINVAL, "problem %d: batching takes the three-stage RK3", p);
         if (c->p.gamma != c0->p.gamma || c->p.scheme != c0->p.scheme || c->p.form != c0->p.form ||
             c->p.sensor != c0->p.sensor || c->p.roe_avg != c0->p.roe_avg || c->p.teno_CT != c0->p.teno_CT ||
             c->p.eps != c0->p.eps)
@@ -876,16 +972,24 @@ int osbli_batch_capture(osbli_batch *b, void *stream) {
     return OSBLI_OK;
 }
 
+int osbli_batch_substep(osbli_batch *b, int stage, void *stream) {
+    if (!b) return OSBLI_EINVAL;
+    if (stage < 0 || stage > 2) return bset_err(b, OSBLI_EINVAL, "stage must be 0..2");
+    hipStream_t s = as_stream(stream);
+    if (b->captured) {
+        HIP_BTRY(b, hipGraphLaunch(b->exec[stage], s));
+    } else {
+        HIP_BTRY(b, launch_batch_stage(b->dp, b->ds, b->T, b->P, b->ph, stage, b->cfl, b->route, b->w, b->zcut,
+                                       b->flags, s));
+    }
+    return OSBLI_OK;
+}
+
 int osbli_batch_step(osbli_batch *b, void *stream) {
     if (!b) return OSBLI_EINVAL;
-    hipStream_t s = as_stream(stream);
     for (int st = 0; st < 3; ++st) {
-        if (b->captured) {
-            HIP_BTRY(b, hipGraphLaunch(b->exec[st], s));
-        } else {
-            HIP_BTRY(b, launch_batch_stage(b->dp, b->ds, b->T, b->P, b->ph, st, b->cfl, b->route, b->w, b->zcut,
-                                           b->flags, s));
-        }
+        const int rc = osbli_batch_substep(b, st, stream);
+        if (rc != OSBLI_OK) return rc;
     }
     return OSBLI_OK;
 }

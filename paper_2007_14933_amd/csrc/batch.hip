@@ -174,7 +174,7 @@ k_b_sweep_xl(const BProb *__restrict__ pr, const BState *__restrict__ st, const 
 // RK stage update (inviscid)
 __global__ void __launch_bounds__(256)
 k_b_finish(const BProb *__restrict__ pr, const BState *__restrict__ st, const int64_t *__restrict__ off, int P,
-           int64_t total, int stage) {
+           int64_t total, RkStage rs) {
     for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int p = find_prob(off, P, tile);
         if (!st[p].active) continue;
@@ -185,7 +185,7 @@ k_b_finish(const BProb *__restrict__ pr, const BState *__restrict__ st, const in
         const double dt = st[p].dt;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-            rk_point(stage, dt, b.R[c * b.g.nint + ci], b.dU + c * b.g.nint + ci, b.U + c * b.g.enpts + e0);
+            rk_point(rs, dt, b.R[c * b.g.nint + ci], b.dU + c * b.g.nint + ci, b.U + c * b.g.enpts + e0);
     }
 }
 
@@ -270,7 +270,8 @@ hipError_t launch_batch_stage(const BProb *pr, BState *st, const BatchTables &T,
                 : b_sweeps<OSBLI_TENO5, false, false>(pr, st, T, P, ph, flags, s);
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_b_finish, dim3(grid_of(T.tot_pt, 1, 2048)), dim3(256), 0, s, pr, st, T.pt, P, T.tot_pt, stage);
+    hipLaunchKernelGGL(k_b_finish, dim3(grid_of(T.tot_pt, 1, 2048)), dim3(256), 0, s, pr, st, T.pt, P, T.tot_pt,
+                       rk3_stage(stage));
     for (int d = 0; d < 2; ++d)
         hipLaunchKernelGGL(k_b_bc, dim3(grid_of(T.tot_f[d], 256, 1024)), dim3(256), 0, s, pr, st, T.f[d], P,
                            T.tot_f[d], ph, d);

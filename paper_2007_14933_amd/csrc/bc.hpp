@@ -61,6 +61,8 @@ __device__ __forceinline__ void ghost_fill(double *__restrict__ U, const Grid &g
 #pragma unroll
             for (int c = 0; c < NC; ++c) U[eg + c * cs] = v[m - 1][c];
         }
+    } else if (kind == OSBLI_DIRICHLET) {
+        // boundary data: the ghosts keep the values the caller set
     } else if (kind == OSBLI_EXTRAPOLATE) {
         double v[NC];
 #pragma unroll

@@ -101,8 +101,90 @@ __device__ __forceinline__ double recon5_fin(const R5 &r, double tinv, double CT
     }
 }
 
+// ---- further reconstructions, one side at a time ----
+// TENO6 (section 2.5, K = 6) at x_{i+1/2} from f_{i-2..i+3}: the three
+// three-point candidates and the cubic on {i..i+3}, value
+// f_i/4 + 13 f_{i+1}/12 - 5 f_{i+2}/12 + f_{i+3}/12 and Jiang-Shu indicator
+// (1/36)(-11 f_i + 18 f_{i+1} - 9 f_{i+2} + 2 f_{i+3})^2
+//   + (13/12)(2 f_i - 5 f_{i+1} + 4 f_{i+2} - f_{i+3})^2
+//   + (781/720)(-f_i + 3 f_{i+1} - 3 f_{i+2} + f_{i+3})^2;
+// tau_6 = |beta_3 - (beta_0 + beta_2 + 4 beta_1)/6|, gamma_r = (1 +
+// tau_6/(beta_r + eps))^6, stencil r cut when gamma_r < C_T sum(gamma),
+// optimal weights (3/10, 9/20, 1/20, 1/5) (the sixth-order reconstruction
+// when every stencil is kept).  The four ratios tau/(beta_r + eps) share
+// one division: x_r = tau prod_{s != r}(beta_s + eps) / prod_s(beta_s + eps).
+__device__ __forceinline__ double recon6_teno(double fm2, double fm1, double f0, double fp1, double fp2, double fp3,
+                                              double CT, double eps, bool *kept) {
+    const double q0 = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
+    const double q1 = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
+    const double q2 = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
+    const double q3 = 0.25 * f0 + (13.0 / 12.0) * fp1 - (5.0 / 12.0) * fp2 + (1.0 / 12.0) * fp3;
+    double s, t;
+    s = f0 - 2.0 * fp1 + fp2;
+    t = 3.0 * f0 - 4.0 * fp1 + fp2;
+    const double b0 = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    s = fm1 - 2.0 * f0 + fp1;
+    t = fm1 - fp1;
+    const double b1 = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    s = fm2 - 2.0 * fm1 + f0;
+    t = fm2 - 4.0 * fm1 + 3.0 * f0;
+    const double b2 = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    const double a = -11.0 * f0 + 18.0 * fp1 - 9.0 * fp2 + 2.0 * fp3;
+    const double b = 2.0 * f0 - 5.0 * fp1 + 4.0 * fp2 - fp3;
+    const double c = -f0 + 3.0 * fp1 - 3.0 * fp2 + fp3;
+    const double b3 = (1.0 / 36.0) * a * a + (13.0 / 12.0) * b * b + (781.0 / 720.0) * c * c;
+    const double tau = fabs(b3 - (b0 + b2 + 4.0 * b1) * (1.0 / 6.0));
+    const double e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps, e3 = b3 + eps;
+    const double e01 = e0 * e1, e23 = e2 * e3;
+    const double tq = tau / (e01 * e23);
+    double c0 = 1.0 + tq * (e1 * e23), c1 = 1.0 + tq * (e0 * e23);
+    double c2 = 1.0 + tq * (e01 * e3), c3 = 1.0 + tq * (e01 * e2);
+    c0 = c0 * c0 * c0;
+    c1 = c1 * c1 * c1;
+    c2 = c2 * c2 * c2;
+    c3 = c3 * c3 * c3;
+    const double g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2, g3 = c3 * c3;
+    const double lim = CT * (g0 + g1 + g2 + g3);
+    const bool k0 = !(g0 < lim), k1 = !(g1 < lim), k2 = !(g2 < lim), k3 = !(g3 < lim);
+    const double w0 = k0 ? 0.3 : 0.0, w1 = k1 ? 0.45 : 0.0, w2 = k2 ? 0.05 : 0.0, w3 = k3 ? 0.2 : 0.0;
+    const double num = w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3;
+    if (kept) *kept = *kept && k0 && k1 && k2 && k3;
+    if (k0 && k1 && k2 && k3) return num;
+    return num / (w0 + w1 + w2 + w3);
+}
+
+// WENO-JS5 (section 2.3, eqs. omega and alpha, p = 2): alpha_r = d_r /
+// (beta_r + eps)^2; the normalisation cancels the common factor
+// prod_s (beta_s + eps)^2, so omega_r = d_r P_r / sum_k d_k P_k with
+// P_r = prod_{s != r} (beta_s + eps)^2 and one division per reconstruction.
+__device__ __forceinline__ double recon5_js(double fm2, double fm1, double f0, double fp1, double fp2, double eps) {
+    const R5 r = recon5_ind(fm2, fm1, f0, fp1, fp2, eps);
+    const double s0 = r.e0 * r.e0, s1 = r.e1 * r.e1, s2 = r.e2 * r.e2;
+    const double a0 = 0.3 * (s1 * s2), a1 = 0.6 * (s0 * s2), a2 = 0.1 * (s0 * s1);
+    return (a0 * r.q0 + a1 * r.q1 + a2 * r.q2) / (a0 + a1 + a2);
+}
+
+// WENO-3Z (third-order WENO-Z, the lowest order of section 5.2) at
+// x_{i+1/2} from f_{i-1..i+1}: candidates (f_i + f_{i+1})/2 and
+// (3 f_i - f_{i-1})/2, indicators (f_{i+1} - f_i)^2 and (f_i - f_{i-1})^2,
+// optimal weights (2/3, 1/3), tau_3 = |beta_0 - beta_1|, alpha_r = d_r (1 +
+// (tau/(beta_r + eps))^2); one division for the two ratios.
+__device__ __forceinline__ double recon3_z(double fm1, double f0, double fp1, double eps) {
+    const double q0 = 0.5 * f0 + 0.5 * fp1, q1 = 1.5 * f0 - 0.5 * fm1;
+    const double d0 = fp1 - f0, d1 = f0 - fm1;
+    const double b0 = d0 * d0, b1 = d1 * d1;
+    const double tau = fabs(b0 - b1);
+    const double e0 = b0 + eps, e1 = b1 + eps;
+    const double tq = tau / (e0 * e1);
+    const double x0 = tq * e1, x1 = tq * e0;
+    const double a0 = (2.0 / 3.0) * (1.0 + x0 * x0), a1 = (1.0 / 3.0) * (1.0 + x1 * x1);
+    return (a0 * q0 + a1 * q1) / (a0 + a1);
+}
+
 // LLF split of one characteristic field over the six points and the two
-// reconstructions: ghat = recon+(g+_{i-2..i+2}) + recon-(g-_{i+3..i-1}).
+// reconstructions: ghat = recon+(g+_{i-2..i+2}) + recon-(g-_{i+3..i-1})
+// (TENO6: recon+(g+_{i-2..i+3}) + recon-(g-_{i+3..i-2}); WENO-3Z:
+// recon+(g+_{i-1..i+1}) + recon-(g-_{i+2..i})).
 // SHARED: one division serves both sides: with D+- = prod_r(beta_r+eps),
 // tau+/D+ = tau+ D- / (D+ D-) and likewise for the other side (D+ D- >=
 // eps^6, which the accepted range of eps keeps a normal number).  This
@@ -118,7 +200,15 @@ __device__ __forceinline__ double split_recon(const double (&V)[6], const double
         gp[k] = 0.5 * (g[k] + alpha * V[k]);
         gm[k] = 0.5 * (g[k] - alpha * V[k]);
     }
-    if (SHARED) {
+    if constexpr (SCHEME == OSBLI_TENO6) {
+        return recon6_teno(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], ph.CT, ph.eps, kept) +
+               recon6_teno(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0], ph.CT, ph.eps, kept);
+    } else if constexpr (SCHEME == OSBLI_WENOJS5) {
+        return recon5_js(gp[0], gp[1], gp[2], gp[3], gp[4], ph.eps) +
+               recon5_js(gm[5], gm[4], gm[3], gm[2], gm[1], ph.eps);
+    } else if constexpr (SCHEME == OSBLI_WENOZ3) {
+        return recon3_z(gp[1], gp[2], gp[3], ph.eps) + recon3_z(gm[4], gm[3], gm[2], ph.eps);
+    } else if (SHARED) {
         const R5 a = recon5_ind(gp[0], gp[1], gp[2], gp[3], gp[4], ph.eps);
         const R5 b = recon5_ind(gm[5], gm[4], gm[3], gm[2], gm[1], ph.eps);
         const double da = (a.e0 * a.e1) * a.e2, db = (b.e0 * b.e1) * b.e2;

@@ -60,9 +60,19 @@ __host__ __device__ inline int64_t int_index(const Grid &g, int64_t i, int64_t j
 // flags word bits
 constexpr unsigned kFlagNonPhys = 1u;
 
-// Low-storage RK3 (2N form) coefficients.
-__host__ __device__ inline double rk_A(int s) { return s == 0 ? 0.0 : (s == 1 ? -5.0 / 9.0 : -153.0 / 128.0); }
-__host__ __device__ inline double rk_B(int s) { return s == 0 ? 1.0 / 3.0 : (s == 1 ? 15.0 / 16.0 : 8.0 / 15.0); }
+// One stage of a low-storage (2N) Runge-Kutta scheme: dU <- A dU + dt R
+// (first: A = 0 and dU is not read), U <- U + B dU (last: dU is not stored,
+// the register is not read again before the next step's first stage).
+struct RkStage {
+    double A, B;
+    int first, last;
+};
+
+// The three-stage third-order scheme's stages (the batched ensemble's scheme).
+inline RkStage rk3_stage(int s) {
+    const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0}, B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    return RkStage{A[s], B[s], s == 0, s == 2};
+}
 
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_metrics_separable(const Grid &g, const double *coord1d, double *invh_out[3],
@@ -103,7 +113,7 @@ hipError_t launch_viscous_fluxes(const Grid &g, const Phys &ph, const Metrics &m
                                  double *G, hipStream_t s);
 // mode 0: R_out = Racc + viscous;  mode 1: RK update of U, dU with Racc + viscous
 hipError_t launch_finish(const Grid &g, const Phys &ph, const Metrics &m, const double *Racc,
-                         const double *G, double *Rout, int stage, double dt, double *U, double *dU,
+                         const double *G, double *Rout, RkStage rs, double dt, double *U, double *dU,
                          int mode, hipStream_t s);
 hipError_t launch_dt(const Grid &g, const Phys &ph, const Metrics &m, const double *U,
                      unsigned long long *slot, hipStream_t s);

@@ -60,13 +60,13 @@ __device__ __forceinline__ double dt_node(const double *__restrict__ U, const Gr
     return sn;
 }
 
-// Williamson low-storage stage: dU <- A_s dU + dt R (A_0 = 0, dU not read),
+// Low-storage (2N) stage: dU <- A_s dU + dt R (A_0 = 0, dU not read),
 // U <- U + B_s dU.  The last stage's dU is never read (the next stage 0
 // ignores it), so it is not stored.
-__device__ __forceinline__ void rk_point(int stage, double dt, double R, double *dU, double *U) {
-    const double du = (stage == 0 ? 0.0 : rk_A(stage) * *dU) + dt * R;
-    if (stage != 2) *dU = du;
-    *U += rk_B(stage) * du;
+__device__ __forceinline__ void rk_point(const RkStage &rs, double dt, double R, double *dU, double *U) {
+    const double du = (rs.first ? 0.0 : rs.A * *dU) + dt * R;
+    if (!rs.last) *dU = du;
+    *U += rs.B * du;
 }
 
 }  // namespace osbli

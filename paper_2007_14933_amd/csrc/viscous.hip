@@ -300,7 +300,7 @@ k_visc_flux_zm(const double *__restrict__ U, double *__restrict__ G, Grid g, Phy
 template <int ND, bool GEN, bool VISC, int MODE>
 __global__ void __launch_bounds__(256)
 k_finish(const double *Racc, const double *__restrict__ G, double *Rout, Grid g,
-         Phys ph, Metrics m, int stage, double dt, double *__restrict__ U, double *__restrict__ dU) {
+         Phys ph, Metrics m, RkStage rs, double dt, double *__restrict__ U, double *__restrict__ dU) {
     constexpr int NC = ND + 2;
     constexpr int NV = ND + 1;
     int64_t idx[3];
@@ -340,7 +340,7 @@ k_finish(const double *Racc, const double *__restrict__ G, double *Rout, Grid g,
         for (int c = 0; c < NC; ++c) Rout[c * g.nint + ci] = R[c];
     } else {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) rk_point(stage, dt, R[c], dU + c * g.nint + ci, U + c * g.enpts + e0);
+        for (int c = 0; c < NC; ++c) rk_point(rs, dt, R[c], dU + c * g.nint + ci, U + c * g.enpts + e0);
     }
 }
 
@@ -357,7 +357,7 @@ constexpr int kFZ = 16;
 constexpr int kFX = 64, kFY = 4;  // columns per block
 
 __global__ void __launch_bounds__(kFX * kFY)
-k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid g, Metrics m, int stage, double dt,
+k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid g, Metrics m, RkStage rs, double dt,
             double *__restrict__ U, double *__restrict__ dU) {
     constexpr int NC = 5, NV = 4;
     const int64_t x = (int64_t)blockIdx.x * kFX + threadIdx.x;
@@ -461,16 +461,16 @@ k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid 
 #pragma unroll
         for (int c = 0; c < NC; ++c) R[c] = Racc[c * g.nint + ci];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) d0[c] = stage == 0 ? 0.0 : dU[c * g.nint + ci];
+        for (int c = 0; c < NC; ++c) d0[c] = rs.first ? 0.0 : dU[c * g.nint + ci];
 #pragma unroll
         for (int c = 0; c < NC; ++c) u0[c] = U[c * g.enpts + e0];
 #pragma unroll
         for (int v = 0; v < NV; ++v) R[1 + v] += acc[v];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double du = (stage == 0 ? 0.0 : rk_A(stage) * d0[c]) + dt * R[c];
-            if (stage != 2) dU[c * g.nint + ci] = du;
-            U[c * g.enpts + e0] = u0[c] + rk_B(stage) * du;
+            const double du = (rs.first ? 0.0 : rs.A * d0[c]) + dt * R[c];
+            if (!rs.last) dU[c * g.nint + ci] = du;
+            U[c * g.enpts + e0] = u0[c] + rs.B * du;
         }
     }
 }
@@ -515,7 +515,7 @@ __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int n) {
 
 template <int ND, bool GEN>
 hipError_t finish_nd(const Grid &g, const Phys &ph, const Metrics &m, const double *Racc, const double *G,
-                     double *Rout, int stage, double dt, double *U, double *dU, int mode, hipStream_t s) {
+                     double *Rout, RkStage rs, double dt, double *U, double *dU, int mode, hipStream_t s) {
     // plane-major order on every XCD: the finish reads its z neighbours'
     // fluxes best when all XCDs advance through the planes together (the
     // per-XCD runs of node_tiles measured slower here)
@@ -523,23 +523,23 @@ hipError_t finish_nd(const Grid &g, const Phys &ph, const Metrics &m, const doub
     if (ND == 3 && !GEN && ph.viscous && mode == 1) {
         const dim3 zb((unsigned)((g.n[0] + kFX - 1) / kFX), (unsigned)((g.n[1] + kFY - 1) / kFY),
                       (unsigned)((g.n[2] + kFZ - 1) / kFZ));
-        hipLaunchKernelGGL(k_finish_zm, zb, dim3(kFX, kFY), 0, s, Racc, G, g, m, stage, dt, U, dU);
+        hipLaunchKernelGGL(k_finish_zm, zb, dim3(kFX, kFY), 0, s, Racc, G, g, m, rs, dt, U, dU);
         return hipGetLastError();
     }
     if (ph.viscous) {
         if (mode == 0)
             hipLaunchKernelGGL((k_finish<ND, GEN, true, 0>), nb, bs, 0, s, Racc, G, Rout, g, ph, m,
-                               stage, dt, U, dU);
+                               rs, dt, U, dU);
         else
             hipLaunchKernelGGL((k_finish<ND, GEN, true, 1>), nb, bs, 0, s, Racc, G, Rout, g, ph, m,
-                               stage, dt, U, dU);
+                               rs, dt, U, dU);
     } else {
         if (mode == 0)
             hipLaunchKernelGGL((k_finish<ND, GEN, false, 0>), nb, bs, 0, s, Racc, G, Rout, g, ph,
-                               m, stage, dt, U, dU);
+                               m, rs, dt, U, dU);
         else
             hipLaunchKernelGGL((k_finish<ND, GEN, false, 1>), nb, bs, 0, s, Racc, G, Rout, g, ph,
-                               m, stage, dt, U, dU);
+                               m, rs, dt, U, dU);
     }
     return hipGetLastError();
 }
@@ -572,16 +572,16 @@ hipError_t launch_viscous_fluxes(const Grid &g, const Phys &ph, const Metrics &m
 }
 
 hipError_t launch_finish(const Grid &g, const Phys &ph, const Metrics &m, const double *Racc, const double *G,
-                         double *Rout, int stage, double dt, double *U, double *dU, int mode, hipStream_t s) {
+                         double *Rout, RkStage rs, double dt, double *U, double *dU, int mode, hipStream_t s) {
     const bool gen = m.general != 0;
     switch (g.nd) {
-        case 1: return finish_nd<1, false>(g, ph, m, Racc, G, Rout, stage, dt, U, dU, mode, s);
+        case 1: return finish_nd<1, false>(g, ph, m, Racc, G, Rout, rs, dt, U, dU, mode, s);
         case 2:
-            return gen ? finish_nd<2, true>(g, ph, m, Racc, G, Rout, stage, dt, U, dU, mode, s)
-                       : finish_nd<2, false>(g, ph, m, Racc, G, Rout, stage, dt, U, dU, mode, s);
+            return gen ? finish_nd<2, true>(g, ph, m, Racc, G, Rout, rs, dt, U, dU, mode, s)
+                       : finish_nd<2, false>(g, ph, m, Racc, G, Rout, rs, dt, U, dU, mode, s);
         default:
-            return gen ? finish_nd<3, true>(g, ph, m, Racc, G, Rout, stage, dt, U, dU, mode, s)
-                       : finish_nd<3, false>(g, ph, m, Racc, G, Rout, stage, dt, U, dU, mode, s);
+            return gen ? finish_nd<3, true>(g, ph, m, Racc, G, Rout, rs, dt, U, dU, mode, s)
+                       : finish_nd<3, false>(g, ph, m, Racc, G, Rout, rs, dt, U, dU, mode, s);
     }
 }
 

@@ -3,7 +3,7 @@ the C ABI.  PyTorch supplies memory and streams only; every step of the
 residual and the update runs in libosbli's kernels.
 
     s = Solver(problem)            # allocates U, dU, workspace on cuda:0
-    s.run(nsteps, cfl=0.5)         # BCs at t=0, then dt + 3 substeps per step
+    s.run(nsteps, cfl=0.5)         # BCs at t=0, then dt + the RK substeps per step
 """
 from __future__ import annotations
 
@@ -49,6 +49,7 @@ class Solver:
         self.dU = torch.zeros(ishape, dtype=torch.float64, device=self.device)
         self.t = 0.0
         self.nsteps_done = 0
+        self.nstages = self.lib.osbli_rk_stages(self.ctx)
 
     def _s(self):
         return C.c_void_p(self.stream.cuda_stream)
@@ -146,9 +147,15 @@ class Solver:
         torch.cuda.synchronize(self.device)
         return out.cpu().numpy()
 
+    def rk_coeffs(self):
+        A = (C.c_double * 5)()
+        Bc = (C.c_double * 5)()
+        B.check(self.lib.osbli_rk_coeffs(self.ctx, A, Bc), self.ctx)
+        return list(A)[: self.nstages], list(Bc)[: self.nstages]
+
     # ---- time loop (section 2.7 ordering: residual, update, BCs) ----
     def step(self, dt):
-        for s in range(3):
+        for s in range(self.nstages):
             self.substep(s, dt)
             self.apply_bc()
         self.t += dt

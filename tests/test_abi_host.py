@@ -67,6 +67,11 @@ def test_workspace_sizes(lib):
     (lambda p: setattr(p, "form", 9), "form"),
     (lambda p: setattr(p, "eps", 1e-60), "eps below the range whose sixth power stays normal"),
     (lambda p: setattr(p, "eps", 0.0), "eps zero"),
+    (lambda p: (setattr(p, "scheme", B.TENO6), setattr(p, "teno_CT", 0.3)), "TENO6 needs C_T < 1/4"),
+    (lambda p: (setattr(p, "scheme", B.TENO6), setattr(p, "form", B.FORM_MIXED)), "precision form: fifth order only"),
+    (lambda p: (setattr(p, "scheme", B.WENOJS5), setattr(p, "sensor", 1)), "routing needs TENO5"),
+    (lambda p: setattr(p, "rk", 3), "Runge-Kutta scheme"),
+    (lambda p: (p.bc_kind[0].__setitem__(0, 5), p.bc_kind[0].__setitem__(1, 5)), "bc kind"),
 ])
 def test_invalid_parameters_rejected_without_device(lib, mutate, why):
     p = B.make_params(I.tgv(8))
@@ -117,6 +122,9 @@ def _gpu_test_problems():
         for p in TB.ensemble(TB.SIZES, 11, TB.T_ENDS):
             out.append((p.name, p, 1, sensor))
     out.append(("sod80_teno", I.sod(80).with_(scheme=I.TENO5), 0, 1))
+    import test_gpu_schemes as TS
+    for name, (prob, _) in TS.CASES.items():
+        out.append((name, prob, 0, 0))
     return out
 
 

@@ -1,0 +1,134 @@
+"""Parity of the HIP path with the FP64 oracle for the further schemes:
+sixth-order TENO with the strong-stability-preserving RK3 (the paper's
+production configuration, sections 2.5 and 2.7), the original WENO-JS5
+weights, third-order WENO-Z on the Shu-Osher case with Dirichlet ends
+(section 5.2), and the five-stage fourth-order RK.  Same bars as the plain
+parity tests: max normwise relative difference per conserved quantity
+<= 1e-11 after the run, single residuals <= 1e-13 of the flux scale, ghosts
+<= 1e-13; the RK coefficients, which both sides derive independently, agree
+to 1e-15.  Every case prints its name before touching the GPU."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2007_14933_amd import inputs as I
+from parity_util import flux_scale, gpu_run, normwise_rel, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+
+TOL_RUN = 1e-11
+TOL_ONE = 1e-13
+
+
+def wavy3d(n=(12, 10, 14), A=0.03):
+    grids = np.meshgrid(*(np.arange(n[d], dtype=float) / n[d] for d in (2, 1, 0)), indexing="ij")
+    K, Jj, Ii = grids
+    X = Ii + A * np.sin(2 * math.pi * Jj) * np.sin(2 * math.pi * K)
+    Y = Jj + A * np.sin(2 * math.pi * K) * np.sin(4 * math.pi * Ii)
+    Z = K + A * np.sin(2 * math.pi * Ii) * np.sin(2 * math.pi * Jj)
+    return X, Y, Z
+
+
+def cases():
+    c = {}
+    T6, SSP = dict(scheme=I.TENO6), dict(rk=I.RK3_SSP)
+    c["sod400_teno6_ssp"] = (I.sod(400).with_(**T6, **SSP), dict(nsteps=10 ** 6, t_end=0.2))
+    c["sod203_teno6_ct1e-7"] = (I.sod(203).with_(scheme=I.TENO6, teno_CT=1e-7), dict(nsteps=100))
+    c["sod203_wenojs5"] = (I.sod(203).with_(scheme=I.WENOJS5, eps=1e-6), dict(nsteps=100))
+    c["shuosher320_wenoz3"] = (I.shu_osher(320, scheme=I.WENOZ3), dict(nsteps=2000, dt_fixed=2e-4))
+    c["shuosher320_wenoz5_rk4"] = (I.shu_osher(320, scheme=I.WENOZ5).with_(rk=I.RK4),
+                                   dict(nsteps=1000, dt_fixed=2e-4))
+    c["riemann2d_70_teno6_ssp"] = (I.riemann2d(70, 5, scheme=I.TENO6).with_(**SSP), dict(nsteps=100))
+    c["shockvortex_96x48_teno6"] = (I.shock_vortex(nx=96, ny=48, seed=42).with_(**T6, **SSP), dict(nsteps=100))
+    # the production configuration on the viscous TGV: 32^3, and 64^3 where
+    # every y / z sweep wave loads ahead and the x sweep runs lanes-along-x
+    c["tgv32_teno6_ssp"] = (I.tgv(32, scheme=I.TENO6).with_(**SSP), dict(nsteps=100))
+    c["tgv64_teno6_ssp"] = (I.tgv(64, scheme=I.TENO6).with_(**SSP), dict(nsteps=40))
+    c["tgv32_wenojs5_rk4"] = (I.tgv(32, scheme=I.WENOJS5).with_(eps=1e-6, rk=I.RK4), dict(nsteps=40))
+    X3, Y3, Z3 = wavy3d()
+    base = I.smooth_random(3, (12, 10, 14), seed=7, amp=0.1, Re=200.0, M=0.6)
+    c["wavy3d_general_teno6_rk4"] = (base.with_(coords1d=None, coords_full=(X3, Y3, Z3), scheme=I.TENO6,
+                                                rk=I.RK4), dict(nsteps=30))
+    wf = I.wall_flow(24, 20, 16, L=(10.0, 8.0, 6.0))
+    c["wall_24x20x16_teno6_ssp"] = (wf.with_(**T6, **SSP), dict(nsteps=60))
+    X, Y = I.sinusoidal_mesh(40, 26)
+    dw = I.density_wave(40, mesh="uniform")
+    U0 = np.zeros(I.ext_shape(2, (40, 26, 1)))
+    Ui = I.interior_view(2, U0)
+    rho = 1.0 + 0.2 * np.sin(math.pi * (X + Y))
+    for k, a in enumerate(I.conserved(1.4, rho, [1.0 + 0 * X, -0.5 + 0 * X], 1.0 + 0 * X)):
+        Ui[k] = a
+    c["dwave_sinusoidal_40x26_wenoz3"] = (dw.with_(n=(40, 26, 1), coords1d=None, coords_full=(X, Y, None), U0=U0,
+                                                   scheme=I.WENOZ3), dict(nsteps=100))
+    return c
+
+
+CASES = cases()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_run_parity(name):
+    prob, kw = CASES[name]
+    say("[gpu schemes run]", name, prob.n, kw)
+    Ug, tg, _ = gpu_run(prob, **kw)
+    Uo, to = oracle_run(prob, **kw)
+    assert abs(tg - to) <= 1e-12 * max(1.0, abs(to)), (tg, to)
+    err = normwise_rel(O.interior(prob, Ug), O.interior(prob, Uo))
+    say("   t=%.6g  normwise rel diff per component:" % tg, err)
+    assert np.all(np.isfinite(err)) and err.max() <= TOL_RUN, err
+
+
+@pytest.mark.parametrize("name", [n for n in CASES if not n.startswith("shuosher")] + ["shuosher320_wenoz3"])
+def test_residual_and_ghosts(name):
+    prob, _ = CASES[name]
+    say("[gpu schemes residual]", name, prob.n)
+    from paper_2007_14933_amd.solver import Solver
+    s = Solver(prob)
+    s.apply_bc()
+    Ug = s.state()
+    Uo = O.apply_bc(prob, prob.U0.copy())
+    nd = prob.ndim
+    core = [slice(None)] + [slice(3, -3) if d < nd else slice(None) for d in (2, 1, 0)]
+    for d in range(nd):
+        sl = list(core)
+        sl[3 - d] = slice(None)
+        assert normwise_rel(Ug[tuple(sl)], Uo[tuple(sl)]).max() <= TOL_ONE
+    Rg = s.residual().cpu().numpy()
+    S, J = O.metrics(prob)
+    Ro = O.residual(prob, S, J, Uo)
+    err = np.abs(Rg - Ro).max(axis=(1, 2, 3)) / flux_scale(prob, Uo, J, S)
+    say("   residual |diff| / flux scale:", err)
+    assert err.max() <= TOL_ONE, err
+    s.check()
+
+
+@pytest.mark.parametrize("rk,stages", [(I.RK3, 3), (I.RK3_SSP, 3), (I.RK4, 5)])
+def test_rk_coefficients_match_the_oracle(rk, stages):
+    from paper_2007_14933_amd.solver import Solver
+    prob = I.sod(32).with_(rk=rk)
+    say("[gpu schemes] RK coefficients", rk)
+    s = Solver(prob)
+    A, B = s.rk_coeffs()
+    Ao, Bo = O.rk_coeffs(prob)
+    assert s.nstages == stages == len(Ao)
+    assert np.abs(np.array(A) - Ao).max() <= 1e-15 * np.abs(Ao).max()
+    assert np.abs(np.array(B) - Bo).max() <= 1e-15
+
+
+def test_dirichlet_ghosts_untouched_and_stage_range():
+    from paper_2007_14933_amd import binding as Bd
+    from paper_2007_14933_amd.solver import Solver
+    say("[gpu schemes] Dirichlet ghosts, stage range")
+    prob = I.shu_osher(64)
+    s = Solver(prob)
+    s.run(20, dt_fixed=2e-4)
+    U = s.state()
+    assert np.array_equal(U[..., :3], prob.U0[..., :3]) and np.array_equal(U[..., -3:], prob.U0[..., -3:])
+    with pytest.raises(Bd.OsbliError):
+        s.substep(3, 1e-4)   # three-stage scheme: stages 0..2
+    s4 = Solver(prob.with_(rk=I.RK4))
+    s4.substep(4, 1e-4)
+    with pytest.raises(Bd.OsbliError):
+        s4.substep(5, 1e-4)
