@@ -68,9 +68,39 @@ def cpu_baseline(n):
     O.rk_substep(prob, S, J, 0, dt, U, dU)
     el = time.perf_counter() - t0
     threads = O.num_threads()
-    return {"value": round(n ** 3 / el / 1e6, 4), "unit": "Mpoint-substeps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "one RK substage (residual + low-storage update) of TGV %d^3, FP64, %.1f s" % (n, el)}
+    out = {"value": round(n ** 3 / el / 1e6, 4), "unit": "Mpoint-substeps/s", "cores": threads,
+           "kind": "oracle",
+           "sample": "one RK substage (residual + low-storage update) of TGV %d^3, FP64, %.1f s" % (n, el),
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    out["one_thread"] = one_thread_rate(64)
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return "unknown"
+
+
+def one_thread_rate(n):
+    """The oracle on one thread (a child process with OMP_NUM_THREADS=1): one
+    RK substage of TGV n^3, Mpoint-substeps/s."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r); from oracle import oracle as O; "
+            "from paper_2007_14933_amd import inputs; import numpy as np; p = inputs.tgv(%d); S, J = O.metrics(p); "
+            "U = p.U0.copy(); O.apply_bc(p, U); dU = np.zeros(O.int_shape(p)); dt = O.compute_dt(p, S, J, U, 0.5); "
+            "t0 = time.perf_counter(); O.rk_substep(p, S, J, 0, dt, U, dU); el = time.perf_counter() - t0; "
+            "print(%d ** 3 / el / 1e6, el, O.num_threads())" % (ROOT, n, n))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    try:
+        v, el, th = r.stdout.split()[-3:]
+        return {"value": round(float(v), 4), "unit": "Mpoint-substeps/s", "threads": int(th),
+                "sample": "one RK substage of TGV %d^3, %.2f s" % (n, float(el))}
+    except ValueError:
+        return {"error": r.stderr[-300:]}
 
 
 SWEEP_SOURCES = ("paper_2007_14933_amd/csrc/sweep.hpp", "paper_2007_14933_amd/csrc/charflux.hpp",
@@ -135,12 +165,7 @@ def cpu_table():
     from oracle import oracle as O
     from paper_2007_14933_amd import inputs
 
-    out = {"threads": O.num_threads()}
-    try:
-        with open("/proc/cpuinfo") as f:
-            out["cpu"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-    except (OSError, StopIteration):
-        out["cpu"] = "unknown"
+    out = {"threads": O.num_threads(), "cpu": cpu_model()}
     cases = [("sod400_full_run", inputs.sod(400), 10 ** 6, 0.2),
              ("tgv256_2_steps", inputs.tgv(256), 2, 0.0),
              ("tgv64_100_steps", inputs.tgv(64), 100, 0.0),
