@@ -11,6 +11,29 @@
 namespace osbli {
 namespace cf {
 
+// 1/x for positive normal x: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps (each squares the relative error), within about one
+// ulp of the correctly rounded quotient, in half the instructions of an IEEE
+// division (which also rescales for denormals and infinities that the
+// kernels' operands never are).
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(e, r, r);
+    e = fma(-x, r, 1.0);
+    return fma(e, r, r);
+}
+
+// sqrt(x) for positive normal x: g = x rsq(x) ~ sqrt(x) and h = rsq(x)/2,
+// one coupled Newton step on both, then g + (x - g^2) h; within about one ulp.
+__device__ __forceinline__ double sqrt64(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    return fma(fma(-g, g, x), h, g);
+}
 
 template <int ND>
 struct Pt {
@@ -27,14 +50,14 @@ struct Loc {
 // derived quantities of a point whose conserved state is in w.U
 template <int ND>
 __device__ __forceinline__ void finish_point(const Phys &ph, Pt<ND> &w, bool &bad) {
-    const double ri = 1.0 / w.U[0];
+    const double ri = rcp64(w.U[0]);
     double ke = 0.0;
 #pragma unroll
     for (int m = 0; m < ND; ++m) ke += w.U[1 + m] * w.U[1 + m];
     const double p = ph.gm1 * (w.U[ND + 1] - 0.5 * ke * ri);
     w.ri = ri;
     w.p = p;
-    w.a = sqrt(ph.gamma * p * ri);
+    w.a = sqrt64(ph.gamma * p * ri);
     bad |= !(w.U[0] > 0.0 && p > 0.0);
 }
 
@@ -82,7 +105,7 @@ __device__ __forceinline__ double recon5_fin(const R5 &r, double tinv, double CT
         const double a0 = 0.3 * (1.0 + x0 * x0);
         const double a1 = 0.6 * (1.0 + x1 * x1);
         const double a2 = 0.1 * (1.0 + x2 * x2);
-        return (a0 * r.q0 + a1 * r.q1 + a2 * r.q2) / (a0 + a1 + a2);
+        return (a0 * r.q0 + a1 * r.q1 + a2 * r.q2) * rcp64(a0 + a1 + a2);
     } else {
         double c0 = 1.0 + x0, c1 = 1.0 + x1, c2 = 1.0 + x2;
         c0 = c0 * c0 * c0;
@@ -97,7 +120,7 @@ __device__ __forceinline__ double recon5_fin(const R5 &r, double tinv, double CT
         const double num = w0 * r.q0 + w1 * r.q1 + w2 * r.q2;
         if (kept) *kept = *kept && k0 && k1 && k2;
         if (k0 && k1 && k2) return num;
-        return num / (w0 + w1 + w2);
+        return num * rcp64(w0 + w1 + w2);
     }
 }
 
@@ -136,7 +159,7 @@ __device__ __forceinline__ double recon6_teno(double fm2, double fm1, double f0,
     const double tau = fabs(b3 - (b0 + b2 + 4.0 * b1) * (1.0 / 6.0));
     const double e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps, e3 = b3 + eps;
     const double e01 = e0 * e1, e23 = e2 * e3;
-    const double tq = tau / (e01 * e23);
+    const double tq = tau * rcp64(e01 * e23);
     double c0 = 1.0 + tq * (e1 * e23), c1 = 1.0 + tq * (e0 * e23);
     double c2 = 1.0 + tq * (e01 * e3), c3 = 1.0 + tq * (e01 * e2);
     c0 = c0 * c0 * c0;
@@ -150,7 +173,7 @@ __device__ __forceinline__ double recon6_teno(double fm2, double fm1, double f0,
     const double num = w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3;
     if (kept) *kept = *kept && k0 && k1 && k2 && k3;
     if (k0 && k1 && k2 && k3) return num;
-    return num / (w0 + w1 + w2 + w3);
+    return num * rcp64(w0 + w1 + w2 + w3);
 }
 
 // WENO-JS5 (section 2.3, eqs. omega and alpha, p = 2): alpha_r = d_r /
@@ -161,7 +184,7 @@ __device__ __forceinline__ double recon5_js(double fm2, double fm1, double f0, d
     const R5 r = recon5_ind(fm2, fm1, f0, fp1, fp2, eps);
     const double s0 = r.e0 * r.e0, s1 = r.e1 * r.e1, s2 = r.e2 * r.e2;
     const double a0 = 0.3 * (s1 * s2), a1 = 0.6 * (s0 * s2), a2 = 0.1 * (s0 * s1);
-    return (a0 * r.q0 + a1 * r.q1 + a2 * r.q2) / (a0 + a1 + a2);
+    return (a0 * r.q0 + a1 * r.q1 + a2 * r.q2) * rcp64(a0 + a1 + a2);
 }
 
 // WENO-3Z (third-order WENO-Z, the lowest order of section 5.2) at
@@ -175,10 +198,10 @@ __device__ __forceinline__ double recon3_z(double fm1, double f0, double fp1, do
     const double b0 = d0 * d0, b1 = d1 * d1;
     const double tau = fabs(b0 - b1);
     const double e0 = b0 + eps, e1 = b1 + eps;
-    const double tq = tau / (e0 * e1);
+    const double tq = tau * rcp64(e0 * e1);
     const double x0 = tq * e1, x1 = tq * e0;
     const double a0 = (2.0 / 3.0) * (1.0 + x0 * x0), a1 = (1.0 / 3.0) * (1.0 + x1 * x1);
-    return (a0 * q0 + a1 * q1) / (a0 + a1);
+    return (a0 * q0 + a1 * q1) * rcp64(a0 + a1);
 }
 
 // LLF split of one characteristic field over the six points and the two
@@ -212,14 +235,14 @@ __device__ __forceinline__ double split_recon(const double (&V)[6], const double
         const R5 a = recon5_ind(gp[0], gp[1], gp[2], gp[3], gp[4], ph.eps);
         const R5 b = recon5_ind(gm[5], gm[4], gm[3], gm[2], gm[1], ph.eps);
         const double da = (a.e0 * a.e1) * a.e2, db = (b.e0 * b.e1) * b.e2;
-        const double inv = 1.0 / (da * db);
+        const double inv = rcp64(da * db);
         return recon5_fin<SCHEME>(a, (a.tau * db) * inv, ph.CT, kept) +
                recon5_fin<SCHEME>(b, (b.tau * da) * inv, ph.CT, kept);
     } else {
         const R5 a = recon5_ind(gp[0], gp[1], gp[2], gp[3], gp[4], ph.eps);
-        const double ha = recon5_fin<SCHEME>(a, a.tau / ((a.e0 * a.e1) * a.e2), ph.CT, kept);
+        const double ha = recon5_fin<SCHEME>(a, a.tau * rcp64((a.e0 * a.e1) * a.e2), ph.CT, kept);
         const R5 b = recon5_ind(gm[5], gm[4], gm[3], gm[2], gm[1], ph.eps);
-        return ha + recon5_fin<SCHEME>(b, b.tau / ((b.e0 * b.e1) * b.e2), ph.CT, kept);
+        return ha + recon5_fin<SCHEME>(b, b.tau * rcp64((b.e0 * b.e1) * b.e2), ph.CT, kept);
     }
 }
 
@@ -232,10 +255,10 @@ __device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph,
     // averaged state at the half node (Roe, or arithmetic mean with unit weights)
     double sl = 1.0, sr = 1.0;
     if (ph.roe) {
-        sl = sqrt(P[2].r);
-        sr = sqrt(P[3].r);
+        sl = sqrt64(P[2].r);
+        sr = sqrt64(P[3].r);
     }
-    const double iw = 1.0 / (sl + sr);
+    const double iw = rcp64(sl + sr);
     const double un = (sl * (P[2].mn * P[2].ri) + sr * (P[3].mn * P[3].ri)) * iw;
     double ut[2] = {0.0, 0.0};
 #pragma unroll
@@ -245,8 +268,8 @@ __device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph,
 #pragma unroll
     for (int s = 0; s < NT; ++s) K += ut[s] * ut[s];
     K *= 0.5;
-    const double ah = sqrt(ph.gm1 * (Hh - K));
-    const double ia = 1.0 / ah;
+    const double ah = sqrt64(ph.gm1 * (Hh - K));
+    const double ia = rcp64(ah);
     const double b = ph.gm1 * ia * ia;
 
     double unk[6], A[6], B[6], am[6], ap[6], a0 = 0.0;
@@ -520,10 +543,10 @@ __device__ __forceinline__ void cheap_flux(const Loc<ND> (&P)[6], const Phys &ph
     constexpr double D6[6] = {1.0 / 60.0, -5.0 / 60.0, 10.0 / 60.0, -10.0 / 60.0, 5.0 / 60.0, -1.0 / 60.0};
     double sl = 1.0, sr = 1.0;
     if (ph.roe) {
-        sl = sqrt(P[2].r);
-        sr = sqrt(P[3].r);
+        sl = sqrt64(P[2].r);
+        sr = sqrt64(P[3].r);
     }
-    const double iw = 1.0 / (sl + sr);
+    const double iw = rcp64(sl + sr);
     const double un = (sl * (P[2].mn * P[2].ri) + sr * (P[3].mn * P[3].ri)) * iw;
     double ut[2] = {0.0, 0.0};
 #pragma unroll
@@ -533,8 +556,8 @@ __device__ __forceinline__ void cheap_flux(const Loc<ND> (&P)[6], const Phys &ph
 #pragma unroll
     for (int s = 0; s < NT; ++s) K += ut[s] * ut[s];
     K *= 0.5;
-    const double ah = sqrt(ph.gm1 * (Hh - K));
-    const double ia = 1.0 / ah;
+    const double ah = sqrt64(ph.gm1 * (Hh - K));
+    const double ia = rcp64(ah);
     const double b = ph.gm1 * ia * ia;
     double aminus = 0.0, aplus = 0.0, a0 = 0.0;
     double cr = 0.0, cn = 0.0, ct[2] = {0.0, 0.0}, cE = 0.0;   // C6 f
