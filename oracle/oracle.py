@@ -83,6 +83,7 @@ def _load():
                 "orc_phys_flux": (None, [P, _D, _D, _D]),
                 "orc_eigen": (None, [P, C.c_int, _D, _D, _D, _D, _D, _D]),
                 "orc_deriv_line": (None, [_D, C.c_int64, C.c_int, _D]),
+                "orc_deriv2_line": (None, [_D, C.c_int64, C.c_int, _D]),
                 "orc_deriv_field": (None, [P, _D, C.c_int, _D]),
                 "orc_viscosity": (C.c_double, [P, C.c_double]),
                 "orc_num_threads": (C.c_int, []),
@@ -282,6 +283,14 @@ def deriv_line(f, periodic):
     f = np.ascontiguousarray(f, dtype=np.float64)
     out = np.zeros_like(f)
     _load().orc_deriv_line(_dp(f), f.size, int(bool(periodic)), _dp(out))
+    return out
+
+
+def deriv2_line(f, periodic):
+    """Second-derivative operator along a line (unit spacing)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    _load().orc_deriv2_line(_dp(f), f.size, int(bool(periodic)), _dp(out))
     return out
 
 

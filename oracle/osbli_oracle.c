@@ -40,7 +40,8 @@
 #define NCMAX 5
 
 enum { BC_PERIODIC = 0, BC_EXTRAPOLATE = 1, BC_ISOTHERMAL = 2, BC_ADIABATIC = 3, BC_DIRICHLET = 4 };
-enum { SCHEME_WENOZ5 = 0, SCHEME_TENO5 = 1, SCHEME_TENO6 = 2, SCHEME_WENOJS5 = 3, SCHEME_WENOZ3 = 4 };
+enum { SCHEME_WENOZ5 = 0, SCHEME_TENO5 = 1, SCHEME_TENO6 = 2, SCHEME_WENOJS5 = 3, SCHEME_WENOZ3 = 4,
+       SCHEME_CENTRAL4 = 5 };
 enum { RK3_WILLIAMSON = 0, RK3_SSP = 1, RK4_CK = 2 };
 
 typedef struct {
@@ -915,6 +916,177 @@ static void viscous_residual(const orc_params *P, const grid_t *g, const double 
     free(Gv);
 }
 
+/* ---------------------------------------------- fourth-order central path --
+ * Section 2.6: central differences for the convective terms of smooth
+ * problems and for the viscous terms, the scheme of the paper's central TGV
+ * benchmark (section 6.1).  Second-derivative operator per unit index
+ *   f''_i = (-f_{i-2} + 16 f_{i-1} - 30 f_i + 16 f_{i+1} - f_{i+2}) / 12
+ * (written difference-first, so a constant gives exactly 0) with the printed
+ * one-sided closures at nodes 0 and 1, mirrored at N-1 and N-2 (a second
+ * derivative does not change sign under x -> -x); periodic: wrap-around.
+ * Readings (the generated code is not printed):
+ *  - convection in conservative form, R_c -= sum_d D_d(F_d,c) / h_d, with
+ *    F_d the physical flux along e_d at the nodes, on separable meshes of
+ *    uniform spacing h_d per direction (the benchmark's), 1/h_d = J S_dd;
+ *  - viscous and heat-flux terms in the expanded form that differentiating
+ *    the printed equations term by term gives: with g_ij = d_j u_i,
+ *    mu~ = mu(T)/Re and kappa = mu~ / ((gamma-1) M^2 Pr),
+ *      d_j tau_ij = sum_j d_j mu~ (g_ij + g_ji) - (2/3) d_i mu~ div
+ *                 + mu~ [sum_j d_jj u_i + sum_j d_j(g_ji) - (2/3) sum_k d_i(g_kk)],
+ *      d_j (u_i tau_ij - q_j) = sum_ij g_ij tau_ij + sum_i u_i d_j tau_ij
+ *                 + sum_j (d_j kappa d_j T + kappa d_jj T);
+ *    a pure second derivative d_jj (and d_j(g_jj)) takes the second-
+ *    derivative operator, a mixed one d_j(g_ji), i != j, the first
+ *    derivative of the first derivative (outer index as written); d_j mu~
+ *    and d_j kappa are first derivatives of their node values.
+ */
+static double d2line(line_fn fn, const void *ctx, int64_t N, int periodic, int64_t p)
+{
+    if (periodic || (p >= 2 && p <= N - 3)) {
+        const double c = fn(ctx, p);
+        return ((4.0 / 3.0) * ((fn(ctx, p + 1) - c) + (fn(ctx, p - 1) - c))
+                - (1.0 / 12.0) * ((fn(ctx, p + 2) - c) + (fn(ctx, p - 2) - c)));
+    }
+    /* the closures' coefficients sum to zero: written on differences from
+     * the boundary node, so a constant gives exactly 0 */
+    const int m = p <= 1 ? 1 : -1;           /* direction into the domain */
+    const int64_t b = p <= 1 ? 0 : N - 1;    /* boundary node */
+    const double f0 = fn(ctx, b);
+    const double d1 = fn(ctx, b + m) - f0, d2 = fn(ctx, b + 2 * m) - f0;
+    const double d3 = fn(ctx, b + 3 * m) - f0, d4 = fn(ctx, b + 4 * m) - f0;
+    if (p == 0 || p == N - 1)
+        return (-104.0 * d1 + 114.0 * d2 - 56.0 * d3 + 11.0 * d4) / 12.0;
+    /* p == 1 or p == N - 2 */
+    return (-20.0 * d1 + 6.0 * d2 + 4.0 * d3 - d4) / 12.0;
+}
+
+static double d2arr(const orc_params *P, const grid_t *g, const double *a, int dir,
+                    int64_t i, int64_t j, int64_t k)
+{
+    arr_line c = {g, a, dir, i, j, k};
+    int64_t q[3] = {i, j, k};
+    return d2line(arr_line_at, &c, g->n[dir], is_periodic(P, dir), q[dir]);
+}
+
+static void central_residual(const orc_params *P, const grid_t *g, const double *S,
+                             const double *J, const double *U, double *R)
+{
+    const int nd = g->nd, nc = g->nc;
+    const int64_t ni = g->nint;
+    double ih[3] = {0.0, 0.0, 0.0};
+    {
+        const int64_t e0 = gidx(g, 0, 0, 0);
+        for (int d = 0; d < nd; d++) ih[d] = J[e0] * S[(d * 3 + d) * g->npts + e0];
+    }
+    /* convective fluxes F_d at the interior nodes, then their derivatives */
+    double *F = (double *)malloc(sizeof(double) * nd * nc * ni);
+    if (!F) return;
+    #pragma omp parallel for collapse(2)
+    for (int64_t k = 0; k < g->n[2]; k++)
+        for (int64_t j = 0; j < g->n[1]; j++)
+            for (int64_t i = 0; i < g->n[0]; i++) {
+                const int64_t e = gidx(g, i, j, k), c = cidx(g, i, j, k);
+                double Uc[NCMAX], f[NCMAX];
+                for (int q = 0; q < nc; q++) Uc[q] = U[q * g->npts + e];
+                prim_t w;
+                to_prim(P, nd, Uc, &w);
+                for (int d = 0; d < nd; d++) {
+                    double nv[3] = {0.0, 0.0, 0.0};
+                    nv[d] = 1.0;
+                    phys_flux(nd, Uc, &w, nv, f);
+                    for (int q = 0; q < nc; q++) F[(d * nc + q) * ni + c] = f[q];
+                }
+            }
+    #pragma omp parallel for collapse(2)
+    for (int64_t k = 0; k < g->n[2]; k++)
+        for (int64_t j = 0; j < g->n[1]; j++)
+            for (int64_t i = 0; i < g->n[0]; i++) {
+                const int64_t c = cidx(g, i, j, k);
+                for (int q = 0; q < nc; q++) {
+                    double s = 0.0;
+                    for (int d = 0; d < nd; d++) s += ih[d] * darr(P, g, F + (d * nc + q) * ni, d, i, j, k);
+                    R[q * ni + c] -= s;
+                }
+            }
+    free(F);
+    if (!(P->Re > 0.0)) return;
+
+    /* node values: u_m (nd), T, mu~, kappa; then the first derivatives g */
+    const int nv = nd + 1;
+    const double gm = P->gamma, M2 = P->Minf * P->Minf;
+    double *phi = (double *)malloc(sizeof(double) * (nv + 2) * ni);
+    double *gr = (double *)malloc(sizeof(double) * nv * nd * ni);
+    if (!phi || !gr) { free(phi); free(gr); return; }
+    #pragma omp parallel for collapse(2)
+    for (int64_t k = 0; k < g->n[2]; k++)
+        for (int64_t j = 0; j < g->n[1]; j++)
+            for (int64_t i = 0; i < g->n[0]; i++) {
+                double T, u[3];
+                node_T(P, nd, U, gidx(g, i, j, k), g->npts, &T, u);
+                const int64_t c = cidx(g, i, j, k);
+                const double mut = viscosity(P, T) / P->Re;
+                for (int m = 0; m < nd; m++) phi[m * ni + c] = u[m];
+                phi[nd * ni + c] = T;
+                phi[(nd + 1) * ni + c] = mut;
+                phi[(nd + 2) * ni + c] = mut / ((gm - 1.0) * M2 * P->Pr);
+            }
+    #pragma omp parallel for collapse(2)
+    for (int64_t k = 0; k < g->n[2]; k++)
+        for (int64_t j = 0; j < g->n[1]; j++)
+            for (int64_t i = 0; i < g->n[0]; i++) {
+                const int64_t c = cidx(g, i, j, k);
+                for (int v = 0; v < nv; v++)
+                    for (int jj = 0; jj < nd; jj++)
+                        gr[(v * nd + jj) * ni + c] = ih[jj] * darr(P, g, phi + v * ni, jj, i, j, k);
+            }
+    #pragma omp parallel for collapse(2)
+    for (int64_t k = 0; k < g->n[2]; k++)
+        for (int64_t j = 0; j < g->n[1]; j++)
+            for (int64_t i = 0; i < g->n[0]; i++) {
+                const int64_t c = cidx(g, i, j, k);
+                double G[4][3], dmu[3], dka[3];
+                for (int v = 0; v < nv; v++)
+                    for (int jj = 0; jj < nd; jj++) G[v][jj] = gr[(v * nd + jj) * ni + c];
+                for (int jj = 0; jj < nd; jj++) {
+                    dmu[jj] = ih[jj] * darr(P, g, phi + (nd + 1) * ni, jj, i, j, k);
+                    dka[jj] = ih[jj] * darr(P, g, phi + (nd + 2) * ni, jj, i, j, k);
+                }
+                const double mut = phi[(nd + 1) * ni + c], kap = phi[(nd + 2) * ni + c];
+                double div = 0.0;
+                for (int m = 0; m < nd; m++) div += G[m][m];
+                double dtau[3], work = 0.0;
+                for (int a = 0; a < nd; a++) {
+                    double first = -(2.0 / 3.0) * dmu[a] * div, second = 0.0;
+                    for (int b = 0; b < nd; b++) {
+                        first += dmu[b] * (G[a][b] + G[b][a]);
+                        /* d_bb u_a */
+                        second += ih[b] * ih[b] * d2arr(P, g, phi + a * ni, b, i, j, k);
+                        /* d_b (g_ba) */
+                        if (a == b) second += ih[b] * ih[b] * d2arr(P, g, phi + b * ni, b, i, j, k);
+                        else second += ih[b] * darr(P, g, gr + (b * nd + a) * ni, b, i, j, k);
+                        /* -(2/3) d_a (g_bb) */
+                        if (a == b) second -= (2.0 / 3.0) * ih[a] * ih[a] * d2arr(P, g, phi + b * ni, a, i, j, k);
+                        else second -= (2.0 / 3.0) * ih[a] * darr(P, g, gr + (b * nd + b) * ni, a, i, j, k);
+                    }
+                    dtau[a] = first + mut * second;
+                }
+                for (int a = 0; a < nd; a++) {
+                    for (int b = 0; b < nd; b++) {
+                        const double tau = mut * (G[a][b] + G[b][a] - (a == b ? (2.0 / 3.0) * div : 0.0));
+                        work += G[a][b] * tau;
+                    }
+                    work += phi[a * ni + c] * dtau[a];
+                    R[(1 + a) * ni + c] += dtau[a];
+                }
+                double heat = 0.0;
+                for (int b = 0; b < nd; b++)
+                    heat += dka[b] * G[nd][b] + kap * ih[b] * ih[b] * d2arr(P, g, phi + nd * ni, b, i, j, k);
+                R[(nd + 1) * ni + c] += work + heat;
+            }
+    free(phi);
+    free(gr);
+}
+
 /* ------------------------------------------------------------ residual --
  * R = dU/dt on interior nodes: convective part -J sum_d (F_{i+1/2} -
  * F_{i-1/2}) (eq. FD_reconstruct in computational space, all directions,
@@ -928,6 +1100,10 @@ int orc_residual(const orc_params *P, const double *S, const double *J, const do
     const int nd = g.nd, nc = g.nc;
     const int64_t ni = g.nint;
     memset(R, 0, sizeof(double) * nc * ni);
+    if (P->scheme == SCHEME_CENTRAL4) {
+        central_residual(P, &g, S, J, U, R);
+        goto body_force;
+    }
     for (int d = 0; d < nd; d++) {
         int64_t N = g.n[d];
         int o1 = (d + 1) % 3, o2 = (d + 2) % 3;
@@ -958,6 +1134,7 @@ int orc_residual(const orc_params *P, const double *S, const double *J, const do
             }
     }
     if (P->Re > 0.0) viscous_residual(P, &g, S, J, U, R);
+body_force:
     if (P->body_force != 0.0) {
         for (int64_t k = 0; k < g.n[2]; k++)
             for (int64_t j = 0; j < g.n[1]; j++)
@@ -1201,6 +1378,18 @@ void orc_eigen(const orc_params *P, int d, const double *UL, const double *UR, c
 }
 
 /* D of a 1D array (n points; periodic flag) */
+void orc_deriv2_line(const double *f, int64_t n, int periodic, double *out)
+{
+    orc_params P;
+    memset(&P, 0, sizeof(P));
+    P.ndim = 1;
+    P.n[0] = n;
+    P.bc[0][0] = P.bc[0][1] = periodic ? BC_PERIODIC : BC_EXTRAPOLATE;
+    grid_t g;
+    grid_make(&P, &g);
+    for (int64_t i = 0; i < n; i++) out[i] = d2arr(&P, &g, f, 0, i, 0, 0);
+}
+
 void orc_deriv_line(const double *f, int64_t n, int periodic, double *out)
 {
     orc_params P;
