@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / sensor forms")
     ap.add_argument("--cpu-n", type=int, default=0, help="oracle sample grid (default: same as --n)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble line")
+    ap.add_argument("--no-central", action="store_true", help="skip the central-path (StoreSome) line")
+    ap.add_argument("--central-steps", type=int, default=20)
     ap.add_argument("--batch-steps", type=int, default=30)
     ap.add_argument("--batch-full", action="store_true",
                     help="also run both batched forms to t = 0.25 and report their density difference")
@@ -402,6 +404,51 @@ def sensor_form(cfl):
     return res
 
 
+def central_form(steps, warmup, cfl, sizes=(192, 256)):
+    """The fourth-order central path on the viscous TGV (the paper's central
+    benchmark; 192^3 is its one-GPU size): StoreSome (velocity gradients
+    stored) against store-all (every derivative in its own work array), same
+    steps, same kernels otherwise."""
+    import torch
+    from paper_2007_14933_amd import inputs
+    from paper_2007_14933_amd.solver import Solver
+    out = {}
+    for n in sizes:
+        prob = inputs.tgv(n, scheme=inputs.CENTRAL4)
+        r = {}
+        for name, store_all in (("storesome", False), ("storeall", True)):
+            s = Solver(prob)
+            if store_all:
+                s.central_store_all(True)
+            s.apply_bc()
+            for _ in range(warmup):
+                s.step(s.compute_dt(cfl))
+            torch.cuda.synchronize()
+            s.profile(True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                s.step(s.compute_dt(cfl))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            s.check()
+            prof = s.profile_read()
+            s.profile(False)
+            nst = s.nstages
+            r[name] = {"value": round(prob.npoints * nst * steps / wall / 1e6, 3),
+                       "ms_per_step": round(wall * 1e3 / steps, 4),
+                       "central_ms_per_substage": round(prof["central"][1] / max(1, prof["central"][0]), 4),
+                       "finish_ms_per_substage": round(prof["finish"][1] / max(1, prof["finish"][0]), 4)}
+            del s
+            torch.cuda.empty_cache()
+        r["storesome_speedup"] = round(r["storesome"]["value"] / r["storeall"]["value"], 3)
+        out["tgv%d" % n] = r
+    out["workload"] = ("TGV n^3 periodic, Re=1600, M=0.1, fourth-order central convection + expanded viscous terms, "
+                       "RK3 CFL=0.5, FP64; %d timed steps" % steps)
+    out["arrays_per_node"] = {"storesome": "U 5 + dU 5 + velocity gradients 9 + residual 5 = 24",
+                              "storeall": "U 5 + dU 5 + 57 derivative arrays (63 slots) + residual 5 = 72"}
+    return out
+
+
 def batch_form(steps, warmup, cfl, tune, full):
     """The batched ensemble: 64 seeded four-quadrant Riemann problems,
     N in {128, 192, ..., 1024}, each with its own dt.  Timed over `steps`
@@ -555,6 +602,9 @@ def main():
         out["forms"]["learned_sensor"] = sensor_form(args.cfl)
         log("wall flow 512x256x256: plain and precision form")
         out["forms"]["wall_precision"] = wall_precision(args.cfl)
+    if not args.no_central:
+        log("central path: StoreSome against store-all")
+        out["central"] = central_form(args.central_steps, args.warmup, args.cfl)
     if not args.no_batch:
         log("batched Riemann ensemble")
         out["batch"] = batch_form(args.batch_steps, args.warmup, args.cfl, not args.no_tune, args.batch_full)

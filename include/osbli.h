@@ -80,7 +80,27 @@ enum osbli_bc {
  *   WENOZ3  third-order WENO-Z (stencils {i, i+1}, {i-1, i}, weights
  *           (2/3, 1/3), tau_3 = |beta_0 - beta_1|).
  * The precision form takes WENOZ5 and TENO5; sensor routing TENO5. */
-enum osbli_scheme { OSBLI_WENOZ5 = 0, OSBLI_TENO5 = 1, OSBLI_TENO6 = 2, OSBLI_WENOJS5 = 3, OSBLI_WENOZ3 = 4 };
+enum osbli_scheme {
+    OSBLI_WENOZ5 = 0, OSBLI_TENO5 = 1, OSBLI_TENO6 = 2, OSBLI_WENOJS5 = 3, OSBLI_WENOZ3 = 4,
+    OSBLI_CENTRAL4 = 5  /* fourth-order central path, below */
+};
+
+/* OSBLI_CENTRAL4 (section 2.6, central schemes for smooth problems; the
+ * scheme of the central Taylor-Green benchmark of section 6.1), on separable
+ * meshes of uniform spacing per direction (checked at set-up), FP64 form:
+ * convection in conservative form, -sum_d D_d(F_d)/h_d with the fourth-order
+ * first derivative and its one-sided closures; viscous and heat-flux terms
+ * in expanded form: with g_ab = d_b u_a, mu~ = mu(T)/Re, kappa = mu~ /
+ * ((gamma-1) M^2 Pr),
+ *   d_b tau_ab = sum_b d_b mu~ (g_ab + g_ba) - (2/3) d_a mu~ div
+ *              + mu~ [sum_b d_bb u_a + sum_b d_b(g_ba) - (2/3) sum_b d_a(g_bb)],
+ *   energy     = sum_ab g_ab tau_ab + sum_a u_a d_b tau_ab
+ *              + sum_b (d_b kappa d_b T + kappa d_bb T),
+ * pure second derivatives with the printed second-derivative operator and
+ * its one-sided closures, mixed ones as first derivatives of first
+ * derivatives.  Two storage strategies (section 6.1): StoreSome (default;
+ * only the velocity gradients are stored, in the workspace) and store-all
+ * (osbli_central_store_all). */
 
 /* Low-storage (2N) Runge-Kutta schemes of section 2.7,
  * dU <- A_s dU + dt R(U), U <- U + B_s dU, A_0 = 0:
@@ -172,6 +192,16 @@ int osbli_rk_substep(osbli_ctx *ctx, int stage, double dt, double *U, double *dU
  * 5), and its coefficients A[s], B[s] (host arrays of at least 5). */
 int osbli_rk_stages(const osbli_ctx *ctx);
 int osbli_rk_coeffs(const osbli_ctx *ctx, double *A, double *B);
+
+/* Central path, store-all strategy (section 6.1's baseline): every
+ * derivative of the residual in its own work array, written by its own pass
+ * and read back by an assembling pass.  osbli_central_store_all_bytes gives
+ * the work size for params (0 unless scheme is OSBLI_CENTRAL4);
+ * osbli_central_store_all(ctx, work, bytes) switches the context to it with
+ * the caller's device buffer (256-byte aligned, kept until switched back),
+ * or back to StoreSome with work = NULL.  Results agree to rounding. */
+size_t osbli_central_store_all_bytes(const osbli_params *params);
+int osbli_central_store_all(osbli_ctx *ctx, void *work, size_t bytes);
 
 /* Allocation-free variant of osbli_rk_substep, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
@@ -366,7 +396,8 @@ enum osbli_kernel_class {
     OSBLI_K_BC = 5,        /* boundary-condition launches of one osbli_apply_bc */
     OSBLI_K_DT = 6,        /* time-step reduction */
     OSBLI_K_SENSOR = 7,    /* learned-sensor routing masks */
-    OSBLI_K_COUNT = 8
+    OSBLI_K_CENTRAL = 8,   /* central path: derivative and residual passes */
+    OSBLI_K_COUNT = 9
 };
 
 /* Instrumentation (not part of the method): when enabled, each launch group

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libosbli.so")
 
 OSBLI_OK, OSBLI_EINVAL, OSBLI_EDEVICE, OSBLI_ENONPHYS, OSBLI_ENOSPACE = 0, -1, -2, -3, -4
 PERIODIC, EXTRAPOLATE, ISOTHERMAL_WALL, ADIABATIC_WALL, DIRICHLET = 0, 1, 2, 3, 4
-WENOZ5, TENO5, TENO6, WENOJS5, WENOZ3 = 0, 1, 2, 3, 4
+WENOZ5, TENO5, TENO6, WENOJS5, WENOZ3, CENTRAL4 = 0, 1, 2, 3, 4, 5
 RK3, RK3_SSP, RK4 = 0, 1, 2
 FORM_FP64, FORM_MIXED = 0, 1
 MESH_SEPARABLE, MESH_GENERAL = 0, 1
@@ -57,6 +57,8 @@ _SIGS = {
     "osbli_rk_substep_noalloc": (C.c_int, [_VP, C.c_int, C.c_double, _VP, _VP, _VP]),
     "osbli_noalloc_scratch_bytes": (C.c_size_t, []),
     "osbli_rk_stages": (C.c_int, [_VP]),
+    "osbli_central_store_all_bytes": (C.c_size_t, [C.POINTER(Params)]),
+    "osbli_central_store_all": (C.c_int, [_VP, _VP, C.c_size_t]),
     "osbli_rk_coeffs": (C.c_int, [_VP, _DP, _DP]),
     "osbli_compute_dt": (C.c_int, [_VP, _VP, C.c_double, _DP, _VP]),
     "osbli_check": (C.c_int, [_VP]),
@@ -88,8 +90,8 @@ _SIGS = {
     "osbli_batch_destroy": (None, [_VP]),
 }
 
-K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_VISC_FLUX, K_FINISH, K_BC, K_DT, K_SENSOR = range(8)
-K_NAMES = ["sweep_x", "sweep_y", "sweep_z", "visc_flux", "finish", "bc", "dt", "sensor"]
+K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_VISC_FLUX, K_FINISH, K_BC, K_DT, K_SENSOR, K_CENTRAL = range(9)
+K_NAMES = ["sweep_x", "sweep_y", "sweep_z", "visc_flux", "finish", "bc", "dt", "sensor", "central"]
 
 
 def load():

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libosbli.so")
 SOURCES = ["abi.hip", "convective.hip", "convective_teno6.hip", "convective_wenojs5.hip", "convective_wenoz3.hip",
-           "viscous.hip", "bc.hip", "metrics.hip", "sensor.hip", "batch.hip"]
+           "viscous.hip", "central.hip", "bc.hip", "metrics.hip", "sensor.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

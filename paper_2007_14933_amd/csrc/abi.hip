@@ -1,5 +1,6 @@
 // C ABI of libosbli (declared in include/osbli.h): parameter validation,
 // workspace carve-up, context lifecycle and the per-call launch sequences.
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -80,6 +81,7 @@ struct osbli_ctx {
     hipError_t scratch_err;
     int nstages;           // Runge-Kutta substages per step (3 or 5)
     double rkA[5], rkB[5]; // their 2N coefficients
+    void *cwork;           // central path: the store-all strategy's work arrays (null: StoreSome)
     char err[320];
 };
 
@@ -142,7 +144,12 @@ int make_grid(const osbli_params *p, Grid &g, char *buf, size_t nb) {
     g.is[2] = g.n[0] * g.n[1];
     g.nint = g.n[0] * g.n[1] * g.n[2];
     if (!(p->gamma > 1.0)) { snprintf(buf, nb, "gamma must exceed 1"); return -1; }
-    if (p->scheme < OSBLI_WENOZ5 || p->scheme > OSBLI_WENOZ3) { snprintf(buf, nb, "bad scheme"); return -1; }
+    if (p->scheme < OSBLI_WENOZ5 || p->scheme > OSBLI_CENTRAL4) { snprintf(buf, nb, "bad scheme"); return -1; }
+    if (p->scheme == OSBLI_CENTRAL4 && (p->mesh == OSBLI_MESH_GENERAL && p->ndim > 1)) {
+        snprintf(buf, nb, "the central path takes separable meshes of uniform spacing");
+        return -1;
+    }
+    if (p->scheme == OSBLI_CENTRAL4 && p->sensor) { snprintf(buf, nb, "sensor routing needs TENO5"); return -1; }
     if (p->rk < OSBLI_RK3 || p->rk > OSBLI_RK4) { snprintf(buf, nb, "bad Runge-Kutta scheme %d", p->rk); return -1; }
     if (p->form != OSBLI_FORM_FP64 && p->form != OSBLI_FORM_MIXED) { snprintf(buf, nb, "bad form %d", p->form); return -1; }
     if (p->form == OSBLI_FORM_MIXED && p->scheme != OSBLI_WENOZ5 && p->scheme != OSBLI_TENO5) {
@@ -405,6 +412,19 @@ int osbli_init_grid(osbli_ctx **out, const osbli_params *p, const double *x, con
     const double *X[3] = {x, y, z};
     for (int d = 0; d < p->ndim; ++d)
         if (!X[d]) return set_err(c, OSBLI_EINVAL, "coordinates of direction %d missing", d);
+    if (p->scheme == OSBLI_CENTRAL4) {
+        // the expanded second derivatives assume a uniform spacing per direction
+        for (int d = 0; d < p->ndim; ++d) {
+            const int64_t N = c->g.n[d];
+            const double h = X[d][1] - X[d][0];
+            if (!(h > 0.0)) return set_err(c, OSBLI_EINVAL, "central path: coordinates of direction %d not increasing", d);
+            for (int64_t i = 1; i + 1 < N; ++i)
+                if (fabs((X[d][i + 1] - X[d][i]) - h) > 1e-10 * h)
+                    return set_err(c, OSBLI_EINVAL, "central path: spacing of direction %d not uniform", d);
+            if (c->g.periodic[d] && fabs(p->period[d] - N * h) > 1e-10 * N * h)
+                return set_err(c, OSBLI_EINVAL, "central path: period of direction %d is not n h", d);
+        }
+    }
     HIP_TRY(c, hipGetDevice(&c->device));
     // the allocation-free substep's scratch on this device (a failure here
     // only disables that entry point)
@@ -477,6 +497,11 @@ int osbli_residual(osbli_ctx *c, const double *U, double *R, void *stream) {
     if ((const void *)U == (const void *)R) return set_err(c, OSBLI_EINVAL, "R aliases U");
     hipStream_t s = as_stream(stream);
     c->last = s;
+    if (c->p.scheme == OSBLI_CENTRAL4) {
+        Timed t(c, OSBLI_K_CENTRAL, s);
+        HIP_TRY(c, launch_central(c->g, c->ph, c->m, U, c->G, c->cwork, R, s));
+        return OSBLI_OK;
+    }
     if (c->p.sensor && c->sensor_ready) HIP_TRY(c, sensor_all(c, U, s));
     if (c->ph.viscous) {
         Timed t(c, OSBLI_K_VISC_FLUX, s);
@@ -507,6 +532,17 @@ int osbli_rk_substep(osbli_ctx *c, int stage, double dt, double *U, double *dU, 
     if ((void *)U == (void *)dU) return set_err(c, OSBLI_EINVAL, "dU aliases U");
     hipStream_t s = as_stream(stream);
     c->last = s;
+    if (c->p.scheme == OSBLI_CENTRAL4) {
+        {
+            Timed t(c, OSBLI_K_CENTRAL, s);
+            HIP_TRY(c, launch_central(c->g, c->ph, c->m, U, c->G, c->cwork, c->Racc, s));
+        }
+        Timed t(c, OSBLI_K_FINISH, s);
+        Phys pf = c->ph;
+        pf.viscous = 0;  // the residual is complete: the pointwise finish only applies the stage
+        HIP_TRY(c, launch_finish(c->g, pf, c->m, c->Racc, nullptr, nullptr, stage_of(c, stage), dt, U, dU, 1, s));
+        return OSBLI_OK;
+    }
     if (c->p.sensor && c->sensor_ready && (stage == 0 || c->sensor_every)) HIP_TRY(c, sensor_all(c, U, s));
     if (c->ph.viscous) {
         Timed t(c, OSBLI_K_VISC_FLUX, s);
@@ -541,6 +577,13 @@ int osbli_rk_substep_noalloc(osbli_ctx *c, int stage, double dt, double *U, doub
     // the same launches as osbli_rk_substep, with the accumulator (stored,
     // not accumulated, by the first sweep) and the viscous fluxes (every
     // interior node written) in the scratch array; no profiling events
+    if (c->p.scheme == OSBLI_CENTRAL4) {
+        HIP_TRY(c, launch_central(c->g, c->ph, c->m, U, G, c->cwork, Racc, s));
+        Phys pf = c->ph;
+        pf.viscous = 0;
+        HIP_TRY(c, launch_finish(c->g, pf, c->m, Racc, nullptr, nullptr, stage_of(c, stage), dt, U, dU, 1, s));
+        return OSBLI_OK;
+    }
     const bool route = c->p.sensor && c->sensor_ready;
     if (route && (stage == 0 || c->sensor_every))
         for (int d = 0; d < c->g.nd; ++d)
@@ -550,6 +593,27 @@ int osbli_rk_substep_noalloc(osbli_ctx *c, int stage, double dt, double *U, doub
         HIP_TRY(c, launch_convective(c->g, c->ph, c->m, U, Racc, c->flags, d, d == 0, route ? c->mask[d] : nullptr,
                                      c->seg[d], s));
     HIP_TRY(c, launch_finish(c->g, c->ph, c->m, Racc, G, nullptr, stage_of(c, stage), dt, U, dU, 1, s));
+    return OSBLI_OK;
+}
+
+size_t osbli_central_store_all_bytes(const osbli_params *p) {
+    Grid g;
+    char buf[200];
+    if (make_grid(p, g, buf, sizeof buf) != 0 || p->scheme != OSBLI_CENTRAL4) return 0;
+    return central_work_bytes(g, p->Re > 0.0);
+}
+
+int osbli_central_store_all(osbli_ctx *c, void *work, size_t ws_bytes) {
+    if (!c) return OSBLI_EINVAL;
+    if (c->p.scheme != OSBLI_CENTRAL4) return set_err(c, OSBLI_EINVAL, "context does not use the central path");
+    if (!work) {
+        c->cwork = nullptr;
+        return OSBLI_OK;
+    }
+    const size_t need = central_work_bytes(c->g, c->ph.viscous != 0);
+    if (ws_bytes < need) return set_err(c, OSBLI_ENOSPACE, "store-all work %zu bytes, need %zu", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(work) % 256 != 0) return set_err(c, OSBLI_EINVAL, "work not 256-byte aligned");
+    c->cwork = work;
     return OSBLI_OK;
 }
 

@@ -115,6 +115,12 @@ hipError_t launch_viscous_fluxes(const Grid &g, const Phys &ph, const Metrics &m
 hipError_t launch_finish(const Grid &g, const Phys &ph, const Metrics &m, const double *Racc,
                          const double *G, double *Rout, RkStage rs, double dt, double *U, double *dU,
                          int mode, hipStream_t s);
+// fourth-order central path: residual R of U (ghosts valid); Gs: velocity
+// gradients (nd^2 per node), used by the StoreSome strategy (work == null);
+// work: the store-all strategy's arrays (central_work_bytes)
+size_t central_work_bytes(const Grid &g, bool viscous);
+hipError_t launch_central(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *Gs, void *work,
+                          double *R, hipStream_t s);
 hipError_t launch_dt(const Grid &g, const Phys &ph, const Metrics &m, const double *U,
                      unsigned long long *slot, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int n, hipStream_t s);

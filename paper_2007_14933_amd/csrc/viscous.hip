@@ -10,28 +10,10 @@
 // Pass 2 (k_finish): per node, J sum_k D_k G_k added to the convective
 // residual, then either stored (residual call) or folded into the RK update.
 #include "point.hpp"
+#include "stencil.hpp"
 
 namespace osbli {
 namespace {
-
-// first derivative per unit index at position p of a line of N nodes; `at`
-// returns the operand at a line index (periodic lines may be read at
-// p +- 1, p +- 2 outside [0, N)).
-template <class At>
-__device__ __forceinline__ double dline(const At &at, int64_t p, int64_t N, bool periodic) {
-    if (periodic || (p >= 2 && p <= N - 3))
-        return (2.0 / 3.0) * (at(p + 1) - at(p - 1)) - (1.0 / 12.0) * (at(p + 2) - at(p - 2));
-    if (p == 0)
-        return (-25.0 * at(0) + 48.0 * at(1) - 36.0 * at(2) + 16.0 * at(3) - 3.0 * at(4)) / 12.0;
-    if (p == 1)
-        return (-3.0 * at(0) - 10.0 * at(1) + 18.0 * at(2) - 6.0 * at(3) + at(4)) / 12.0;
-    if (p == N - 2)
-        return (-at(N - 5) + 6.0 * at(N - 4) - 18.0 * at(N - 3) + 10.0 * at(N - 2) + 3.0 * at(N - 1)) / 12.0;
-    return (3.0 * at(N - 5) - 16.0 * at(N - 4) + 36.0 * at(N - 3) - 48.0 * at(N - 2) + 25.0 * at(N - 1)) / 12.0;
-}
-
-// pointwise kernels: blocks of 64 x 4 threads over (i, j) of one k plane
-constexpr int kBX = 64, kBY = 4;
 
 // Tile placement: workgroups go to the eight XCDs (each with its own L2) in
 // turn, so a 1D grid of 8 * per blocks is used and the linear block id b is
@@ -63,18 +45,6 @@ __device__ __forceinline__ bool node_of_thread(const Grid &g, const NodeTiles &T
     idx[1] = (int64_t)by * kBY + threadIdx.y;
     idx[2] = L / (T.tx * T.ty);
     return idx[0] < g.n[0] && idx[1] < g.n[1];
-}
-
-// the plain 3D grid: blockIdx (x, y) over the plane's tiles, blockIdx.z the plane
-__device__ __forceinline__ bool node_of_plane_thread(const Grid &g, int64_t (&idx)[3]) {
-    idx[0] = (int64_t)blockIdx.x * kBX + threadIdx.x;
-    idx[1] = (int64_t)blockIdx.y * kBY + threadIdx.y;
-    idx[2] = blockIdx.z;
-    return idx[0] < g.n[0] && idx[1] < g.n[1];
-}
-
-inline dim3 node_grid(const Grid &g) {
-    return dim3((unsigned)((g.n[0] + kBX - 1) / kBX), (unsigned)((g.n[1] + kBY - 1) / kBY), (unsigned)g.n[2]);
 }
 
 template <int ND>

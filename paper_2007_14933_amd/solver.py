@@ -147,6 +147,18 @@ class Solver:
         torch.cuda.synchronize(self.device)
         return out.cpu().numpy()
 
+    def central_store_all(self, enable=True):
+        """Central path: switch to the store-all strategy (every derivative in
+        its own work array, allocated here) or back to StoreSome."""
+        if not enable:
+            B.check(self.lib.osbli_central_store_all(self.ctx, None, 0), self.ctx)
+            self._cwork = None
+            return
+        nb = self.lib.osbli_central_store_all_bytes(C.byref(self.params))
+        self._cwork = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._cwork.data_ptr()) % 256
+        B.check(self.lib.osbli_central_store_all(self.ctx, C.c_void_p(self._cwork.data_ptr() + off), nb), self.ctx)
+
     def rk_coeffs(self):
         A = (C.c_double * 5)()
         Bc = (C.c_double * 5)()

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2007_14933_amd import binding as B
@@ -93,6 +94,35 @@ def test_too_few_wall_nodes_rejected(lib):
     lib.osbli_destroy(ctx)
 
 
+@pytest.mark.parametrize("why", ["non-uniform", "period"])
+def test_central_path_needs_uniform_spacing(lib, why):
+    """The central path's expanded second derivatives assume uniform spacing:
+    a stretched mesh (or a period other than n h) is refused at set-up, on
+    the host, before any device call."""
+    prob = I.tgv(8, scheme=I.CENTRAL4)
+    p = B.make_params(prob)
+    x = np.ascontiguousarray(prob.coords1d[0], dtype=np.float64).copy()
+    if why == "non-uniform":
+        x[3] += 1e-3
+    else:
+        p.period[0] = 1.01 * p.period[0]
+    xs = [x.ctypes.data_as(C.POINTER(C.c_double))] + [
+        np.ascontiguousarray(prob.coords1d[d]).ctypes.data_as(C.POINTER(C.c_double)) for d in (1, 2)]
+    need = lib.osbli_workspace_bytes(C.byref(p))
+    ctx = C.c_void_p()
+    rc = lib.osbli_init_grid(C.byref(ctx), C.byref(p), *xs, C.c_void_p(256), need, None)
+    assert rc == B.OSBLI_EINVAL and b"central path" in lib.osbli_last_error(ctx)
+    lib.osbli_destroy(ctx)
+
+
+def test_central_store_all_sizes(lib):
+    p = B.make_params(I.tgv(16, scheme=I.CENTRAL4))
+    n = 16 ** 3
+    # F 15, G 18, S 12, X 9, Y 9 arrays of n doubles
+    assert lib.osbli_central_store_all_bytes(C.byref(p)) == 8 * n * (15 + 18 + 12 + 9 + 9)
+    assert lib.osbli_central_store_all_bytes(C.byref(B.make_params(I.tgv(16)))) == 0
+
+
 def test_small_workspace_rejected(lib):
     prob = I.sod(50)
     p = B.make_params(prob)
@@ -124,6 +154,9 @@ def _gpu_test_problems():
     out.append(("sod80_teno", I.sod(80).with_(scheme=I.TENO5), 0, 1))
     import test_gpu_schemes as TS
     for name, (prob, _) in TS.CASES.items():
+        out.append((name, prob, 0, 0))
+    import test_gpu_central as TC
+    for name, (prob, _) in TC.CASES.items():
         out.append((name, prob, 0, 0))
     return out
 
