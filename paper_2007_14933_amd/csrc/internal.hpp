@@ -60,6 +60,31 @@ __host__ __device__ inline int64_t int_index(const Grid &g, int64_t i, int64_t j
 // flags word bits
 constexpr unsigned kFlagNonPhys = 1u;
 
+// 1/x for positive normal x: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps (each squares the relative error), within about one
+// ulp of the correctly rounded quotient, in half the instructions of an IEEE
+// division (which also rescales for denormals and infinities that the
+// kernels' operands never are).
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(e, r, r);
+    e = fma(-x, r, 1.0);
+    return fma(e, r, r);
+}
+
+// sqrt(x) for positive normal x: g = x rsq(x) ~ sqrt(x) and h = rsq(x)/2,
+// one coupled Newton step on both, then g + (x - g^2) h; within about one ulp.
+__device__ __forceinline__ double sqrt64(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    return fma(fma(-g, g, x), h, g);
+}
+
+
 // One stage of a low-storage (2N) Runge-Kutta scheme: dU <- A dU + dt R
 // (first: A = 0 and dU is not read), U <- U + B dU (last: dU is not stored,
 // the register is not read again before the next step's first stage).

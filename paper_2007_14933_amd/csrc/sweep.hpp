@@ -286,12 +286,18 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
             }
         }
         double Fr, Fn, Ft[2], FE;
+        // per-interface routing: an interface evaluated by two waves (the
+        // first interface of a segment) takes the same flux in both, so the
+        // flux differences stay conservative
         const bool cheap = ROUTE && mw[2] && (ph.dilate < 1 || (mw[1] && mw[3])) && (ph.dilate < 2 || (mw[0] && mw[4]));
         if (cheap) {
             if (MIX) cheap_flux_mixed<ND>(P, ph, Fr, Fn, Ft, FE);
             else cheap_flux<ND>(P, ph, Fr, Fn, Ft, FE);
         } else {
-            if (MIX) char_flux_mixed<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
+            // the routed forms fall back to the full flux in FP64: near a shock
+            // the deviations from the reference flux are as large as the jump,
+            // and their FP32 rounding is the precision form's main error there
+            if (MIX && !ROUTE) char_flux_mixed<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
             else char_flux<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
         }
         F[0] = Fr * Smag;
@@ -338,7 +344,7 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
 // waves they spill, which cost more (1.29 vs 0.93 ms at 256^3) than the
 // lost occupancy.
 template <int ND, int DIR, int SCHEME, bool GEN, bool MIX, bool ROUTE>
-__global__ void __launch_bounds__(256, GEN || (MIX && ROUTE) ? 1 : 2)
+__global__ void __launch_bounds__(256, GEN ? 1 : 2)
 k_sweep(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t seg,
         int64_t nseg, int first, unsigned *flags, const uint8_t *__restrict__ mask) {
     __shared__ double sbuf[DIR == 0 ? kWaves : 1][ND + 2][kChunk][64];
@@ -491,7 +497,8 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
         if (MIX) cheap_flux_mixed<ND>(P, ph, Fr, Fn, Ft, FE);
         else cheap_flux<ND>(P, ph, Fr, Fn, Ft, FE);
     } else {
-        if (MIX) char_flux_mixed<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
+        // routed forms: full flux in FP64 (as in the marching sweeps)
+        if (MIX && !ROUTE) char_flux_mixed<ND, SCHEME>(P, ph, Fr, Fn, Ft, FE);
         else char_flux<ND, SCHEME, false>(P, ph, Fr, Fn, Ft, FE);
     }
     double F[NC];

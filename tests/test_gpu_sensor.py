@@ -173,8 +173,9 @@ def oracle_cheap_residual(prob, U):
 
 @pytest.mark.parametrize("mixed", [0, 1])
 def test_routed_limits(mixed):
-    """All interfaces routed cheap: the oracle's cheap flux everywhere; all
-    routed full: the plain residual."""
+    """All interfaces routed cheap: the oracle's cheap flux everywhere (FP32
+    deviations in the precision form); all routed full: the plain FP64
+    residual (the routed forms fall back to the FP64 full flux)."""
     from paper_2007_14933_amd.solver import Solver
     prob = I.riemann2d(40, 11)
     U = state_after(prob, 20)
@@ -194,7 +195,8 @@ def test_routed_limits(mixed):
     s2.set_sensor(const_net(-30.0), 0.5)
     Rf = s2.residual().cpu().numpy()
     assert s2.sensor_stats()[0] == 0
-    Rp = Solver(p2, form=mixed).residual().cpu().numpy()
+    # the routed forms' full flux is the FP64 one in both precisions
+    Rp = Solver(p2).residual().cpu().numpy()
     assert np.abs(Rf - Rp).max() <= 1e-13 * np.abs(Rp).max()
 
 
@@ -290,13 +292,12 @@ def test_routing_masks_match_oracle_decisions(case):
     assert 0 < nsmooth < ntot  # both classes occur
 
 
-def test_trained_sensor_error_and_gain():
+@pytest.fixture(scope="module")
+def trained_routing_run():
     """Train the network on method-made labels (small run), choose the
     routing (threshold, dilation) on held-out shock-vortex seeds, then run
-    the measured shock-vortex field (seed 42) routed vs plain to its end
-    time: density L1 error <= 1e-4 relative.  The routed fraction and the
-    sweep times are reported (how much is routed depends on how well the
-    network separates the classes, which this small run does not pin)."""
+    the measured shock-vortex field (seed 42, 256 x 128) routed and plain to
+    its end time."""
     import torch
     from paper_2007_14933_amd import sensor as SN
     from paper_2007_14933_amd.solver import Solver
@@ -310,7 +311,6 @@ def test_trained_sensor_error_and_gain():
     _, rec = SN.pick_threshold(zv, yv)
     acc = float(((zv >= 0) == (yv == 1)).float().mean().item())
     say("   samples %d, held-out accuracy %.4f, smooth recall at 0.1%% false-smooth %.3f" % (len(y), acc, rec))
-    assert acc > 0.6  # balanced classes: well above chance
     thr, _, _, dil = SN.pick_threshold_by_error(tr.weights_bits(), SN.heldout_problems(256, 128, (1000, 1001)),
                                                  log=say)
     prob = I.shock_vortex(256, 128, seed=42)
@@ -323,13 +323,37 @@ def test_trained_sensor_error_and_gain():
         s.run(10 ** 9, cfl=prob.cfl, t_end=prob.t_end)
         s.check()
         prof = s.profile_read()
-        res[name] = (s.interior(), sum(prof["sweep_%s" % a][1] for a in "xy"), s.sensor_stats() if kw else None,
-                     prof["sensor"][1], s.nsteps_done)
-    a, b = res["routed"][0], res["plain"][0]
-    l1 = np.abs(a[0] - b[0]).mean() / np.abs(b[0]).mean()
-    sm, tot = res["routed"][2]
+        res[name] = {"rho": s.interior()[0], "sweep_ms": sum(prof["sweep_%s" % a][1] for a in "xy"),
+                     "sensor_ms": prof["sensor"][1], "stats": s.sensor_stats() if kw else None,
+                     "steps": s.nsteps_done}
+    a, b = res["routed"]["rho"], res["plain"]["rho"]
+    res["l1"] = np.abs(a - b).mean() / np.abs(b).mean()
+    res["acc"], res["thr"] = acc, thr
+    sm, tot = res["routed"]["stats"]
     say("   threshold %.3f, %d steps: rel L1(rho) routed vs plain %.3e; smooth fraction %.3f; "
         "sweep ms plain %.2f routed %.2f (+ sensor %.2f)"
-        % (thr, res["plain"][4], l1, sm / tot, res["plain"][1], res["routed"][1], res["routed"][3]))
-    assert l1 <= 1e-4
-    assert 0 <= sm <= tot
+        % (thr, res["plain"]["steps"], res["l1"], sm / tot, res["plain"]["sweep_ms"], res["routed"]["sweep_ms"],
+           res["routed"]["sensor_ms"]))
+    return res
+
+
+def test_trained_sensor_error(trained_routing_run):
+    """The trained network separates the classes well above chance, and the
+    routed run stays within the 1e-4 relative L1 density bar of plain."""
+    r = trained_routing_run
+    assert r["acc"] > 0.6  # balanced classes: well above chance
+    assert r["l1"] <= 1e-4
+    sm, tot = r["routed"]["stats"]
+    assert sm > 0  # some interfaces do take the cheap flux
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "measured on MI355X: the routed sweeps plus the sensor are slower than plain TENO5 sweeps -- "
+    "only 5-12 % of the shock-vortex interfaces are routed cheap by the network trained here, the cheap "
+    "flux is about 35 % cheaper than TENO5 per interface (the Roe state, eigen-projection, per-point "
+    "loads and the register window stay), and features plus inference cost about a quarter of a sweep"))
+def test_trained_sensor_gain(trained_routing_run):
+    """What the trained network gains over the method without it: routed
+    sweeps plus the sensor against the plain sweeps of the same run."""
+    r = trained_routing_run
+    assert r["routed"]["sweep_ms"] + r["routed"]["sensor_ms"] < r["plain"]["sweep_ms"]
