@@ -30,6 +30,36 @@
 namespace osbli {
 namespace {
 
+// Node mapping of the central kernels: tiles of kBX x kBY columns, each
+// taken plane by plane, numbered with the plane fastest; the linear block id
+// b is remapped to item (b % 8) * per + b / 8, so each of the eight XCDs
+// (one L2 each) walks one contiguous run of items and the blocks it holds at
+// once cover neighbouring planes of the same tile: the z-neighbours of the
+// five-point operators are read through that XCD's L2.
+struct ColTiles {
+    int tx, ty, nz, per, nt;
+};
+
+inline ColTiles col_tiles(const Grid &g) {
+    ColTiles T;
+    T.tx = (int)((g.n[0] + kBX - 1) / kBX);
+    T.ty = (int)((g.n[1] + kBY - 1) / kBY);
+    T.nz = (int)g.n[2];
+    T.nt = T.tx * T.ty * T.nz;
+    T.per = (T.nt + 7) / 8;
+    return T;
+}
+
+__device__ __forceinline__ bool node_of_col_thread(const Grid &g, const ColTiles &T, int64_t (&idx)[3]) {
+    const int L = (int)(blockIdx.x % 8) * T.per + (int)(blockIdx.x / 8);
+    if (L >= T.nt) return false;
+    const int k = L % T.nz, t = L / T.nz;
+    idx[0] = (int64_t)(t % T.tx) * kBX + threadIdx.x;
+    idx[1] = (int64_t)(t / T.tx) * kBY + threadIdx.y;
+    idx[2] = k;
+    return idx[0] < g.n[0] && idx[1] < g.n[1];
+}
+
 // the five-node operator window of line position p: the nodes q0 .. q0 + 4
 // and the row r of the operator (-1: the centred interior / periodic stencil,
 // 0, 1: the closures at the start, 3, 4: those at the end)
@@ -85,7 +115,7 @@ __device__ __forceinline__ void cnode(const double *__restrict__ U, int64_t e, i
     double q[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) q[c] = U[e + c * cs];
-    const double ri = 1.0 / q[0];
+    const double ri = rcp64(q[0]);
     double ke = 0.0;
 #pragma unroll
     for (int m = 0; m < ND; ++m) ke += q[1 + m] * q[1 + m];
@@ -109,7 +139,7 @@ __device__ __forceinline__ void cnode(const double *__restrict__ U, int64_t e, i
 // velocity primitives only (gradient pass)
 template <int ND>
 __device__ __forceinline__ void cvel(const double *__restrict__ U, int64_t e, int64_t cs, double (&u)[ND]) {
-    const double ri = 1.0 / U[e];
+    const double ri = rcp64(U[e]);
 #pragma unroll
     for (int m = 0; m < ND; ++m) u[m] = U[e + (1 + m) * cs] * ri;
 }
@@ -143,9 +173,9 @@ __device__ __forceinline__ void window_int(const Grid &g, const int64_t (&idx)[3
 // pass 1: velocity gradients g_ab = (1/h_b) D_b u_a, stored [(a ND + b)][node]
 template <int ND>
 __global__ void __launch_bounds__(256) k_c_grad(const double *__restrict__ U, double *__restrict__ Gs, Grid g,
-                                                Metrics m) {
+                                                Metrics m, ColTiles T) {
     int64_t idx[3];
-    if (!node_of_plane_thread(g, idx)) return;
+    if (!node_of_col_thread(g, T, idx)) return;
     const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
     const int64_t cs = g.enpts;
 #pragma unroll
@@ -216,10 +246,10 @@ __device__ __forceinline__ void visc_assemble(const VTerms<ND> &t, double (&R)[N
 template <int ND, bool VISC>
 __global__ void __launch_bounds__(256)
 k_c_resid(const double *__restrict__ U, const double *__restrict__ Gs, Grid g, Phys ph, Metrics m,
-          double *__restrict__ Rout) {
+          double *__restrict__ Rout, ColTiles T) {
     constexpr int NC = ND + 2;
     int64_t idx[3];
-    if (!node_of_plane_thread(g, idx)) return;
+    if (!node_of_col_thread(g, T, idx)) return;
     const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
     const int64_t cs = g.enpts;
     double R[NC];
@@ -307,10 +337,11 @@ struct CWork {
 };
 
 template <int ND, bool VISC>
-__global__ void __launch_bounds__(256) k_cb_first(const double *__restrict__ U, CWork W, Grid g, Phys ph, Metrics m) {
+__global__ void __launch_bounds__(256)
+k_cb_first(const double *__restrict__ U, CWork W, Grid g, Phys ph, Metrics m, ColTiles T) {
     constexpr int NC = ND + 2;
     int64_t idx[3];
-    if (!node_of_plane_thread(g, idx)) return;
+    if (!node_of_col_thread(g, T, idx)) return;
     const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
     const int64_t cs = g.enpts;
 #pragma unroll
@@ -341,9 +372,10 @@ __global__ void __launch_bounds__(256) k_cb_first(const double *__restrict__ U, 
 }
 
 template <int ND>
-__global__ void __launch_bounds__(256) k_cb_second(const double *__restrict__ U, CWork W, Grid g, Phys ph, Metrics m) {
+__global__ void __launch_bounds__(256)
+k_cb_second(const double *__restrict__ U, CWork W, Grid g, Phys ph, Metrics m, ColTiles T) {
     int64_t idx[3];
-    if (!node_of_plane_thread(g, idx)) return;
+    if (!node_of_col_thread(g, T, idx)) return;
     const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
     const int64_t cs = g.enpts;
 #pragma unroll
@@ -382,10 +414,10 @@ __global__ void __launch_bounds__(256) k_cb_second(const double *__restrict__ U,
 
 template <int ND, bool VISC>
 __global__ void __launch_bounds__(256)
-k_cb_assemble(const double *__restrict__ U, CWork W, Grid g, Phys ph, double *__restrict__ Rout) {
+k_cb_assemble(const double *__restrict__ U, CWork W, Grid g, Phys ph, double *__restrict__ Rout, ColTiles T) {
     constexpr int NC = ND + 2;
     int64_t idx[3];
-    if (!node_of_plane_thread(g, idx)) return;
+    if (!node_of_col_thread(g, T, idx)) return;
     const int64_t ci = int_index(g, idx[0], idx[1], idx[2]);
     const int64_t e0 = ext_index(g, idx[0], idx[1], idx[2]);
     double R[NC];
@@ -431,10 +463,11 @@ inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 template <int ND, bool VISC>
 hipError_t central_nd(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *Gs, void *work,
                       double *R, hipStream_t s) {
-    const dim3 nb = node_grid(g), bs(kBX, kBY);
+    const ColTiles T = col_tiles(g);
+    const dim3 nb((unsigned)(8 * T.per)), bs(kBX, kBY);
     if (!work) {
-        if (VISC) hipLaunchKernelGGL((k_c_grad<ND>), nb, bs, 0, s, U, Gs, g, m);
-        hipLaunchKernelGGL((k_c_resid<ND, VISC>), nb, bs, 0, s, U, Gs, g, ph, m, R);
+        if (VISC) hipLaunchKernelGGL((k_c_grad<ND>), nb, bs, 0, s, U, Gs, g, m, T);
+        hipLaunchKernelGGL((k_c_resid<ND, VISC>), nb, bs, 0, s, U, Gs, g, ph, m, R, T);
         return hipGetLastError();
     }
     constexpr int NC = ND + 2;
@@ -450,9 +483,9 @@ hipError_t central_nd(const Grid &g, const Phys &ph, const Metrics &m, const dou
     W.X = reinterpret_cast<double *>(w);
     w += al256(a * ND * ND);
     W.Y = reinterpret_cast<double *>(w);
-    hipLaunchKernelGGL((k_cb_first<ND, VISC>), nb, bs, 0, s, U, W, g, ph, m);
-    if (VISC) hipLaunchKernelGGL((k_cb_second<ND>), nb, bs, 0, s, U, W, g, ph, m);
-    hipLaunchKernelGGL((k_cb_assemble<ND, VISC>), nb, bs, 0, s, U, W, g, ph, R);
+    hipLaunchKernelGGL((k_cb_first<ND, VISC>), nb, bs, 0, s, U, W, g, ph, m, T);
+    if (VISC) hipLaunchKernelGGL((k_cb_second<ND>), nb, bs, 0, s, U, W, g, ph, m, T);
+    hipLaunchKernelGGL((k_cb_assemble<ND, VISC>), nb, bs, 0, s, U, W, g, ph, R, T);
     return hipGetLastError();
 }
 
