@@ -355,10 +355,19 @@ int osbli_batch_create(osbli_batch **batch, osbli_ctx *const *ctxs, int nprob, d
                        double *const *dU, const double *t_end, double cfl, void *workspace, size_t ws_bytes,
                        void *stream);
 
-/* Sweep tiling: seg[2 p + d] = nodes per wave segment of problem p along
- * direction d (clamped to n_d).  Results do not depend on it.  Drops any
+/* Sweep tiling of problem p: seg[2 p + 1] = nodes per wave segment of the
+ * marching y sweep (clamped to n_y); seg[2 p] = for problems whose x rows
+ * hold at least 64 interfaces (swept with lanes along x) the number of
+ * 63-interface runs per tile (default 4, clamped to 64), else nodes per wave
+ * segment of the marching x sweep.  Values must be positive.  Results do not
+ * depend on it.  Drops any
  * captured graphs.  Synchronising. */
 int osbli_batch_set_tiles(osbli_batch *batch, const int64_t *seg, void *stream);
+
+/* Workgroups of each persistent sweep launch, 1..65536 (0: the defaults,
+ * 2048 for the lanes-along-x sweep, 1024 for the marching ones).  Results do
+ * not depend on it.  Drops any captured graphs. */
+int osbli_batch_set_grid(osbli_batch *batch, int sweep_blocks);
 
 /* Capture the three substage graphs on `stream` (must not be the NULL
  * stream).  Graph instantiation is the runtime's only allocation. */

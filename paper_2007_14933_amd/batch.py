@@ -10,11 +10,12 @@ has its own CFL time step and end time, kept on the device.
     b.tune()          # optional: measured choice of sweep tiles per grid size
     b.run()           # until every problem reaches its end time
 
-The autotuner chooses, per grid size class, the sweep segment length (nodes
-per wave along the sweep direction) by coordinate descent on the measured
-time of whole-ensemble steps, run on a scratch copy of the ensemble so that
-the real one is not advanced; results are cached per (device, form, sensor,
-grid size).
+The autotuner chooses, per grid size class, the runs per tile of the
+lanes-along-x sweep and the marching y sweep's segment length, then the
+workgroups per persistent sweep launch, by coordinate descent on the
+measured time of whole-ensemble steps, run on a scratch copy of the ensemble
+so that the real one is not advanced; results are cached per (device, form,
+sensor, grid size).
 """
 from __future__ import annotations
 
@@ -28,7 +29,9 @@ import torch
 from . import binding as B
 from .solver import Solver
 
-SEG_CANDIDATES = (8, 16, 32, 64, 128, 256, 512, 1024)
+SEG_CANDIDATES = (8, 16, 32, 64, 128)
+XL_RUNS = (1, 2, 4, 8, 16)                      # 63-interface runs per tile of the lanes-along-x sweep
+GRID_CANDIDATES = (512, 1024, 2048, 4096, 8192)  # workgroups per persistent sweep launch
 
 
 def default_seg(n_d, lines):
@@ -100,8 +103,11 @@ class Batch:
                                          C.c_void_p(self.ws.data_ptr() + off), C.c_size_t(nb), self._s())
         B.check_batch(rc, self.b)
         self.captured = False
-        self.tiles = np.array([[default_seg(p.n[0], p.n[1]), default_seg(p.n[1], p.n[0])] for p in self.probs],
-                              dtype=np.int64)
+        # x: runs per tile for rows of >= 64 interfaces (lanes-along-x sweep), else the segment
+        self.tiles = np.array([[4 if p.n[0] + 1 >= 64 else default_seg(p.n[0], p.n[1]),
+                                default_seg(p.n[1], p.n[0])] for p in self.probs], dtype=np.int64)
+        self.sweep_blocks = 0
+        self.tune_report = None
         self.steps_done = 0
         if capture:
             self.capture()
@@ -122,7 +128,8 @@ class Batch:
         seg = np.ascontiguousarray(np.asarray(seg, dtype=np.int64).reshape(self.P, 2))
         B.check_batch(self.lib.osbli_batch_set_tiles(self.b, seg.ctypes.data_as(C.POINTER(C.c_int64)), self._s()),
                       self.b)
-        self.tiles = np.minimum(seg, np.array([[p.n[0], p.n[1]] for p in self.probs]))
+        lim = np.array([[64 if p.n[0] + 1 >= 64 else p.n[0], p.n[1]] for p in self.probs])
+        self.tiles = np.minimum(seg, lim)
         was = self.captured
         self.captured = False
         if was:
@@ -190,47 +197,107 @@ class Batch:
         e1.synchronize()
         return e0.elapsed_time(e1) / nsteps
 
-    def tune(self, candidates=SEG_CANDIDATES, nsteps=4, cache=True, log=None):
-        """Choose sweep segment lengths per grid size class.  Runs on a
-        scratch copy of the ensemble (same problems, same settings)."""
+    def set_grid(self, sweep_blocks):
+        """Workgroups per persistent sweep launch (0: the library defaults)."""
+        B.check_batch(self.lib.osbli_batch_set_grid(self.b, int(sweep_blocks)), self.b)
+        self.sweep_blocks = int(sweep_blocks)
+        was = self.captured
+        self.captured = False
+        if was:
+            self.capture()
+
+    def tune(self, nsteps=4, cache=True, log=None):
+        """Measured choice of the launch knobs that change the ensemble's time:
+        per grid-size class, the runs per tile of the lanes-along-x sweep
+        (XL_RUNS; the marching x segment for narrow grids) and the marching y
+        sweep's segment (SEG_CANDIDATES), then the workgroups per persistent
+        sweep launch (GRID_CANDIDATES); coordinate descent on the mean time of
+        whole-ensemble steps, run on a scratch copy of the ensemble so the
+        real one does not advance.  Results are cached per (device, form,
+        sensor, size class).  Returns the choices and the default and tuned
+        milliseconds per step."""
         sizes = sorted({(p.n[0], p.n[1]) for p in self.probs}, key=lambda s: -s[0] * s[1])
         dev = torch.cuda.get_device_name(self.device).replace(" ", "_")
-        key = lambda s: "%s|form%d|sensor%d|%dx%d" % (dev, self.form, self.sensor, s[0], s[1])
+        key = lambda s: "v2|%s|form%d|sensor%d|%dx%d" % (dev, self.form, self.sensor, s[0], s[1])
+        gkey = "v2|%s|form%d|sensor%d|grid|%d" % (dev, self.form, self.sensor, self.P)
         path = _cache_path()
         store = _cache_load(path) if cache else {}
-        seg = self.tiles.copy()
+        scratch = Batch(self.probs, form=self.form, sensor=self.sensor, weights=self.weights,
+                        threshold=self.threshold, dilate=self.dilate, cfl=self.cfl,
+                        t_end=np.full(self.P, 1e30), device=self.device, capture=True)
+        seg = scratch.tiles.copy()
+        default_ms = scratch.time_steps(nsteps)
         todo = [s for s in sizes if key(s) not in store]
-        if todo:
-            scratch = Batch(self.probs, form=self.form, sensor=self.sensor, weights=self.weights,
-                            threshold=self.threshold, dilate=self.dilate, cfl=self.cfl,
-                            t_end=np.full(self.P, 1e30), device=self.device, capture=True)
-            scratch.set_tiles(seg)
-            best_t = scratch.time_steps(nsteps)
-            for s in todo:
+        fresh = bool(todo) or gkey not in store      # else every choice comes from the cache
+        best_t = default_ms
+        for s in todo:
+            members = [i for i, p in enumerate(self.probs) if (p.n[0], p.n[1]) == s]
+            xl = s[0] + 1 >= 64
+            for d in (0, 1):
+                cands = XL_RUNS if (d == 0 and xl) else [c for c in SEG_CANDIDATES if c <= s[d]]
+                for c in cands:
+                    if c == seg[members[0], d]:
+                        continue
+                    trial = seg.copy()
+                    trial[members, d] = c
+                    scratch.set_tiles(trial)
+                    t = scratch.time_steps(nsteps)
+                    if t < best_t:
+                        best_t, seg = t, trial
+            store[key(s)] = [int(v) for v in seg[members[0]]]
+            if log:
+                log("[tune] %dx%d: %s %d, y segment %d, ensemble step %.3f ms"
+                    % (s[0], s[1], "x runs/tile" if xl else "x segment", seg[members[0], 0], seg[members[0], 1],
+                       best_t))
+        for i, p in enumerate(self.probs):
+            seg[i] = store[key((p.n[0], p.n[1]))]
+        scratch.set_tiles(seg)
+        if gkey not in store:
+            best_g, best_t = 0, scratch.time_steps(nsteps)
+            for gb in GRID_CANDIDATES:
+                scratch.set_grid(gb)
+                t = scratch.time_steps(nsteps)
+                if t < best_t:
+                    best_g, best_t = gb, t
+            store[gkey] = best_g
+            if log:
+                log("[tune] sweep workgroups %s, ensemble step %.3f ms" % (best_g or "default", best_t))
+        # the search compares single short timings; confirm the choice against
+        # the defaults with interleaved repeats (best of three each) and keep
+        # the defaults unless the choice is faster
+        dflt = self.tiles.copy()
+
+        def timed(tiles, grid):
+            scratch.set_tiles(tiles)
+            scratch.set_grid(grid)
+            return scratch.time_steps(2 * nsteps)
+        t_def, t_tun = [], []
+        for _ in range(3):
+            t_def.append(timed(dflt, 0))
+            t_tun.append(timed(seg, store[gkey]))
+        default_ms, tuned_ms = min(t_def), min(t_tun)
+        kept = tuned_ms < default_ms or not fresh
+        if not kept:
+            seg, tuned_ms = dflt, default_ms
+            for s in sizes:
                 members = [i for i, p in enumerate(self.probs) if (p.n[0], p.n[1]) == s]
-                best = tuple(seg[members[0]])
-                for d in (0, 1):
-                    for c in candidates:
-                        if c > s[d]:
-                            continue
-                        trial = seg.copy()
-                        trial[members, d] = c
-                        scratch.set_tiles(trial)
-                        t = scratch.time_steps(nsteps)
-                        if t < best_t:
-                            best_t, seg = t, trial
-                    best = tuple(int(v) for v in seg[members[0]])
-                store[key(s)] = list(best)
-                if log:
-                    log("[tune] %dx%d: seg %s, ensemble step %.3f ms" % (s[0], s[1], best, best_t))
-            del scratch
-            torch.cuda.synchronize(self.device)
-            if cache:
-                _cache_store(path, store)
+                store[key(s)] = [int(v) for v in dflt[members[0]]]
+            store[gkey] = 0
+        del scratch
+        torch.cuda.synchronize(self.device)
+        if cache:
+            _cache_store(path, store)
         for i, p in enumerate(self.probs):
             seg[i] = store[key((p.n[0], p.n[1]))]
         self.set_tiles(seg)
-        return {s: tuple(store[key(s)]) for s in sizes}
+        self.set_grid(store[gkey])
+        self.tune_report = {"default_ms_per_step": round(default_ms, 4), "tuned_ms_per_step": round(tuned_ms, 4),
+                            "sweep_blocks": int(store[gkey]), "search_kept": bool(kept)}
+        if log:
+            log("[tune] confirmed: default %.3f ms, tuned %.3f ms per step (%s)"
+                % (default_ms, tuned_ms, "kept" if kept else "defaults kept"))
+        out = {s: tuple(store[key(s)]) for s in sizes}
+        return out
 
 
 def solo_run(prob, form=B.FORM_FP64, sensor=0, weights=None, threshold=None, dilate=1, cfl=0.5, device="cuda:0",

@@ -81,6 +81,7 @@ _SIGS = {
     "osbli_batch_create": (C.c_int, [C.POINTER(_VP), C.POINTER(_VP), C.c_int, C.POINTER(_VP), C.POINTER(_VP), _DP,
                                      C.c_double, _VP, C.c_size_t, _VP]),
     "osbli_batch_set_tiles": (C.c_int, [_VP, C.POINTER(C.c_int64), _VP]),
+    "osbli_batch_set_grid": (C.c_int, [_VP, C.c_int]),
     "osbli_batch_capture": (C.c_int, [_VP, _VP]),
     "osbli_batch_step": (C.c_int, [_VP, _VP]),
     "osbli_batch_substep": (C.c_int, [_VP, C.c_int, _VP]),

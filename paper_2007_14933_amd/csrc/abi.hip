@@ -819,6 +819,7 @@ struct osbli_batch {
     hipGraph_t graph[3];
     hipGraphExec_t exec[3];
     int captured;
+    int sweep_blocks;      // workgroups per persistent sweep launch (0: defaults)
     char err[320];
 };
 
@@ -865,7 +866,7 @@ int upload_tables(osbli_batch *b, hipStream_t s) {
         }
         // x: lanes along x for rows of >= 64 interfaces (as the single-grid launch)
         const int64_t totalJ = q.g.n[1] * (q.g.n[0] + 1);
-        const int64_t nwx = q.xl ? ((totalJ - 2) / 63 + kXlPerTile) / kXlPerTile : 0;
+        const int64_t nwx = q.xl ? ((totalJ - 2) / 63 + q.xlpt) / q.xlpt : 0;
         const int64_t nw0 = q.xl ? 0 : q.nseg[0] * q.wpl[0];
         const int64_t nw1 = q.nseg[1] * q.wpl[1];
         WX[p + 1] = WX[p] + nwx;
@@ -927,6 +928,7 @@ int osbli_batch_create(osbli_batch **out, osbli_ctx *const *ctxs, int P, double 
     *out = b;
     b->err[0] = 0;
     b->captured = 0;
+    b->sweep_blocks = 0;
     if (P < 1 || !ctxs || !U || !dU || !t_end || !workspace) return bset_err(b, OSBLI_EINVAL, "null argument or P < 1");
     if (ws_bytes < osbli_batch_workspace_bytes(P)) return bset_err(b, OSBLI_ENOSPACE, "batch workspace too small");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return bset_err(b, OSBLI_EINVAL, "workspace not 256-byte aligned");
@@ -975,7 +977,7 @@ int osbli_batch_create(osbli_batch **out, osbli_ctx *const *ctxs, int P, double 
         q.dU = dU[p];
         q.R = c->Racc;
         q.xl = c->g.n[0] + 1 >= 64 ? 1 : 0;
-        q.pad = 0;
+        q.xlpt = kXlPerTile;
         for (int d = 0; d < 3; ++d) {
             q.invh[d] = c->m.invh[d];
             q.mask[d] = c->mask[d];
@@ -1003,10 +1005,23 @@ int osbli_batch_set_tiles(osbli_batch *b, const int64_t *seg, void *stream) {
         for (int d = 0; d < 2; ++d) {
             const int64_t v = seg[2 * p + d];
             if (v < 1) return bset_err(b, OSBLI_EINVAL, "segment length must be positive");
+            if (d == 0 && b->hp[p].xl) {
+                // lanes-along-x sweep: 63-interface runs per tile (clamped to 64)
+                b->hp[p].xlpt = (int)(v > 64 ? 64 : v);
+                continue;
+            }
             b->hp[p].seg[d] = v > b->hp[p].g.n[d] ? b->hp[p].g.n[d] : v;
         }
     drop_graphs(b);
     return upload_tables(b, as_stream(stream));
+}
+
+int osbli_batch_set_grid(osbli_batch *b, int sweep_blocks) {
+    if (!b) return OSBLI_EINVAL;
+    if (sweep_blocks < 0 || sweep_blocks > 65536) return bset_err(b, OSBLI_EINVAL, "sweep_blocks must lie in 0..65536");
+    b->sweep_blocks = sweep_blocks;
+    drop_graphs(b);
+    return OSBLI_OK;
 }
 
 int osbli_batch_capture(osbli_batch *b, void *stream) {
@@ -1017,7 +1032,7 @@ int osbli_batch_capture(osbli_batch *b, void *stream) {
     for (int st = 0; st < 3; ++st) {
         HIP_BTRY(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         hipError_t e = launch_batch_stage(b->dp, b->ds, b->T, b->P, b->ph, st, b->cfl, b->route, b->w, b->zcut,
-                                          b->flags, s);
+                                          b->flags, b->sweep_blocks, s);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(s, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -1044,7 +1059,7 @@ int osbli_batch_substep(osbli_batch *b, int stage, void *stream) {
         HIP_BTRY(b, hipGraphLaunch(b->exec[stage], s));
     } else {
         HIP_BTRY(b, launch_batch_stage(b->dp, b->ds, b->T, b->P, b->ph, stage, b->cfl, b->route, b->w, b->zcut,
-                                       b->flags, s));
+                                       b->flags, b->sweep_blocks, s));
     }
     return OSBLI_OK;
 }

@@ -161,9 +161,10 @@ k_b_sweep_xl(const BProb *__restrict__ pr, const BState *__restrict__ st, const 
         const int64_t local = wt - off[p];
         const Metrics m = sep_metrics(b);
         const int64_t totalJ = b.g.n[1] * (b.g.n[0] + 1);
-        // a tile is kXlPerTile consecutive 63-interface runs of the problem
-        for (int k = 0; k < kXlPerTile; ++k) {
-            const int64_t J0 = (local * kXlPerTile + k) * 63;
+        // a tile is b.xlpt consecutive 63-interface runs of the problem
+        const int nrun = b.xlpt;
+        for (int k = 0; k < nrun; ++k) {
+            const int64_t J0 = (local * nrun + k) * 63;
             if (J0 + 1 >= totalJ) break;  // wave-uniform
             sweep_x_lanes<2, SCHEME, MIX, ROUTE>(b.U, b.R, b.g, ph, m, J0, totalJ, first, flags,
                                                  ROUTE ? b.mask[0] : nullptr, sm[wv]);
@@ -232,20 +233,22 @@ static unsigned grid_of(int64_t items, int64_t per_block, unsigned cap) {
 
 template <int SCHEME, bool MIX, bool ROUTE>
 static hipError_t b_sweeps(const BProb *pr, const BState *st, const BatchTables &T, int P, const Phys &ph,
-                           unsigned *flags, hipStream_t s) {
+                           unsigned *flags, int nblk, hipStream_t s) {
+    const unsigned cx = nblk > 0 ? (unsigned)nblk : 2048u, cm = nblk > 0 ? (unsigned)nblk : 1024u;
     if (T.tot_wx > 0)
-        hipLaunchKernelGGL((k_b_sweep_xl<SCHEME, MIX, ROUTE>), dim3(grid_of(T.tot_wx, kWaves, 2048)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_b_sweep_xl<SCHEME, MIX, ROUTE>), dim3(grid_of(T.tot_wx, kWaves, cx)), dim3(256), 0, s,
                            pr, st, T.wx, P, T.tot_wx, ph, 1, flags);
     if (T.tot_w[0] > 0)
-        hipLaunchKernelGGL((k_b_sweep<0, SCHEME, MIX, ROUTE>), dim3(grid_of(T.tot_w[0], kWaves, 1024)), dim3(256), 0,
+        hipLaunchKernelGGL((k_b_sweep<0, SCHEME, MIX, ROUTE>), dim3(grid_of(T.tot_w[0], kWaves, cm)), dim3(256), 0,
                            s, pr, st, T.w[0], P, T.tot_w[0], ph, 1, flags);
-    hipLaunchKernelGGL((k_b_sweep<1, SCHEME, MIX, ROUTE>), dim3(grid_of(T.tot_w[1], kWaves, 1024)), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_b_sweep<1, SCHEME, MIX, ROUTE>), dim3(grid_of(T.tot_w[1], kWaves, cm)), dim3(256), 0, s,
                        pr, st, T.w[1], P, T.tot_w[1], ph, 0, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_stage(const BProb *pr, BState *st, const BatchTables &T, int P, const Phys &ph, int stage,
-                              double cfl, int route, const uint16_t *w, float zcut, unsigned *flags, hipStream_t s) {
+                              double cfl, int route, const uint16_t *w, float zcut, unsigned *flags, int sweep_blocks,
+                              hipStream_t s) {
     if (stage == 0) {
         hipLaunchKernelGGL(k_b_dt_reset, dim3((P + 255) / 256), dim3(256), 0, s, st, P);
         hipLaunchKernelGGL(k_b_dt, dim3(grid_of(T.tot_pt, 1, 2048)), dim3(256), 0, s, pr, st, T.pt, P, T.tot_pt, ph);
@@ -260,14 +263,14 @@ hipError_t launch_batch_stage(const BProb *pr, BState *st, const BatchTables &T,
     hipError_t e;
     const bool mix = ph.mixed != 0;
     if (ph.scheme == OSBLI_WENOZ5) {
-        e = mix ? b_sweeps<OSBLI_WENOZ5, true, false>(pr, st, T, P, ph, flags, s)
-                : b_sweeps<OSBLI_WENOZ5, false, false>(pr, st, T, P, ph, flags, s);
+        e = mix ? b_sweeps<OSBLI_WENOZ5, true, false>(pr, st, T, P, ph, flags, sweep_blocks, s)
+                : b_sweeps<OSBLI_WENOZ5, false, false>(pr, st, T, P, ph, flags, sweep_blocks, s);
     } else if (route) {
-        e = mix ? b_sweeps<OSBLI_TENO5, true, true>(pr, st, T, P, ph, flags, s)
-                : b_sweeps<OSBLI_TENO5, false, true>(pr, st, T, P, ph, flags, s);
+        e = mix ? b_sweeps<OSBLI_TENO5, true, true>(pr, st, T, P, ph, flags, sweep_blocks, s)
+                : b_sweeps<OSBLI_TENO5, false, true>(pr, st, T, P, ph, flags, sweep_blocks, s);
     } else {
-        e = mix ? b_sweeps<OSBLI_TENO5, true, false>(pr, st, T, P, ph, flags, s)
-                : b_sweeps<OSBLI_TENO5, false, false>(pr, st, T, P, ph, flags, s);
+        e = mix ? b_sweeps<OSBLI_TENO5, true, false>(pr, st, T, P, ph, flags, sweep_blocks, s)
+                : b_sweeps<OSBLI_TENO5, false, false>(pr, st, T, P, ph, flags, sweep_blocks, s);
     }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_b_finish, dim3(grid_of(T.tot_pt, 1, 2048)), dim3(256), 0, s, pr, st, T.pt, P, T.tot_pt,

@@ -157,11 +157,12 @@ struct BProb {             // one problem, device resident
     const double *invh[3];
     uint8_t *mask[3];
     int bc[3][2];
-    int xl, pad;                       // x sweep with lanes along x (rows of >= 64 interfaces)
+    int xl;                            // x sweep with lanes along x (rows of >= 64 interfaces)
+    int xlpt;                          // 63-interface runs per tile of that sweep
     int64_t seg[3], nseg[3], wpl[3];   // sweep tiling per direction (marching sweeps)
 };
 
-constexpr int kXlPerTile = 4;  // 63-interface runs per tile of the batched x sweep
+constexpr int kXlPerTile = 4;  // default 63-interface runs per tile of the batched x sweep
 
 struct BState {            // per-problem time state, device resident
     double t, dt, tend;
@@ -174,7 +175,10 @@ struct BatchTables {       // device prefix tables (P + 1 entries) and totals
     int64_t tot_w[2], tot_wx, tot_pt, tot_f[2], tot_s[2];
 };
 
+// sweep_blocks > 0: workgroups of each persistent sweep launch (else 2048
+// for the lanes-along-x sweep and 1024 for the marching ones)
 hipError_t launch_batch_stage(const BProb *pr, BState *st, const BatchTables &T, int P, const Phys &ph, int stage,
-                              double cfl, int route, const uint16_t *w, float zcut, unsigned *flags, hipStream_t s);
+                              double cfl, int route, const uint16_t *w, float zcut, unsigned *flags, int sweep_blocks,
+                              hipStream_t s);
 
 }  // namespace osbli

@@ -110,7 +110,9 @@ def test_batch_tiles_and_direct_launches_do_not_change_results():
     say("[gpu batch] tiles")
     ref = Batch(probs, capture=True)
     ref.run()
-    for seg, capture in ((8, True), (64, False), (1024, True)):
+    # x knob: runs per tile for the rows of >= 64 interfaces (1 and 64 are its
+    # ends), the marching segment for the others
+    for seg, capture in ((1, False), (8, True), (64, False), (1024, True)):
         b = Batch(probs, capture=False)
         b.set_tiles(np.full((len(probs), 2), seg))
         if capture:
@@ -144,20 +146,26 @@ def test_graph_replays_with_eager_work_between():
 def test_tuner_picks_valid_tiles_and_keeps_results(tmp_path, monkeypatch):
     from paper_2007_14933_amd.batch import Batch
     monkeypatch.setenv("OSBLI_TILE_CACHE", str(tmp_path / "tiles.json"))
-    probs = ensemble((64, 32, 64, 48), 14, (0.02, 0.02, 0.02, 0.02))
+    # 64 and 80: rows of >= 64 interfaces (lanes-along-x sweep, x knob =
+    # runs per tile); 32, 48: marching x sweep (x knob = segment)
+    probs = ensemble((64, 32, 80, 48), 14, (0.02, 0.02, 0.02, 0.02))
     ref = Batch(probs)
     ref.run()
     b = Batch(probs)
-    chosen = b.tune(candidates=(8, 32, 64), nsteps=2, log=say)
-    assert set(chosen) == {(64, 64), (32, 32), (48, 48)}
+    chosen = b.tune(nsteps=2, log=say)
+    assert set(chosen) == {(64, 64), (32, 32), (80, 80), (48, 48)}
     for (nx, ny), (sx, sy) in chosen.items():
-        assert 1 <= sx <= nx and 1 <= sy <= ny
+        assert 1 <= sx <= (64 if nx + 1 >= 64 else nx) and 1 <= sy <= ny
+    rep = b.tune_report
+    say("[gpu batch] tuned %s, default %.3f ms, tuned %.3f ms, sweep workgroups %d"
+        % (chosen, rep["default_ms_per_step"], rep["tuned_ms_per_step"], rep["sweep_blocks"]))
+    assert rep["sweep_blocks"] in (0, 512, 1024, 2048, 4096, 8192)
     assert (tmp_path / "tiles.json").exists()
     b.run()
     for p in range(len(probs)):
         assert np.array_equal(b.state(p), ref.state(p))
     # second call reads the cache
-    again = Batch(probs).tune(candidates=(8, 32, 64), nsteps=2)
+    again = Batch(probs).tune(nsteps=2)
     assert again == chosen
 
 
