@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble line")
     ap.add_argument("--no-central", action="store_true", help="skip the central-path (StoreSome) line")
     ap.add_argument("--central-steps", type=int, default=20)
+    ap.add_argument("--no-schemes", action="store_true", help="skip the TENO6 / WENO-JS5 / WENO-3Z line")
+    ap.add_argument("--scheme-steps", type=int, default=10)
     ap.add_argument("--batch-steps", type=int, default=30)
     ap.add_argument("--batch-full", action="store_true",
                     help="also run both batched forms to t = 0.25 and report their density difference")
@@ -207,8 +209,8 @@ def cpu_table():
 
 
 def timed_run(prob, form, steps, warmup, cfl, sensor=0, bits=None, thr=None, keep_rho=False, dilate=1):
-    """W warm-up steps, then K timed steps (dt reduction + 3 substages + BCs
-    each) with the library's per-kernel event timing on."""
+    """W warm-up steps, then K timed steps (dt reduction + the RK substages +
+    BCs each) with the library's per-kernel event timing on."""
     import torch
     from paper_2007_14933_amd.solver import Solver
     s = Solver(prob, form=form, sensor=sensor)
@@ -404,6 +406,25 @@ def sensor_form(cfl):
     return res
 
 
+def schemes_form(steps, warmup, cfl, n=256):
+    """The further schemes on the headline TGV n^3 (viscous, FP64): TENO6 with
+    the SSP RK3 (the paper's production configuration), WENO-JS5 with the
+    five-stage RK4, WENO-3Z with RK3; same timing as the headline line."""
+    from paper_2007_14933_amd import inputs
+    out = {}
+    for name, kw in (("teno6_ssp_rk3", dict(scheme=inputs.TENO6, rk=inputs.RK3_SSP)),
+                     ("wenojs5_rk4", dict(scheme=inputs.WENOJS5, rk=inputs.RK4, eps=1e-6)),
+                     ("wenoz3_rk3", dict(scheme=inputs.WENOZ3))):
+        prob = inputs.tgv(n).with_(**kw)
+        nst = inputs.rk_stages(prob.rk)
+        wall, _, prof, _ = timed_run(prob, 0, steps, warmup, cfl)
+        sw = sum(prof["sweep_%s" % a][1] for a in "xyz") / max(1, sum(prof["sweep_%s" % a][0] for a in "xyz"))
+        out[name] = {"value": round(n ** 3 * nst * steps / wall / 1e6, 3), "ms_per_step": round(wall * 1e3 / steps, 4),
+                     "substages_per_step": nst, "sweep_avg_ms": round(sw, 4)}
+    out["workload"] = "TGV %d^3 periodic, Re=1600, M=0.1, viscous, CFL 0.5, FP64; %d timed steps" % (n, steps)
+    return out
+
+
 def central_form(steps, warmup, cfl, sizes=(192, 256)):
     """The fourth-order central path on the viscous TGV (the paper's central
     benchmark; 192^3 is its one-GPU size): StoreSome (velocity gradients
@@ -469,11 +490,11 @@ def batch_form(steps, warmup, cfl, tune, full):
     forms = [("plain_fp64", 0, 0)] + ([("fp32_learned", 1, 1)] if have_w else [])
     bits, thr = SN.load() if have_w else (None, None)
     dil = SN.load_dilate() if have_w else 1
-    finals = {}
+    finals, snaps = {}, {}
     for name, form, sensor in forms:
         kw = dict(form=form, sensor=sensor, weights=bits, threshold=thr, cfl=cfl, dilate=dil)
         b = Batch(probs, **kw)
-        tiles = b.tune(candidates=(16, 32, 64, 128, 256), nsteps=3) if tune else None
+        tiles = b.tune(nsteps=3) if tune else None
         b.step(warmup)
         b.stream.synchronize()
         _, act, _ = b.status()
@@ -491,6 +512,16 @@ def batch_form(steps, warmup, cfl, tune, full):
              "tiles_tuned": bool(tune)}
         if tiles:
             r["tiles"] = {"%dx%d" % k: list(v) for k, v in sorted(tiles.items())}
+            r["tiles_note"] = ("per size class: [runs per tile of the lanes-along-x sweep, y segment]; "
+                               "sweep workgroups %d (0 = defaults)" % b.tune_report["sweep_blocks"])
+            r["tuned_vs_default"] = {"default_ms_per_step": b.tune_report["default_ms_per_step"],
+                                     "tuned_ms_per_step": b.tune_report["tuned_ms_per_step"],
+                                     "ratio": round(b.tune_report["default_ms_per_step"]
+                                                    / b.tune_report["tuned_ms_per_step"], 3)}
+        # both forms start from the same states and advance the same number of
+        # ensemble steps: their densities are compared after them (the whole
+        # run to t = 0.25 with --batch-full)
+        snaps[name] = [b.interior(p)[0] for p in range(len(probs))]
         if full:
             n = b.run()
             b.check()
@@ -501,6 +532,11 @@ def batch_form(steps, warmup, cfl, tune, full):
         torch.cuda.empty_cache()
     if "fp32_learned" in out:
         out["fp32_learned"]["speedup_vs_plain"] = round(out["fp32_learned"]["value"] / out["plain_fp64"]["value"], 3)
+        errs = [float(np.abs(a - b).mean() / np.abs(b).mean()) for a, b in zip(snaps["fp32_learned"],
+                                                                                 snaps["plain_fp64"])]
+        out["fp32_learned"]["rel_L1_rho_vs_plain_after_%d_steps" % (steps + warmup)] = {
+            "median": float("%.3e" % np.median(errs)), "max": float("%.3e" % max(errs)),
+            "meets_1e-4": bool(max(errs) <= 1e-4)}
     if full and len(finals) == 2:
         errs = [float(np.abs(a - b).mean() / np.abs(b).mean()) for a, b in zip(finals["fp32_learned"],
                                                                                  finals["plain_fp64"])]
@@ -602,6 +638,9 @@ def main():
         out["forms"]["learned_sensor"] = sensor_form(args.cfl)
         log("wall flow 512x256x256: plain and precision form")
         out["forms"]["wall_precision"] = wall_precision(args.cfl)
+    if not args.no_schemes:
+        log("further schemes on TGV")
+        out["schemes"] = schemes_form(args.scheme_steps, args.warmup, args.cfl, n)
     if not args.no_central:
         log("central path: StoreSome against store-all")
         out["central"] = central_form(args.central_steps, args.warmup, args.cfl)
