@@ -121,13 +121,14 @@ def sweep_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel of known
-    size), or None when the sweep sources changed since it was taken."""
+def sweep_profile():
+    """Per-launch figures of the sweeps from the committed rocprofv3 counter
+    summary: HBM bytes (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel of
+    known size) and executed FP64 flops (SQ_INSTS_VALU_FLOPS_FP64), or {}
+    when the sweep sources changed since the counters were taken."""
     path = os.path.join(ROOT, TRAFFIC_PROFILE)
     if not os.path.exists(path):
-        return None
+        return {}
     vals = {}
     with open(path) as f:
         for line in f:
@@ -135,11 +136,14 @@ def measured_traffic():
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("source_hash") != sweep_source_hash():
-        return None
-    try:
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for key in ("traffic_bytes_per_launch", "executed_fp64_flops_per_launch"):
+        try:
+            out[key] = float(vals[key])
+        except (KeyError, ValueError):
+            pass
+    return out
 
 
 def copy_ceiling(nbytes=1 << 30, reps=5):
@@ -588,14 +592,22 @@ def main():
     avg_ms = sweep_ms / max(1, sweep_cnt)
     achieved = fl_launch / (avg_ms * 1e-3) / 1e12
     peak = cost.PEAK_FP64_VALU_TFLOPS
-    traffic = measured_traffic()
+    sp = sweep_profile()
+    traffic = sp.get("traffic_bytes_per_launch")
+    executed = sp.get("executed_fp64_flops_per_launch")
     sweep_alg_bytes = npts * sum(cost.sweep_bytes_per_point(3, d == 0) for d in range(3)) / 3.0
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "traffic_vs_algorithmic": (round(traffic / sweep_alg_bytes, 3) if traffic else None),
                 "algorithmic_bytes_per_launch": sweep_alg_bytes,
                 "kernel": "k_sweep<3,d,TENO5> (average over x, y, z)", "avg_ms": round(avg_ms, 4),
-                "flops_per_launch": fl_launch}
+                "flops_per_launch": fl_launch,
+                "flops_model": ("nominal: the full TENO5 characteristic flux, weights at every reconstruction "
+                                "(%d flops per interface); the kernel skips the weights where a bound proves no "
+                                "stencil is cut" % fl_if),
+                "executed_fp64_flops_per_launch": executed,
+                "executed_achieved": (round(executed / (avg_ms * 1e-3) / 1e12, 3) if executed else None),
+                "executed_frac": (round(executed / (avg_ms * 1e-3) / 1e12 / peak, 4) if executed else None)}
     breakdown = {k: {"launch_groups": c, "avg_ms": round(ms / c, 4) if c else 0.0} for k, (c, ms) in prof.items()}
 
     out = {

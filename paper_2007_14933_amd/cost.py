@@ -1,9 +1,13 @@
 """Algorithmic operation and byte counts of the hot path, used to place the
 measured kernels on their rooflines.
 
-Flops are counted on the characteristic interface flux as the sweep kernel
-evaluates it (an FMA counts 2, add / mul / div / sqrt / max count 1, abs and
-compares 0), per interface of one direction:
+Flops are the nominal count of a direct evaluation of the characteristic
+interface flux (an FMA counts 2, add / mul / div / sqrt / max count 1, abs and
+compares 0), per interface of one direction.  The kernels execute fewer where
+an exact shortcut applies (TENO weights skipped when a bound proves that no
+stencil is cut, the LLF halving folded into the projections), so a rate from
+this count is an effective rate; the executed FP64 flops measured by the
+hardware counters are reported next to it.
 
   per-point primitives (1/rho, |m|^2, p, a), amortised to one point  8 + 2 nd
   averaged (Roe) state, a, 1/a, b = (gamma-1)/a^2                   26 + 8 nt

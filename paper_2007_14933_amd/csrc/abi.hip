@@ -230,6 +230,17 @@ Phys make_phys(const osbli_params *p) {
     ph.Ts = p->Ts_over_Tref;
     ph.CT = p->teno_CT;
     ph.eps = p->eps;
+    // With x_r = tau/(beta_r + eps) <= X for each of the K stencils, every
+    // gamma_r = (1 + x_r)^6 >= 1 while C_T sum(gamma) <= K C_T (1 + X)^6;
+    // X = (2 K C_T)^(-1/6) - 1 makes that 1/2, so no stencil can be cut (the
+    // factor 2 covers the rounding of the kernels' evaluation of x_r).
+    {
+        const int K = p->scheme == OSBLI_TENO6 ? 4 : 3;
+        const double q = 2.0 * K * p->teno_CT;
+        ph.teno_fast = (p->scheme == OSBLI_TENO5 || p->scheme == OSBLI_TENO6) && q > 0.0 && q < 1.0
+                           ? pow(q, -1.0 / 6.0) - 1.0
+                           : 0.0;
+    }
     ph.viscous = p->Re > 0.0;
     ph.mu_re = ph.viscous ? 1.0 / p->Re : 0.0;
     ph.kheat = ph.viscous ? 1.0 / ((p->gamma - 1.0) * ph.M2 * p->Pr * p->Re) : 0.0;

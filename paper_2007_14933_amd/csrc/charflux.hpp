@@ -52,27 +52,38 @@ struct R5 {
     double q0, q1, q2, tau, e0, e1, e2;
 };
 
-__device__ __forceinline__ R5 recon5_ind(double fm2, double fm1, double f0, double fp1, double fp2, double eps) {
+__device__ __forceinline__ R5 recon5_ind(double fm2, double fm1, double f0, double fp1, double fp2, double eps4) {
+    // from the first differences d1..d4 of f_{i-2..i+2}: each candidate is
+    // f_i plus two differences; the indicators are taken times 4,
+    // 4 beta_r = (13/3) s_r^2 + t_r^2 (s_r the second difference, t_r the
+    // one-sided or central first-difference combination of stencil r), with
+    // eps4 = 4 eps, which leaves every ratio tau / (beta_r + eps) unchanged
+    const double d1 = fm1 - fm2, d2 = f0 - fm1, d3 = fp1 - f0, d4 = fp2 - fp1;
     R5 r;
-    r.q0 = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
-    r.q1 = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
-    r.q2 = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
-    double s, t;
-    s = f0 - 2.0 * fp1 + fp2;
-    t = 3.0 * f0 - 4.0 * fp1 + fp2;
-    const double b0 = (13.0 / 12.0) * s * s + 0.25 * t * t;
-    s = fm1 - 2.0 * f0 + fp1;
-    t = fm1 - fp1;
-    const double b1 = (13.0 / 12.0) * s * s + 0.25 * t * t;
-    s = fm2 - 2.0 * fm1 + f0;
-    t = fm2 - 4.0 * fm1 + 3.0 * f0;
-    const double b2 = (13.0 / 12.0) * s * s + 0.25 * t * t;
+    r.q0 = f0 + (2.0 / 3.0) * d3 - (1.0 / 6.0) * d4;
+    r.q1 = f0 + (1.0 / 6.0) * d2 + (1.0 / 3.0) * d3;
+    r.q2 = f0 - (1.0 / 3.0) * d1 + (5.0 / 6.0) * d2;
+    const double s0 = d4 - d3, s1 = d3 - d2, s2 = d2 - d1;
+    const double t0 = d4 - 3.0 * d3, t1 = d2 + d3, t2 = 3.0 * d2 - d1;
+    const double b0 = ((13.0 / 3.0) * s0) * s0 + t0 * t0;
+    const double b1 = ((13.0 / 3.0) * s1) * s1 + t1 * t1;
+    const double b2 = ((13.0 / 3.0) * s2) * s2 + t2 * t2;
     r.tau = fabs(b0 - b2);
-    r.e0 = b0 + eps;
-    r.e1 = b1 + eps;
-    r.e2 = b2 + eps;
+    r.e0 = b0 + eps4;
+    r.e1 = b1 + eps4;
+    r.e2 = b2 + eps4;
     return r;
 }
+
+// TENO's cut test decided by a bound: tau < X min_r(beta_r + eps) with X =
+// ph.teno_fast proves that no stencil is cut (the host derives X from C_T),
+// so the value is the linear fifth-order one and the weights, with their
+// division, are not evaluated.  Exact: the general path would keep all
+// three stencils for these data too.
+__device__ __forceinline__ bool teno5_all_kept(const R5 &r, double X) {
+    return r.tau < X * fmin(fmin(r.e0, r.e1), r.e2);
+}
+__device__ __forceinline__ double lin5(const R5 &r) { return 0.3 * r.q0 + 0.6 * r.q1 + 0.1 * r.q2; }
 
 template <int SCHEME>
 __device__ __forceinline__ double recon5_fin(const R5 &r, double tinv, double CT, bool *kept) {
@@ -113,7 +124,7 @@ __device__ __forceinline__ double recon5_fin(const R5 &r, double tinv, double CT
 // when every stencil is kept).  The four ratios tau/(beta_r + eps) share
 // one division: x_r = tau prod_{s != r}(beta_s + eps) / prod_s(beta_s + eps).
 __device__ __forceinline__ double recon6_teno(double fm2, double fm1, double f0, double fp1, double fp2, double fp3,
-                                              double CT, double eps, bool *kept) {
+                                              double CT, double eps, double X, bool *kept) {
     const double q0 = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
     const double q1 = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
     const double q2 = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
@@ -134,6 +145,8 @@ __device__ __forceinline__ double recon6_teno(double fm2, double fm1, double f0,
     const double b3 = (1.0 / 36.0) * a * a + (13.0 / 12.0) * b * b + (781.0 / 720.0) * c * c;
     const double tau = fabs(b3 - (b0 + b2 + 4.0 * b1) * (1.0 / 6.0));
     const double e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps, e3 = b3 + eps;
+    // cut test decided by the bound (as for TENO5): no stencil cut
+    if (tau < X * fmin(fmin(e0, e1), fmin(e2, e3))) return 0.3 * q0 + 0.45 * q1 + 0.05 * q2 + 0.2 * q3;
     const double e01 = e0 * e1, e23 = e2 * e3;
     const double tq = tau * rcp64(e01 * e23);
     double c0 = 1.0 + tq * (e1 * e23), c1 = 1.0 + tq * (e0 * e23);
@@ -157,7 +170,7 @@ __device__ __forceinline__ double recon6_teno(double fm2, double fm1, double f0,
 // prod_s (beta_s + eps)^2, so omega_r = d_r P_r / sum_k d_k P_k with
 // P_r = prod_{s != r} (beta_s + eps)^2 and one division per reconstruction.
 __device__ __forceinline__ double recon5_js(double fm2, double fm1, double f0, double fp1, double fp2, double eps) {
-    const R5 r = recon5_ind(fm2, fm1, f0, fp1, fp2, eps);
+    const R5 r = recon5_ind(fm2, fm1, f0, fp1, fp2, 4.0 * eps);
     const double s0 = r.e0 * r.e0, s1 = r.e1 * r.e1, s2 = r.e2 * r.e2;
     const double a0 = 0.3 * (s1 * s2), a1 = 0.6 * (s0 * s2), a2 = 0.1 * (s0 * s1);
     return (a0 * r.q0 + a1 * r.q1 + a2 * r.q2) * rcp64(a0 + a1 + a2);
@@ -183,7 +196,8 @@ __device__ __forceinline__ double recon3_z(double fm1, double f0, double fp1, do
 // LLF split of one characteristic field over the six points and the two
 // reconstructions: ghat = recon+(g+_{i-2..i+2}) + recon-(g-_{i+3..i-1})
 // (TENO6: recon+(g+_{i-2..i+3}) + recon-(g-_{i+3..i-2}); WENO-3Z:
-// recon+(g+_{i-1..i+1}) + recon-(g-_{i+2..i})).
+// recon+(g+_{i-1..i+1}) + recon-(g-_{i+2..i})).  Takes V, gh = g/2 and
+// ha = alpha/2, so g+- = (g +- alpha V)/2 = gh +- ha V.
 // SHARED: one division serves both sides: with D+- = prod_r(beta_r+eps),
 // tau+/D+ = tau+ D- / (D+ D-) and likewise for the other side (D+ D- >=
 // eps^6, which the accepted range of eps keeps a normal number).  This
@@ -191,34 +205,41 @@ __device__ __forceinline__ double recon3_z(double fm1, double f0, double fp1, do
 // at once, which the marching sweeps can afford and the lane-per-interface
 // sweep cannot (it spills), so that one divides per side.
 template <int SCHEME, bool SHARED>
-__device__ __forceinline__ double split_recon(const double (&V)[6], const double (&g)[6], double alpha,
+__device__ __forceinline__ double split_recon(const double (&V)[6], const double (&gh)[6], double ha,
                                               const Phys &ph, bool *kept = nullptr) {
     double gp[6], gm[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        gp[k] = 0.5 * (g[k] + alpha * V[k]);
-        gm[k] = 0.5 * (g[k] - alpha * V[k]);
+        gp[k] = gh[k] + ha * V[k];
+        gm[k] = gh[k] - ha * V[k];
     }
     if constexpr (SCHEME == OSBLI_TENO6) {
-        return recon6_teno(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], ph.CT, ph.eps, kept) +
-               recon6_teno(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0], ph.CT, ph.eps, kept);
+        return recon6_teno(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], ph.CT, ph.eps, ph.teno_fast, kept) +
+               recon6_teno(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0], ph.CT, ph.eps, ph.teno_fast, kept);
     } else if constexpr (SCHEME == OSBLI_WENOJS5) {
         return recon5_js(gp[0], gp[1], gp[2], gp[3], gp[4], ph.eps) +
                recon5_js(gm[5], gm[4], gm[3], gm[2], gm[1], ph.eps);
     } else if constexpr (SCHEME == OSBLI_WENOZ3) {
         return recon3_z(gp[1], gp[2], gp[3], ph.eps) + recon3_z(gm[4], gm[3], gm[2], ph.eps);
     } else if (SHARED) {
-        const R5 a = recon5_ind(gp[0], gp[1], gp[2], gp[3], gp[4], ph.eps);
-        const R5 b = recon5_ind(gm[5], gm[4], gm[3], gm[2], gm[1], ph.eps);
+        const double eps4 = 4.0 * ph.eps;
+        const R5 a = recon5_ind(gp[0], gp[1], gp[2], gp[3], gp[4], eps4);
+        const R5 b = recon5_ind(gm[5], gm[4], gm[3], gm[2], gm[1], eps4);
+        if (SCHEME == OSBLI_TENO5 && teno5_all_kept(a, ph.teno_fast) && teno5_all_kept(b, ph.teno_fast))
+            return lin5(a) + lin5(b);
         const double da = (a.e0 * a.e1) * a.e2, db = (b.e0 * b.e1) * b.e2;
         const double inv = rcp64(da * db);
         return recon5_fin<SCHEME>(a, (a.tau * db) * inv, ph.CT, kept) +
                recon5_fin<SCHEME>(b, (b.tau * da) * inv, ph.CT, kept);
     } else {
-        const R5 a = recon5_ind(gp[0], gp[1], gp[2], gp[3], gp[4], ph.eps);
-        const double ha = recon5_fin<SCHEME>(a, a.tau * rcp64((a.e0 * a.e1) * a.e2), ph.CT, kept);
-        const R5 b = recon5_ind(gm[5], gm[4], gm[3], gm[2], gm[1], ph.eps);
-        return ha + recon5_fin<SCHEME>(b, b.tau * rcp64((b.e0 * b.e1) * b.e2), ph.CT, kept);
+        const double eps4 = 4.0 * ph.eps;
+        const R5 a = recon5_ind(gp[0], gp[1], gp[2], gp[3], gp[4], eps4);
+        double ha5;
+        if (SCHEME == OSBLI_TENO5 && teno5_all_kept(a, ph.teno_fast)) ha5 = lin5(a);
+        else ha5 = recon5_fin<SCHEME>(a, a.tau * rcp64((a.e0 * a.e1) * a.e2), ph.CT, kept);
+        const R5 b = recon5_ind(gm[5], gm[4], gm[3], gm[2], gm[1], eps4);
+        if (SCHEME == OSBLI_TENO5 && teno5_all_kept(b, ph.teno_fast)) return ha5 + lin5(b);
+        return ha5 + recon5_fin<SCHEME>(b, b.tau * rcp64((b.e0 * b.e1) * b.e2), ph.CT, kept);
     }
 }
 
@@ -247,19 +268,22 @@ __device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph,
     const double ah = sqrt64(ph.gm1 * (Hh - K));
     const double ia = rcp64(ah);
     const double b = ph.gm1 * ia * ia;
-
-    double unk[6], A[6], B[6], am[6], ap[6], a0 = 0.0;
+    // Every field is split as g+- = gh +- (alpha/2) V with gh = g/2, built
+    // directly from hu = u_n/2 and the halved combinations A, B below, so no
+    // product is scaled by 1/2 afterwards (powers of two: exact).
+    const double hb = 0.5 * b, hia = 0.5 * ia;
+    double hu[6], A[6], B[6], am[6], ap[6], a0 = 0.0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        unk[k] = P[k].mn * P[k].ri;
+        hu[k] = P[k].mn * (0.5 * P[k].ri);
         double um = un * P[k].mn;
 #pragma unroll
         for (int s = 0; s < NT; ++s) um += ut[s] * P[k].mt[s];
-        A[k] = b * (K * P[k].r - um + P[k].E);
-        B[k] = (un * P[k].r - P[k].mn) * ia;
-        am[k] = fabs(unk[k] - P[k].a);
-        ap[k] = fabs(unk[k] + P[k].a);
-        a0 = fmax(a0, fabs(unk[k]));
+        A[k] = hb * (K * P[k].r - um + P[k].E);
+        B[k] = (un * P[k].r - P[k].mn) * hia;
+        am[k] = fabs(2.0 * hu[k] - P[k].a);
+        ap[k] = fabs(2.0 * hu[k] + P[k].a);
+        a0 = fmax(a0, fabs(hu[k]));
     }
     double aminus = am[0], aplus = ap[0];
 #pragma unroll
@@ -267,38 +291,39 @@ __device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph,
         aminus = fmax(aminus, am[k]);
         aplus = fmax(aplus, ap[k]);
     }
-    double V[6], g[6];
-    // field u_n - a
+    double V[6], gh[6];
+    // field u_n - a: V = (A + B)|full / 2, g = u_n V + p (b u_n - (b un + 1/a)) / 2
+    const double cm = 0.25 * (b * un + ia), cp = 0.25 * (b * un - ia), hbun = hb * un;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        V[k] = 0.5 * (A[k] + B[k]);
-        g[k] = unk[k] * V[k] + P[k].p * (0.5 * b * unk[k] - 0.5 * (b * un + ia));
+        V[k] = A[k] + B[k];
+        gh[k] = hu[k] * V[k] + P[k].p * (hb * hu[k] - cm);
     }
-    const double h0 = split_recon<SCHEME, SHARED>(V, g, aminus, ph, kept);
+    const double h0 = split_recon<SCHEME, SHARED>(V, gh, 0.5 * aminus, ph, kept);
     // field u_n + a
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        V[k] = 0.5 * (A[k] - B[k]);
-        g[k] = unk[k] * V[k] + P[k].p * (0.5 * b * unk[k] - 0.5 * (b * un - ia));
+        V[k] = A[k] - B[k];
+        gh[k] = hu[k] * V[k] + P[k].p * (hb * hu[k] - cp);
     }
-    const double h4 = split_recon<SCHEME, SHARED>(V, g, aplus, ph, kept);
-    // entropy field
+    const double h4 = split_recon<SCHEME, SHARED>(V, gh, 0.5 * aplus, ph, kept);
+    // entropy field: V = rho - b (K rho - u.m + E), g = u_n V + p b (un - u_n)
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        V[k] = P[k].r - A[k];
-        g[k] = unk[k] * V[k] + P[k].p * (b * (un - unk[k]));
+        V[k] = P[k].r - 2.0 * A[k];
+        gh[k] = hu[k] * V[k] + P[k].p * (hbun - b * hu[k]);
     }
-    const double h1 = split_recon<SCHEME, SHARED>(V, g, a0, ph, kept);
-    // shear fields
+    const double h1 = split_recon<SCHEME, SHARED>(V, gh, a0, ph, kept);
+    // shear fields: V = m_t - ut rho, g = u_n V
     double ht[2] = {0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < NT; ++s) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             V[k] = P[k].mt[s] - ut[s] * P[k].r;
-            g[k] = unk[k] * V[k];
+            gh[k] = hu[k] * V[k];
         }
-        ht[s] = split_recon<SCHEME, SHARED>(V, g, a0, ph, kept);
+        ht[s] = split_recon<SCHEME, SHARED>(V, gh, a0, ph, kept);
     }
     // back to physical space: F = R ghat
     const double hs = h0 + h1 + h4;
@@ -329,7 +354,8 @@ __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x)
 // FP32 range at nearly every jump), WENO-Z's alpha on x_r / max(x) once
 // max(x) >= 1.  Both are algebraically the FP64 test.
 template <int SCHEME>
-__device__ __forceinline__ float recon5f(float fm2, float fm1, float f0, float fp1, float fp2, float CT, float eps) {
+__device__ __forceinline__ float recon5f(float fm2, float fm1, float f0, float fp1, float fp2, float CT, float eps,
+                                         float X) {
     const float q0 = (1.0f / 3.0f) * f0 + (5.0f / 6.0f) * fp1 - (1.0f / 6.0f) * fp2;
     const float q1 = -(1.0f / 6.0f) * fm1 + (5.0f / 6.0f) * f0 + (1.0f / 3.0f) * fp1;
     const float q2 = (1.0f / 3.0f) * fm2 - (7.0f / 6.0f) * fm1 + (11.0f / 6.0f) * f0;
@@ -344,6 +370,8 @@ __device__ __forceinline__ float recon5f(float fm2, float fm1, float f0, float f
     t = fm2 - 4.0f * fm1 + 3.0f * f0;
     const float b2 = (13.0f / 12.0f) * s * s + 0.25f * t * t;
     const float tau = fabsf(b0 - b2);
+    // TENO: no stencil can be cut under the bound (as in FP64)
+    if (SCHEME == OSBLI_TENO5 && tau < X * (fminf(fminf(b0, b1), b2) + eps)) return 0.3f * q0 + 0.6f * q1 + 0.1f * q2;
     const float x0 = tau * rcpf(b0 + eps), x1 = tau * rcpf(b1 + eps), x2 = tau * rcpf(b2 + eps);
     if (SCHEME == OSBLI_WENOZ5) {
         const float xm = fmaxf(x0, fmaxf(x1, x2));
@@ -379,15 +407,15 @@ __device__ __forceinline__ float recon5f(float fm2, float fm1, float f0, float f
 
 template <int SCHEME>
 __device__ __forceinline__ float split_reconf(const float (&V)[6], const float (&G)[6], float alpha, float CT,
-                                              float eps) {
+                                              float eps, float X) {
     float gp[6], gm[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         gp[k] = 0.5f * (G[k] + alpha * V[k]);
         gm[k] = 0.5f * (G[k] - alpha * V[k]);
     }
-    return recon5f<SCHEME>(gp[0], gp[1], gp[2], gp[3], gp[4], CT, eps) +
-           recon5f<SCHEME>(gm[5], gm[4], gm[3], gm[2], gm[1], CT, eps);
+    return recon5f<SCHEME>(gp[0], gp[1], gp[2], gp[3], gp[4], CT, eps, X) +
+           recon5f<SCHEME>(gm[5], gm[4], gm[3], gm[2], gm[1], CT, eps, X);
 }
 
 template <int ND, int SCHEME>
@@ -445,7 +473,7 @@ __device__ __forceinline__ void char_flux_mixed(const Loc<ND> (&P)[6], const Phy
     const float ah = sqrtf(gm1 * (Hh - K));
     const float ia = rcpf(ah);
     const float b = gm1 * ia * ia;
-    const float CT = (float)ph.CT, eps = (float)ph.eps;
+    const float CT = (float)ph.CT, eps = (float)ph.eps, X = (float)ph.teno_fast;
 
     float A[6], B[6], Ag[6], Bg[6], aminus = 0.0f, aplus = 0.0f, a0 = 0.0f;
 #pragma unroll
@@ -470,19 +498,19 @@ __device__ __forceinline__ void char_flux_mixed(const Loc<ND> (&P)[6], const Phy
         V[k] = 0.5f * (A[k] + B[k]);
         G[k] = 0.5f * (Ag[k] + Bg[k]);
     }
-    const float h0 = split_reconf<SCHEME>(V, G, aminus, CT, eps);
+    const float h0 = split_reconf<SCHEME>(V, G, aminus, CT, eps, X);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         V[k] = 0.5f * (A[k] - B[k]);
         G[k] = 0.5f * (Ag[k] - Bg[k]);
     }
-    const float h4 = split_reconf<SCHEME>(V, G, aplus, CT, eps);
+    const float h4 = split_reconf<SCHEME>(V, G, aplus, CT, eps, X);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         V[k] = dr[k] - A[k];
         G[k] = gr[k] - Ag[k];
     }
-    const float h1 = split_reconf<SCHEME>(V, G, a0, CT, eps);
+    const float h1 = split_reconf<SCHEME>(V, G, a0, CT, eps, X);
     float ht[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int s = 0; s < NT; ++s) {
@@ -491,7 +519,7 @@ __device__ __forceinline__ void char_flux_mixed(const Loc<ND> (&P)[6], const Phy
             V[k] = dmt[s][k] - ut[s] * dr[k];
             G[k] = gmt[s][k] - ut[s] * gr[k];
         }
-        ht[s] = split_reconf<SCHEME>(V, G, a0, CT, eps);
+        ht[s] = split_reconf<SCHEME>(V, G, a0, CT, eps, X);
     }
     const float hs = h0 + h1 + h4, hd = h4 - h0;
     float dFE = Hh * (h0 + h4) + ah * un * hd + K * h1;

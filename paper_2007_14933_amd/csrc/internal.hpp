@@ -28,6 +28,7 @@ struct Grid {
 // Physical and scheme constants, precomputed once.
 struct Phys {
     double gamma, gm1, Re, Pr, Minf, M2, Ts, CT, eps;
+    double teno_fast;  // TENO: every stencil is kept when tau < teno_fast * min_r(beta_r + eps)
     double mu_re;      // 1/Re
     double kheat;      // 1/((gamma-1) M^2 Pr Re)
     double nu_fac;     // max(4/3, gamma/Pr)
