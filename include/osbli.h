@@ -209,10 +209,11 @@ int osbli_central_store_all(osbli_ctx *ctx, void *work, size_t bytes);
  * osbli_rk_substep; the per-substage scratch (residual accumulator, and the
  * viscous fluxes when Re > 0) lives in one library-owned static device array
  * of osbli_noalloc_scratch_bytes() = 64 MiB per GPU instead of the context's
- * workspace: 8 nc n bytes plus, when viscous, 8 ndim (ndim + 1) n bytes
- * (n interior nodes, each part rounded up to 256) must fit, e.g. a viscous
- * 3D grid of up to about 4.9e5 nodes, an inviscid 2D grid of up to about
- * 2.0e6.  Larger grids return OSBLI_ENOSPACE before any launch.  The call
+ * workspace: 8 nc n bytes plus, when viscous, 8 (ndim (ndim + 1) / 2 + ndim) n
+ * bytes on separable meshes (each distinct stress and energy flux once) or
+ * 8 ndim (ndim + 1) n on general ones (n interior nodes, each part rounded
+ * up to 256) must fit, e.g. a viscous separable 3D grid of up to about
+ * 6.0e5 nodes, an inviscid 2D grid of up to about 2.0e6.  Larger grids return OSBLI_ENOSPACE before any launch.  The call
  * allocates nothing (no hipMalloc / hipFree, no profiling events).  Every
  * call on a GPU shares that GPU's one array and leaves its contents behind:
  * calls that overlap on one GPU (several streams or threads) race, so

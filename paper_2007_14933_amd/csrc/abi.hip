@@ -200,7 +200,7 @@ Layout make_layout(const osbli_params *p, const Grid &g) {
     L.Racc = off;
     size_t racc = align256(sizeof(double) * g.nc * g.nint);
     L.G = L.Racc + racc;
-    size_t gsz = p->Re > 0.0 ? align256(sizeof(double) * g.nd * (g.nd + 1) * g.nint) : 0;
+    size_t gsz = p->Re > 0.0 ? align256(sizeof(double) * gflux_count(g.nd, gen) * g.nint) : 0;
     size_t stage;
     if (p->mesh == OSBLI_MESH_GENERAL && g.nd >= 2)
         stage = align256(sizeof(double) * g.nd * g.nint) + (g.nd == 3 ? align256(sizeof(double) * 9 * g.nint) : 0);
@@ -574,7 +574,8 @@ int osbli_rk_substep_noalloc(osbli_ctx *c, int stage, double dt, double *U, doub
     if (stage < 0 || stage >= c->nstages) return set_err(c, OSBLI_EINVAL, "stage must be 0..%d", c->nstages - 1);
     if ((void *)U == (void *)dU) return set_err(c, OSBLI_EINVAL, "dU aliases U");
     const size_t racc = align256(sizeof(double) * c->g.nc * c->g.nint);
-    const size_t gsz = c->ph.viscous ? align256(sizeof(double) * c->g.nd * (c->g.nd + 1) * c->g.nint) : 0;
+    const size_t gsz =
+        c->ph.viscous ? align256(sizeof(double) * gflux_count(c->g.nd, c->m.general != 0) * c->g.nint) : 0;
     if (racc + gsz > kScratchBytes)
         return set_err(c, OSBLI_ENOSPACE, "grid needs %zu bytes of scratch; the allocation-free substep holds %zu",
                        racc + gsz, kScratchBytes);

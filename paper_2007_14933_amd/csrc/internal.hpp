@@ -86,6 +86,22 @@ __device__ __forceinline__ double sqrt64(double x) {
 }
 
 
+// Stored viscous-flux arrays.  General meshes keep every component of
+// G_k = S_k . Fv (nd (nd + 1) arrays); separable meshes store G_k = Fv_k,
+// whose momentum part is the symmetric stress tensor, so its nd (nd + 1) / 2
+// distinct entries (diagonal first, then (0,1), (0,2), (1,2)) and the nd
+// energy fluxes are kept once each: 6 + 3 arrays in 3D instead of 12.
+__host__ __device__ constexpr int gflux_count(int nd, bool gen) {
+    return gen ? nd * (nd + 1) : nd * (nd + 1) / 2 + nd;
+}
+template <int ND, bool GEN>
+__host__ __device__ constexpr int gslot(int k, int v) {
+    if (GEN) return k * (ND + 1) + v;
+    if (v == ND) return ND * (ND + 1) / 2 + k;
+    const int a = k < v ? k : v, b = k < v ? v : k;
+    return a == b ? a : (ND == 2 ? 2 : (a == 0 ? 2 + b : 5));
+}
+
 // One stage of a low-storage (2N) Runge-Kutta scheme: dU <- A dU + dt R
 // (first: A = 0 and dU is not read), U <- U + B dU (last: dU is not stored,
 // the register is not read again before the next step's first stage).

@@ -6,7 +6,8 @@
 // Pass 1 (k_visc_flux): per node, gradients of (u, T) from the central
 // operator (closures at non-periodic ends; periodic ends read the ghost
 // copies), stress tensor, heat flux and the contravariant viscous fluxes
-// G_k = S_k . Fv, stored once per node.
+// G_k = S_k . Fv, stored once per node (separable meshes: each distinct
+// stress once, see gslot).
 // Pass 2 (k_finish): per node, J sum_k D_k G_k added to the convective
 // residual, then either stored (residual call) or folded into the RK update.
 #include "point.hpp"
@@ -156,7 +157,8 @@ __device__ __forceinline__ void visc_store(const double (&phi0)[ND + 1], const d
 #pragma unroll
                 for (int b = 0; b < ND; ++b) s += m.S[(kk * ND + b) * cs + e0] * Fv[b][v];
             }
-            G[(kk * NV + v) * g.nint + ci] = s;
+            // each distinct stress once (separable meshes)
+            if (GEN || v == ND || kk <= v) G[gslot<ND, GEN>(kk, v) * g.nint + ci] = s;
         }
 }
 
@@ -292,7 +294,7 @@ k_finish(const double *Racc, const double *__restrict__ G, double *Rout, Grid g,
             const double sc = GEN ? 1.0 : m.invh[kk][p];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double *Gv = G + (kk * NV + v) * g.nint + line;
+                const double *Gv = G + gslot<ND, GEN>(kk, v) * g.nint + line;
                 auto at = [&](int64_t q) {
                     int64_t w = q;
                     if (per) w = q < 0 ? q + N : (q >= N ? q - N : q);
@@ -354,13 +356,16 @@ k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid 
         ox[k] = wrap(x + d, Nx, perx) - x;
         oy[k] = (wrap(y + d, Ny, pery) - y) * sy;
     }
-    const double *Gx = G, *Gy = G + NV * g.nint, *Gz = G + 2 * NV * g.nint;
+    // component v of G_x, G_y, G_z
+    auto Gx = [&](int v) { return G + gslot<3, false>(0, v) * g.nint; };
+    auto Gy = [&](int v) { return G + gslot<3, false>(1, v) * g.nint; };
+    auto Gz = [&](int v) { return G + gslot<3, false>(2, v) * g.nint; };
     double gz[5][NV];  // G_z of this column at z-2 .. z+2
 #pragma unroll
     for (int k = 1; k < 5; ++k) {
         const int64_t zp = wrap(z0 - 3 + k, Nz, perz);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) gz[k][v] = Gz[v * g.nint + col + zp * sz];
+        for (int v = 0; v < NV; ++v) gz[k][v] = Gz(v)[col + zp * sz];
     }
 #pragma unroll 1
     for (int64_t z = z0; z < z1; ++z) {
@@ -374,7 +379,7 @@ k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid 
         // the fluxes this node needs: G_z from the window, then the x and the
         // y neighbours, four loads per flux component requested together
 #pragma unroll
-        for (int v = 0; v < NV; ++v) gz[4][v] = Gz[v * g.nint + col + zn * sz];
+        for (int v = 0; v < NV; ++v) gz[4][v] = Gz(v)[col + zn * sz];
         double acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = 0.0;
@@ -384,14 +389,14 @@ k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid 
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) a[v][k] = Gx[v * g.nint + ci + ox[k]];
+                for (int k = 0; k < 4; ++k) a[v][k] = Gx(v)[ci + ox[k]];
 #pragma unroll
             for (int v = 0; v < NV; ++v)
                 acc[v] += scx * ((2.0 / 3.0) * (a[v][2] - a[v][1]) - (1.0 / 12.0) * (a[v][3] - a[v][0]));
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double *Gv = Gx + v * g.nint + (ci - x);
+                const double *Gv = Gx(v) + (ci - x);
                 auto at = [&](int64_t q) { return Gv[q]; };
                 acc[v] += scx * dline(at, x, Nx, false);
             }
@@ -401,14 +406,14 @@ k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid 
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) a[v][k] = Gy[v * g.nint + ci + oy[k]];
+                for (int k = 0; k < 4; ++k) a[v][k] = Gy(v)[ci + oy[k]];
 #pragma unroll
             for (int v = 0; v < NV; ++v)
                 acc[v] += scy * ((2.0 / 3.0) * (a[v][2] - a[v][1]) - (1.0 / 12.0) * (a[v][3] - a[v][0]));
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double *Gv = Gy + v * g.nint + (ci - y * sy);
+                const double *Gv = Gy(v) + (ci - y * sy);
                 auto at = [&](int64_t q) { return Gv[q * sy]; };
                 acc[v] += scy * dline(at, y, Ny, false);
             }
@@ -421,7 +426,7 @@ k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid 
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double *Gv = Gz + v * g.nint + col;
+                const double *Gv = Gz(v) + col;
                 auto at = [&](int64_t q) { return Gv[q * sz]; };
                 acc[v] += scz * dline(at, z, Nz, false);
             }

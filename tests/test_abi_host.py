@@ -51,9 +51,10 @@ def test_workspace_sizes(lib):
     tgv = I.tgv(16)
     n = 16 ** 3
     ws = _ws(tgv)
-    # residual accumulator 5n + viscous fluxes 12n doubles, plus small tables
-    assert ws >= 8 * (5 * n + 12 * n)
-    assert ws < 8 * (5 * n + 12 * n) + 64 * 1024
+    # residual accumulator 5n + viscous fluxes 9n doubles (separable mesh:
+    # six distinct stresses and three energy fluxes), plus small tables
+    assert ws >= 8 * (5 * n + 9 * n)
+    assert ws < 8 * (5 * n + 9 * n) + 64 * 1024
     sod = I.sod(400)
     assert 8 * 3 * 400 <= _ws(sod) < 64 * 1024
 

@@ -53,8 +53,9 @@ def test_noalloc_substep_matches_substep(order):
 def test_noalloc_substep_refuses_oversized_grid():
     from paper_2007_14933_amd.solver import Solver
     say("[gpu no-alloc] oversized grid refused")
-    # viscous 3D at 84^3: 17 doubles per node = 80.6 MB > 64 MiB
-    s = Solver(I.tgv(84))
+    # viscous separable 3D at 90^3: 14 doubles per node (residual 5, viscous
+    # fluxes 9) = 81.6 MB > 64 MiB
+    s = Solver(I.tgv(90))
     rc = s.lib.osbli_rk_substep_noalloc(s.ctx, 0, 1e-4, _ptr(s.U), _ptr(s.dU), s._s())
     assert rc == B.OSBLI_ENOSPACE
     assert b"scratch" in s.lib.osbli_last_error(s.ctx)
