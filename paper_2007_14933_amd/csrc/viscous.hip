@@ -224,15 +224,22 @@ k_visc_flux_zm(const double *__restrict__ U, double *__restrict__ G, Grid g, Phy
             for (int v = 0; v < NV; ++v) w[k][v] = w[k + 1][v];
         phi_at<3>(U, ecol + (z + 2) * sz, cs, ph, w[4]);
         const int b = (int)((z - z0) & 1);
+        // the tile's own nodes come from the columns' windows (w[2] is this
+        // plane); only the halo and the nodes beyond the grid are loaded
         for (int t = tid; t < kHX * kHY; t += kZX * kZY) {
             const int cx = t % kHX, cy = t / kHX;
             int64_t gx = x0 - 2 + cx, gy = y0 - 2 + cy;
+            if (cx >= 2 && cx < kZX + 2 && cy >= 2 && cy < kZY + 2 && gx < Nx && gy < Ny) continue;
             gx = gx > Nx + 2 ? Nx + 2 : gx;
             gy = gy > Ny + 2 ? Ny + 2 : gy;
             double f[NV];
             phi_at<3>(U, ext_index(g, gx, gy, z), cs, ph, f);
 #pragma unroll
             for (int v = 0; v < NV; ++v) tile[b][v][cy][cx] = f[v];
+        }
+        if (own) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) tile[b][v][ty + 2][tx + 2] = w[2][v];
         }
         __syncthreads();
         if (own) {
@@ -330,13 +337,20 @@ constexpr int kFX = 64, kFY = 4;  // columns per block
 
 __global__ void __launch_bounds__(kFX * kFY)
 k_finish_zm(const double *__restrict__ Racc, const double *__restrict__ G, Grid g, Metrics m, RkStage rs, double dt,
-            double *__restrict__ U, double *__restrict__ dU) {
+            double *__restrict__ U, double *__restrict__ dU, int ntx, int nty, int stripe) {
     constexpr int NC = 5, NV = 4;
-    const int64_t x = (int64_t)blockIdx.x * kFX + threadIdx.x;
-    const int64_t y = (int64_t)blockIdx.y * kFY + threadIdx.y;
+    // XCD k (blocks b with b % 8 == k) owns the stripe of y tiles
+    // [k stripe, (k + 1) stripe); within it x tiles run fastest, then y, then
+    // z runs, so every XCD advances through the planes at the same pace and
+    // the y neighbours' fluxes are read through the one L2
+    const int xcd = (int)(blockIdx.x % kXcds), l = (int)(blockIdx.x / kXcds);
+    const int bxt = l % ntx, byt = xcd * stripe + (l / ntx) % stripe, bzt = l / (ntx * stripe);
+    if (byt >= nty) return;
+    const int64_t x = (int64_t)bxt * kFX + threadIdx.x;
+    const int64_t y = (int64_t)byt * kFY + threadIdx.y;
     const int64_t Nx = g.n[0], Ny = g.n[1], Nz = g.n[2];
     if (x >= Nx || y >= Ny) return;  // no block-wide synchronisation below
-    const int64_t z0 = (int64_t)blockIdx.z * kFZ;
+    const int64_t z0 = (int64_t)bzt * kFZ;
     const int64_t z1 = z0 + kFZ < Nz ? z0 + kFZ : Nz;
     const bool perx = g.periodic[0] != 0, pery = g.periodic[1] != 0, perz = g.periodic[2] != 0;
     const bool intx = perx || (x >= 2 && x <= Nx - 3);
@@ -496,9 +510,11 @@ hipError_t finish_nd(const Grid &g, const Phys &ph, const Metrics &m, const doub
     // per-XCD runs of node_tiles measured slower here)
     const dim3 nb = node_grid(g), bs(kBX, kBY);
     if (ND == 3 && !GEN && ph.viscous && mode == 1) {
-        const dim3 zb((unsigned)((g.n[0] + kFX - 1) / kFX), (unsigned)((g.n[1] + kFY - 1) / kFY),
-                      (unsigned)((g.n[2] + kFZ - 1) / kFZ));
-        hipLaunchKernelGGL(k_finish_zm, zb, dim3(kFX, kFY), 0, s, Racc, G, g, m, rs, dt, U, dU);
+        const int ntx = (int)((g.n[0] + kFX - 1) / kFX), nty = (int)((g.n[1] + kFY - 1) / kFY);
+        const int ntz = (int)((g.n[2] + kFZ - 1) / kFZ), stripe = (nty + kXcds - 1) / kXcds;
+        const unsigned nblk = (unsigned)kXcds * (unsigned)(ntx * stripe * ntz);
+        hipLaunchKernelGGL(k_finish_zm, dim3(nblk), dim3(kFX, kFY), 0, s, Racc, G, g, m, rs, dt, U, dU, ntx, nty,
+                           stripe);
         return hipGetLastError();
     }
     if (ph.viscous) {
