@@ -305,6 +305,7 @@ def tgv_learned(prob, args, plain_value, plain_extra):
                      "smooth_fraction_last": ex["smooth_fraction_last"],
                      "rel_L1_rho_vs_plain": float("%.3e" % (np.abs(ex["rho"] - ref).mean() / np.abs(ref).mean())),
                      "t_diff_vs_plain": float("%.3e" % (ex["t"] - plain_extra["t"]))}
+        res[name]["meets_1e-4"] = bool(res[name]["rel_L1_rho_vs_plain"] <= 1e-4)
     return res
 
 
@@ -401,6 +402,7 @@ def sensor_form(cfl):
             ref = rho
         else:
             r["rel_L1_rho_vs_plain"] = float("%.3e" % (np.abs(rho - ref).mean() / np.abs(ref).mean()))
+            r["meets_1e-4"] = bool(r["rel_L1_rho_vs_plain"] <= 1e-4)
             r["speedup_vs_plain"] = round(v / res["plain_fp64"]["value"], 3)
         res[name] = r
         del s
