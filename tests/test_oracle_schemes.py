@@ -388,3 +388,37 @@ def test_shu_osher_higher_order_resolves_the_entropy_waves():
     e3 = np.abs(sols[(I.WENOZ3, 320)] - fine)[hf].mean()
     e5 = np.abs(sols[(I.WENOZ5, 320)] - fine)[hf].mean()
     assert e5 < 0.5 * e3, (e3, e5)
+
+
+@pytest.mark.parametrize("scheme,K", [(I.TENO5, 3), (I.TENO6, 4)])
+@pytest.mark.parametrize("CT", [1e-5, 1e-7, 1e-3, 0.05])
+def test_teno_bound_proves_every_stencil_kept(scheme, K, CT):
+    """The kernels skip TENO's weights when tau < X min_r(beta_r + eps) with
+    X = (2 K C_T)^(-1/6) - 1: then every gamma_r >= 1 while C_T sum(gamma)
+    <= 1/2, so no stencil can be cut.  The oracle, which always evaluates
+    the weights, must keep every stencil on such data (section 2.5, eqs.
+    TENO_weights and cutoff_eqn).  Seeded stencils of every scale, many of
+    them close to the bound, and the extreme case of the derivation."""
+    X = (2 * K * CT) ** (-1.0 / 6.0) - 1.0
+    eps = 1e-16
+    # the extreme case: one ratio 0, the others X
+    g = np.array([1.0] + [(1.0 + X) ** 6] * (K - 1))
+    assert np.all(g >= CT * g.sum()) and CT * g.sum() <= 0.5 + 1e-12
+    rng = np.random.default_rng(2007 + K)
+    near = checked = 0
+    for _ in range(3000):
+        x = np.arange(6, dtype=float) - 2.0
+        c = rng.normal(size=5) * 10.0 ** rng.uniform(-8, 2, size=5)
+        f = sum(c[k] * x ** k for k in range(5)) + rng.normal(size=6) * 10.0 ** rng.uniform(-12, 0)
+        if scheme == I.TENO6:
+            b, tau = O.smoothness6(f)
+        else:
+            b = O.smoothness5(f[:5])
+            tau = abs(b[0] - b[2])
+        ratio = tau / (b.min() + eps)
+        if ratio < X:
+            _, dl = O.recon(scheme, CT, eps, f)
+            assert list(dl)[:K] == [1] * K, (f, ratio, X, list(dl))
+            checked += 1
+            near += ratio > 0.5 * X
+    assert checked > 500 and near > 20, (checked, near)
