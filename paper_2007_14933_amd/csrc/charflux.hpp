@@ -125,26 +125,28 @@ __device__ __forceinline__ double recon5_fin(const R5 &r, double tinv, double CT
 // one division: x_r = tau prod_{s != r}(beta_s + eps) / prod_s(beta_s + eps).
 __device__ __forceinline__ double recon6_teno(double fm2, double fm1, double f0, double fp1, double fp2, double fp3,
                                               double CT, double eps, double X, bool *kept) {
-    const double q0 = (1.0 / 3.0) * f0 + (5.0 / 6.0) * fp1 - (1.0 / 6.0) * fp2;
-    const double q1 = -(1.0 / 6.0) * fm1 + (5.0 / 6.0) * f0 + (1.0 / 3.0) * fp1;
-    const double q2 = (1.0 / 3.0) * fm2 - (7.0 / 6.0) * fm1 + (11.0 / 6.0) * f0;
-    const double q3 = 0.25 * f0 + (13.0 / 12.0) * fp1 - (5.0 / 12.0) * fp2 + (1.0 / 12.0) * fp3;
-    double s, t;
-    s = f0 - 2.0 * fp1 + fp2;
-    t = 3.0 * f0 - 4.0 * fp1 + fp2;
-    const double b0 = (13.0 / 12.0) * s * s + 0.25 * t * t;
-    s = fm1 - 2.0 * f0 + fp1;
-    t = fm1 - fp1;
-    const double b1 = (13.0 / 12.0) * s * s + 0.25 * t * t;
-    s = fm2 - 2.0 * fm1 + f0;
-    t = fm2 - 4.0 * fm1 + 3.0 * f0;
-    const double b2 = (13.0 / 12.0) * s * s + 0.25 * t * t;
-    const double a = -11.0 * f0 + 18.0 * fp1 - 9.0 * fp2 + 2.0 * fp3;
-    const double b = 2.0 * f0 - 5.0 * fp1 + 4.0 * fp2 - fp3;
-    const double c = -f0 + 3.0 * fp1 - 3.0 * fp2 + fp3;
-    const double b3 = (1.0 / 36.0) * a * a + (13.0 / 12.0) * b * b + (781.0 / 720.0) * c * c;
+    // from the first differences d1..d5 of f_{i-2..i+3} (as recon5_ind): each
+    // candidate is f_i plus differences, and the indicators are taken times 4
+    // with 4 eps, which leaves every ratio tau / (beta_r + eps) unchanged
+    const double d1 = fm1 - fm2, d2 = f0 - fm1, d3 = fp1 - f0, d4 = fp2 - fp1, d5 = fp3 - fp2;
+    const double q0 = f0 + (2.0 / 3.0) * d3 - (1.0 / 6.0) * d4;
+    const double q1 = f0 + (1.0 / 6.0) * d2 + (1.0 / 3.0) * d3;
+    const double q2 = f0 - (1.0 / 3.0) * d1 + (5.0 / 6.0) * d2;
+    const double q3 = f0 + 0.75 * d3 - (1.0 / 3.0) * d4 + (1.0 / 12.0) * d5;
+    const double s0 = d4 - d3, s1 = d3 - d2, s2 = d2 - d1;
+    const double t0 = d4 - 3.0 * d3, t1 = d2 + d3, t2 = 3.0 * d2 - d1;
+    const double b0 = ((13.0 / 3.0) * s0) * s0 + t0 * t0;
+    const double b1 = ((13.0 / 3.0) * s1) * s1 + t1 * t1;
+    const double b2 = ((13.0 / 3.0) * s2) * s2 + t2 * t2;
+    // the cubic's combinations -11 f_i + 18 f_{i+1} - 9 f_{i+2} + 2 f_{i+3},
+    // 2 f_i - 5 f_{i+1} + 4 f_{i+2} - f_{i+3}, -f_i + 3 f_{i+1} - 3 f_{i+2} + f_{i+3}
+    const double a = 11.0 * d3 - 7.0 * d4 + 2.0 * d5;
+    const double b = 3.0 * d4 - 2.0 * d3 - d5;
+    const double c = d3 - 2.0 * d4 + d5;
+    const double b3 = ((1.0 / 9.0) * a) * a + ((13.0 / 3.0) * b) * b + ((781.0 / 180.0) * c) * c;
     const double tau = fabs(b3 - (b0 + b2 + 4.0 * b1) * (1.0 / 6.0));
-    const double e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps, e3 = b3 + eps;
+    const double eps4 = 4.0 * eps;
+    const double e0 = b0 + eps4, e1 = b1 + eps4, e2 = b2 + eps4, e3 = b3 + eps4;
     // cut test decided by the bound (as for TENO5): no stencil cut
     if (tau < X * fmin(fmin(e0, e1), fmin(e2, e3))) return 0.3 * q0 + 0.45 * q1 + 0.05 * q2 + 0.2 * q3;
     const double e01 = e0 * e1, e23 = e2 * e3;
