@@ -78,6 +78,8 @@ def _load():
                 "orc_recon": (C.c_double, [C.c_int, C.c_double, C.c_double, _D, _I]),
                 "orc_rk_coeffs": (None, [P, _D, _D, _I]),
                 "orc_smoothness6": (C.c_double, [_D, _D]),
+                "orc_recon_wenoz7": (C.c_double, [C.c_double, _D]),
+                "orc_smoothness7": (None, [_D, _D, _D]),
                 "orc_smoothness5": (None, [_D, _D]),
                 "orc_iface_flux": (None, [P, C.c_int, _D, _D, _D, _I]),
                 "orc_phys_flux": (None, [P, _D, _D, _D]),
@@ -219,6 +221,23 @@ def recon(scheme, CT, eps, f):
     dl = np.zeros(4, dtype=np.intc)
     v = _load().orc_recon(int(scheme), float(CT), float(eps), _dp(f), _ip(dl))
     return v, dl
+
+
+def recon_wenoz7(eps, f):
+    """WENO-7Z at x_{i+1/2} from f_{i-3..i+3} (seven values)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    assert f.size == 7
+    return _load().orc_recon_wenoz7(float(eps), _dp(f))
+
+
+def smoothness7(f):
+    """WENO-7Z indicators beta_0..beta_3 and candidates q_0..q_3 of f_{i-3..i+3}."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    assert f.size == 7
+    b = np.zeros(4)
+    q = np.zeros(4)
+    _load().orc_smoothness7(_dp(f), _dp(b), _dp(q))
+    return b, q
 
 
 def smoothness6(f):

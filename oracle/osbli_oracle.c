@@ -41,7 +41,7 @@
 
 enum { BC_PERIODIC = 0, BC_EXTRAPOLATE = 1, BC_ISOTHERMAL = 2, BC_ADIABATIC = 3, BC_DIRICHLET = 4 };
 enum { SCHEME_WENOZ5 = 0, SCHEME_TENO5 = 1, SCHEME_TENO6 = 2, SCHEME_WENOJS5 = 3, SCHEME_WENOZ3 = 4,
-       SCHEME_CENTRAL4 = 5 };
+       SCHEME_CENTRAL4 = 5, SCHEME_WENOZ7 = 6 };
 enum { RK3_WILLIAMSON = 0, RK3_SSP = 1, RK4_CK = 2 };
 
 typedef struct {
@@ -402,10 +402,102 @@ static double recon_wenoz3(double eps, const double *f)
     return (a0 / sum) * q0 + (a1 / sum) * q1;
 }
 
+/* ---------------------------------------------- WENO-7Z (per scalar) --
+ * Seventh-order WENO-Z (k = 4; the highest order of section 5.2), written
+ * from the definitions: four candidate stencils S_r = {i-r .. i-r+3} of
+ * f_{i-3..i+3} (f[0..6]); on each, the cubic p_r whose averages over the
+ * cells [x_j - 1/2, x_j + 1/2] (unit spacing, cell i = [-1/2, 1/2]) are the
+ * stencil's values; candidate q_r = p_r(1/2); indicator (eq.
+ * smoothness_indicator) beta_r = sum_{l=1..3} integral over cell i of
+ * (p_r^(l))^2, the integrals by three-point Gauss-Legendre quadrature (exact
+ * for these polynomial degrees); alpha_r = d_r (1 + (tau/(beta_r + eps))^2)
+ * (eq. wenoz_weights).  Readings (not printed): the optimal weights
+ * d = (4/35, 18/35, 12/35, 1/35) of the cited source (the unique weights
+ * whose combination of the candidates is the seven-cell reconstruction), and
+ * tau_7 = |beta_0 + 3 beta_1 - 3 beta_2 - beta_3| (Castro et al., the paper
+ * prints only the fifth-order tau). */
+static double wz7_basis[4][4][4];  /* [r][j][k]: coefficient of x^k of the cubic of unit data at node j of S_r */
+
+/* the cubics of unit data (called before any reconstruction; idempotent) */
+static void wz7_init(void)
+{
+    for (int r = 0; r < 4; r++)
+        for (int j = 0; j < 4; j++) {
+            /* cell-average conditions: sum_k c_k int_{x_m-1/2}^{x_m+1/2} x^k dx = [m == j] */
+            double A[4][5];
+            for (int m = 0; m < 4; m++) {
+                const double xm = (double)(m - r), lo = xm - 0.5, hi = xm + 0.5;
+                double plo = lo, phi = hi;
+                for (int k = 0; k < 4; k++) {
+                    A[m][k] = (phi - plo) / (k + 1);
+                    plo *= lo;
+                    phi *= hi;
+                }
+                A[m][4] = m == j ? 1.0 : 0.0;
+            }
+            for (int c = 0; c < 4; c++) {  /* Gauss-Jordan with partial pivoting */
+                int pv = c;
+                for (int m = c + 1; m < 4; m++)
+                    if (fabs(A[m][c]) > fabs(A[pv][c])) pv = m;
+                for (int k = 0; k < 5; k++) {
+                    double t = A[c][k];
+                    A[c][k] = A[pv][k];
+                    A[pv][k] = t;
+                }
+                for (int m = 0; m < 4; m++) {
+                    if (m == c) continue;
+                    const double fac = A[m][c] / A[c][c];
+                    for (int k = 0; k < 5; k++) A[m][k] -= fac * A[c][k];
+                }
+            }
+            for (int k = 0; k < 4; k++) wz7_basis[r][j][k] = A[k][4] / A[k][k];
+        }
+}
+
+/* the four indicators of f_{i-3..i+3}, and the candidates if q != NULL */
+static void smoothness7(const double *f, double *beta, double *q)
+{
+    const double gx[3] = {-0.5 * sqrt(0.6), 0.0, 0.5 * sqrt(0.6)};  /* Gauss-Legendre on [-1/2, 1/2] */
+    const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+    for (int r = 0; r < 4; r++) {
+        double c[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 4; j++)
+            for (int k = 0; k < 4; k++) c[k] += wz7_basis[r][j][k] * f[3 - r + j];
+        double b = 0.0;
+        for (int t = 0; t < 3; t++) {
+            const double x = gx[t];
+            const double d1 = c[1] + 2.0 * c[2] * x + 3.0 * c[3] * x * x;
+            const double d2 = 2.0 * c[2] + 6.0 * c[3] * x;
+            const double d3 = 6.0 * c[3];
+            b += gw[t] * (d1 * d1 + d2 * d2 + d3 * d3);
+        }
+        beta[r] = b;
+        if (q) q[r] = c[0] + 0.5 * c[1] + 0.25 * c[2] + 0.125 * c[3];
+    }
+}
+
+static double recon_wenoz7(double eps, const double *f)
+{
+    double q[4], beta[4];
+    smoothness7(f, beta, q);
+    const double tau = fabs(beta[0] + 3.0 * beta[1] - 3.0 * beta[2] - beta[3]);
+    const double dr[4] = {4.0 / 35.0, 18.0 / 35.0, 12.0 / 35.0, 1.0 / 35.0};
+    double a[4], sum = 0.0;
+    for (int r = 0; r < 4; r++) {
+        const double x = tau / (beta[r] + eps);
+        a[r] = dr[r] * (1.0 + x * x);
+        sum += a[r];
+    }
+    double v = 0.0;
+    for (int r = 0; r < 4; r++) v += (a[r] / sum) * q[r];
+    return v;
+}
+
 /* Reconstruction of the scheme at x_{i+1/2} from f[0..5] = f_{i-2..i+3}
- * (the fifth-order schemes read f[0..4], WENO-3Z f[1..3]).  delta (may be
- * NULL) receives four cut-off flags; stencils a scheme does not have, and
- * every stencil of a WENO scheme, read 1. */
+ * (the fifth-order schemes read f[0..4], WENO-3Z f[1..3]; WENO-7Z reads
+ * f[0..6] = f_{i-3..i+3}).  delta (may be NULL) receives four cut-off flags;
+ * stencils a scheme does not have, and every stencil of a WENO scheme,
+ * read 1. */
 static double recon(int scheme, double CT, double eps, const double *f, int *delta)
 {
     int dl[4] = {1, 1, 1, 1};
@@ -414,6 +506,7 @@ static double recon(int scheme, double CT, double eps, const double *f, int *del
     case SCHEME_TENO6: v = recon_teno6(CT, eps, f, dl); break;
     case SCHEME_WENOJS5: v = recon_wenojs5(eps, f); break;
     case SCHEME_WENOZ3: v = recon_wenoz3(eps, f); break;
+    case SCHEME_WENOZ7: v = recon_wenoz7(eps, f); break;
     default: v = recon5(scheme, CT, eps, f, dl); break;
     }
     if (delta) for (int r = 0; r < 4; r++) delta[r] = dl[r];
@@ -437,14 +530,15 @@ static void iface_flux(const orc_params *P, int d, const double *Uk, const doubl
                        double *F, int *delta)
 {
     const int nd = P->ndim, nc = nd + 2;
+    const int W = P->scheme == SCHEME_WENOZ7 ? 8 : 6;  /* stencil points i-W/2+1 .. i+W/2 */
     double Smag = 0.0, nv[3] = {0.0, 0.0, 0.0};
     for (int m = 0; m < nd; m++) Smag += S[m] * S[m];
     Smag = sqrt(Smag);
     for (int m = 0; m < nd; m++) nv[m] = S[m] / Smag;
 
-    prim_t w[6];
-    double fk[6][NCMAX], lam[6][NCMAX];
-    for (int k = 0; k < 6; k++) {
+    prim_t w[8];
+    double fk[8][NCMAX], lam[8][NCMAX];
+    for (int k = 0; k < W; k++) {
         to_prim(P, nd, Uk + k * nc, &w[k]);
         phys_flux(nd, Uk + k * nc, &w[k], nv, fk[k]);
         double un = 0.0;
@@ -454,13 +548,13 @@ static void iface_flux(const orc_params *P, int d, const double *Uk, const doubl
         lam[k][nd + 1] = un + w[k].a;
     }
     double uh[3], Hh;
-    double a2 = half_state(P, nd, &w[2], &w[3], uh, &Hh);
+    double a2 = half_state(P, nd, &w[W / 2 - 1], &w[W / 2], uh, &Hh);
     double ah = sqrt(a2);
     double Lm[NCMAX][NCMAX], Rm[NCMAX][NCMAX];
     eigvecs(P, nd, d, uh, Hh, ah, nv, Lm, Rm);
 
-    double V[6][NCMAX], G[6][NCMAX];
-    for (int k = 0; k < 6; k++)
+    double V[8][NCMAX], G[8][NCMAX];
+    for (int k = 0; k < W; k++)
         for (int j = 0; j < nc; j++) {
             double sv = 0.0, sg = 0.0;
             for (int c = 0; c < nc; c++) {
@@ -473,11 +567,11 @@ static void iface_flux(const orc_params *P, int d, const double *Uk, const doubl
     double ghat[NCMAX];
     for (int j = 0; j < nc; j++) {
         double alpha = 0.0;
-        for (int k = 0; k < 6; k++) alpha = fmax(alpha, fabs(lam[k][j]));
-        double gp[6], gm[6];
-        for (int m = 0; m < 6; m++) {
-            gp[m] = 0.5 * (G[m][j] + alpha * V[m][j]);          /* k = i-2+m   */
-            gm[m] = 0.5 * (G[5 - m][j] - alpha * V[5 - m][j]);  /* k = i+3-m   */
+        for (int k = 0; k < W; k++) alpha = fmax(alpha, fabs(lam[k][j]));
+        double gp[8], gm[8];
+        for (int m = 0; m < W; m++) {
+            gp[m] = 0.5 * (G[m][j] + alpha * V[m][j]);                  /* k = i-W/2+1+m */
+            gm[m] = 0.5 * (G[W - 1 - m][j] - alpha * V[W - 1 - m][j]);  /* k = i+W/2-m   */
         }
         int *dp = delta ? delta + (j * 2 + 0) * 4 : NULL;
         int *dm = delta ? delta + (j * 2 + 1) * 4 : NULL;
@@ -1104,6 +1198,8 @@ int orc_residual(const orc_params *P, const double *S, const double *J, const do
         central_residual(P, &g, S, J, U, R);
         goto body_force;
     }
+    const int W = P->scheme == SCHEME_WENOZ7 ? 8 : 6;
+    if (P->scheme == SCHEME_WENOZ7) wz7_init();
     for (int d = 0; d < nd; d++) {
         int64_t N = g.n[d];
         int o1 = (d + 1) % 3, o2 = (d + 2) % 3;
@@ -1116,9 +1212,16 @@ int orc_residual(const orc_params *P, const double *S, const double *J, const do
                     int64_t q[3];
                     q[d] = p; q[o1] = a; q[o2] = b;
                     int64_t e = gidx(&g, q[0], q[1], q[2]);
-                    double Uk[6 * NCMAX], Sh[3];
-                    for (int k = 0; k < 6; k++)
-                        for (int c = 0; c < nc; c++) Uk[k * nc + c] = U[c * g.npts + e + (k - 2) * g.s[d]];
+                    double Uk[8 * NCMAX], Sh[3];
+                    for (int k = 0; k < W; k++) {
+                        int64_t pos = p + k - (W / 2 - 1);
+                        /* WENO-7Z reads one node past the three ghost layers at the
+                           outermost interfaces: the wrapped interior on periodic
+                           lines, else the third ghost layer again */
+                        if (pos < -NGHOST) pos = is_periodic(P, d) ? N + pos : -NGHOST;
+                        if (pos > N - 1 + NGHOST) pos = is_periodic(P, d) ? pos - N : N - 1 + NGHOST;
+                        for (int c = 0; c < nc; c++) Uk[k * nc + c] = U[c * g.npts + e + (pos - p) * g.s[d]];
+                    }
                     half_area(&g, S, d, e, Sh);
                     iface_flux(P, d, Uk, Sh, Fl + (p + 1) * nc, NULL);
                 }
@@ -1338,6 +1441,19 @@ double orc_recon(int scheme, double CT, double eps, const double *f, int *delta)
 }
 
 double orc_smoothness6(const double *f, double *beta) { return smoothness6(f, beta); }
+
+/* WENO-7Z at x_{i+1/2} from f_{i-3..i+3}; its indicators and candidates */
+double orc_recon_wenoz7(double eps, const double *f)
+{
+    wz7_init();
+    return recon_wenoz7(eps, f);
+}
+
+void orc_smoothness7(const double *f, double *beta, double *q)
+{
+    wz7_init();
+    smoothness7(f, beta, q);
+}
 
 double orc_recon5(int scheme, double CT, double eps, const double *f, int *delta)
 {

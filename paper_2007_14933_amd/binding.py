@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libosbli.so")
 
 OSBLI_OK, OSBLI_EINVAL, OSBLI_EDEVICE, OSBLI_ENONPHYS, OSBLI_ENOSPACE = 0, -1, -2, -3, -4
 PERIODIC, EXTRAPOLATE, ISOTHERMAL_WALL, ADIABATIC_WALL, DIRICHLET = 0, 1, 2, 3, 4
-WENOZ5, TENO5, TENO6, WENOJS5, WENOZ3, CENTRAL4 = 0, 1, 2, 3, 4, 5
+WENOZ5, TENO5, TENO6, WENOJS5, WENOZ3, CENTRAL4, WENOZ7 = 0, 1, 2, 3, 4, 5, 6
 RK3, RK3_SSP, RK4 = 0, 1, 2
 FORM_FP64, FORM_MIXED = 0, 1
 MESH_SEPARABLE, MESH_GENERAL = 0, 1

@@ -19,7 +19,7 @@ from typing import Optional, Tuple
 import numpy as np
 
 PERIODIC, EXTRAPOLATE, ISOTHERMAL, ADIABATIC, DIRICHLET = 0, 1, 2, 3, 4
-WENOZ5, TENO5, TENO6, WENOJS5, WENOZ3, CENTRAL4 = 0, 1, 2, 3, 4, 5
+WENOZ5, TENO5, TENO6, WENOJS5, WENOZ3, CENTRAL4, WENOZ7 = 0, 1, 2, 3, 4, 5, 6
 RK3, RK3_SSP, RK4 = 0, 1, 2       # low-storage Runge-Kutta schemes (3, 3 and 5 substages)
 NGHOST = 3
 

@@ -1,9 +1,9 @@
 """Pins of the oracle's further schemes against what the paper and the
 mathematics fix: sixth-order TENO (section 2.5, K = 6), the original WENO
-weights (section 2.3, eqs. omega and alpha), third-order WENO-Z (the orders of
-section 5.2), the strong-stability-preserving and fourth-order low-storage
-Runge-Kutta schemes (section 2.7), and the Dirichlet ends of the Shu-Osher
-case (section 5.2).  Each pin is independent of the oracle's own formulas:
+weights (section 2.3, eqs. omega and alpha), third- and seventh-order
+WENO-Z (the orders of section 5.2), the strong-stability-preserving and
+fourth-order low-storage Runge-Kutta schemes (section 2.7), and the
+Dirichlet ends of the Shu-Osher case (section 5.2).  Each pin is independent of the oracle's own formulas:
 polynomial exactness, the integral definition of the indicators, exact
 rational cut-off decisions, order conditions of the Butcher tableau, the
 Rankine-Hugoniot relations, convergence orders."""
@@ -369,9 +369,9 @@ def test_shu_osher_higher_order_resolves_the_entropy_waves():
     sits where a Mach-3 shock started at x = -4 lands (x ~ 2.4), and in the
     high-frequency region behind it (0.5 < x < 2.2) WENO-5Z lies much closer
     than WENO-3Z to a fine WENO-5Z solution (N = 960, averaged to the coarse
-    cells)."""
+    cells), and WENO-7Z closer still (the ordering of the paper's figure)."""
     sols = {}
-    for sc, N in ((I.WENOZ3, 320), (I.WENOZ5, 320), (I.WENOZ5, 960)):
+    for sc, N in ((I.WENOZ3, 320), (I.WENOZ5, 320), (I.WENOZ7, 320), (I.WENOZ5, 960)):
         p = I.shu_osher(N, scheme=sc)
         S, J = O.metrics(p)
         U = p.U0.copy()
@@ -387,7 +387,8 @@ def test_shu_osher_higher_order_resolves_the_entropy_waves():
     hf = (x > 0.5) & (x < 2.2)
     e3 = np.abs(sols[(I.WENOZ3, 320)] - fine)[hf].mean()
     e5 = np.abs(sols[(I.WENOZ5, 320)] - fine)[hf].mean()
-    assert e5 < 0.5 * e3, (e3, e5)
+    e7 = np.abs(sols[(I.WENOZ7, 320)] - fine)[hf].mean()
+    assert e5 < 0.5 * e3 and e7 < 0.8 * e5, (e3, e5, e7)
 
 
 @pytest.mark.parametrize("scheme,K", [(I.TENO5, 3), (I.TENO6, 4)])
@@ -422,3 +423,98 @@ def test_teno_bound_proves_every_stencil_kept(scheme, K, CT):
             checked += 1
             near += ratio > 0.5 * X
     assert checked > 500 and near > 20, (checked, near)
+
+
+# ----------------------------------------------------------------- WENO-7Z
+def _cubic_cell_averages(c, left, npts):
+    """Exact cell averages over [j - 1/2, j + 1/2] of sum_k c_k x^k."""
+    out = []
+    for j in range(left, left + npts):
+        lo, hi = Fr(j) - Fr(1, 2), Fr(j) + Fr(1, 2)
+        out.append(sum(ck * (hi ** (k + 1) - lo ** (k + 1)) / (k + 1) for k, ck in enumerate(c)))
+    return out
+
+
+def test_wenoz7_indicators_and_candidates_on_cubics():
+    """Cell averages of one cubic P on i-3..i+3: every candidate stencil's
+    cubic is P itself, so each q_r = P(1/2) and each beta_r is the Jiang-Shu
+    integral (eq. smoothness_indicator) of P over cell i, here
+    int (P')^2 + (P'')^2 + (P''')^2 dx on [-1/2, 1/2] in exact arithmetic."""
+    rng = np.random.default_rng(77)
+    for _ in range(5):
+        c = [Fr(int(v)) / 7 for v in rng.integers(-20, 21, size=4)]
+        f = np.array([float(v) for v in _cubic_cell_averages(c, -3, 7)])
+        b, q = O.smoothness7(f)
+        d1 = [c[1], 2 * c[2], 3 * c[3]]                 # P'  = d1[0] + d1[1] x + d1[2] x^2
+        d2 = [2 * c[2], 6 * c[3]]                       # P'' = d2[0] + d2[1] x
+        d3 = 6 * c[3]
+
+        def integ(p):  # int_{-1/2}^{1/2} sum_k p_k x^k
+            return sum(pk * (Fr(1, 2) ** (k + 1) - Fr(-1, 2) ** (k + 1)) / (k + 1) for k, pk in enumerate(p))
+
+        def sq(p):
+            r = [Fr(0)] * (2 * len(p) - 1)
+            for i, a in enumerate(p):
+                for j, bb in enumerate(p):
+                    r[i + j] += a * bb
+            return r
+        beta = float(integ(sq(d1)) + integ(sq(d2)) + d3 * d3)
+        val = float(sum(ck * Fr(1, 2) ** k for k, ck in enumerate(c)))
+        assert np.abs(b - beta).max() <= 1e-12 * (1 + abs(beta)), (b, beta)
+        assert np.abs(q - val).max() <= 1e-12 * (1 + abs(val)), (q, val)
+
+
+@pytest.mark.parametrize("deg", [0, 3, 5, 6])
+def test_wenoz7_linear_limit_is_the_seven_cell_reconstruction(deg):
+    """With eps far above every indicator the weights are the optimal ones,
+    and their combination of the four candidates is exact for the cell
+    averages of every polynomial of degree <= 6 (seventh order)."""
+    rng = np.random.default_rng(deg)
+    c = [Fr(int(v)) / 5 for v in rng.integers(-9, 10, size=deg + 1)]
+    f = np.array([float(v) for v in _cubic_cell_averages(c, -3, 7)])
+    val = float(sum(ck * Fr(1, 2) ** k for k, ck in enumerate(c)))
+    v = O.recon_wenoz7(1e30, f)
+    assert abs(v - val) <= 1e-11 * (1 + abs(val)), (v, val)
+    w = cell_avg_weights(-3, 7)
+    assert abs(v - w @ f) <= 1e-11 * (1 + abs(val))
+
+
+def test_wenoz7_is_essentially_non_oscillatory_at_a_jump():
+    """A unit jump between cells i and i+1: only S_3 = {i-3..i} is smooth,
+    the value stays at the left state to within the weights' residue; a jump
+    between i-1 and i makes the value follow the right state."""
+    v = O.recon_wenoz7(1e-16, np.array([0.0, 0.0, 0.0, 0.0, 1.0, 1.0, 1.0]))
+    assert abs(v) < 1e-6, v
+    v = O.recon_wenoz7(1e-16, np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0, 1.0]))
+    assert abs(v - 1.0) < 1e-6, v
+
+
+def test_wenoz7_tau_is_of_higher_order_than_the_outer_difference():
+    """On smooth data tau_7 = |beta_0 + 3 beta_1 - 3 beta_2 - beta_3| falls
+    faster with h than |beta_0 - beta_3| (which alone would lower the order
+    of the Z weights)."""
+    r7, r03 = [], []
+    for h in (0.2, 0.1, 0.05):
+        f = sin_cell_averages(0.3, h, -3, 7)
+        b, _ = O.smoothness7(f)
+        r7.append(abs(b[0] + 3 * b[1] - 3 * b[2] - b[3]))
+        r03.append(abs(b[0] - b[3]))
+    o7 = math.log2(r7[1] / r7[2])
+    o03 = math.log2(r03[1] / r03[2])
+    assert o7 > o03 + 1.5, (o7, o03, r7, r03)
+
+
+def test_wenoz7_density_wave_converges_at_seventh_order():
+    """The 1D travelling density wave with WENO-7Z and the five-stage RK4
+    (time error negligible at dt = 2e-4): L1 error order on N = 20, 40, 80
+    (the stencil's outer node past the ghost layers wraps on this periodic
+    line)."""
+    e = []
+    for N in (20, 40, 80):
+        p = I.density_wave_1d(N, scheme=I.WENOZ7, rk=I.RK4)
+        S, J = O.metrics(p)
+        U = p.U0.copy()
+        O.run(p, S, J, U, 10 ** 6, dt_fixed=2e-4, t_end=0.2)
+        e.append(np.abs(O.interior(p, U)[0].ravel() - I.exact_density_wave(p, 0.2).ravel()).mean())
+    o = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert min(o) >= 6.3, (o, e)
