@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble line")
     ap.add_argument("--no-central", action="store_true", help="skip the central-path (StoreSome) line")
     ap.add_argument("--central-steps", type=int, default=20)
-    ap.add_argument("--no-schemes", action="store_true", help="skip the TENO6 / WENO-JS5 / WENO-3Z line")
+    ap.add_argument("--no-schemes", action="store_true", help="skip the TENO6 / WENO-JS5 / WENO-3Z / WENO-7Z line")
     ap.add_argument("--scheme-steps", type=int, default=10)
     ap.add_argument("--batch-steps", type=int, default=30)
     ap.add_argument("--batch-full", action="store_true",
@@ -415,12 +415,14 @@ def sensor_form(cfl):
 def schemes_form(steps, warmup, cfl, n=256):
     """The further schemes on the headline TGV n^3 (viscous, FP64): TENO6 with
     the SSP RK3 (the paper's production configuration), WENO-JS5 with the
-    five-stage RK4, WENO-3Z with RK3; same timing as the headline line."""
+    five-stage RK4, WENO-3Z and WENO-7Z with RK3; same timing as the
+    headline line."""
     from paper_2007_14933_amd import inputs
     out = {}
     for name, kw in (("teno6_ssp_rk3", dict(scheme=inputs.TENO6, rk=inputs.RK3_SSP)),
                      ("wenojs5_rk4", dict(scheme=inputs.WENOJS5, rk=inputs.RK4, eps=1e-6)),
-                     ("wenoz3_rk3", dict(scheme=inputs.WENOZ3))):
+                     ("wenoz3_rk3", dict(scheme=inputs.WENOZ3)),
+                     ("wenoz7_rk3", dict(scheme=inputs.WENOZ7))):
         prob = inputs.tgv(n).with_(**kw)
         nst = inputs.rk_stages(prob.rk)
         wall, _, prof, _ = timed_run(prob, 0, steps, warmup, cfl)

@@ -78,11 +78,20 @@ enum osbli_bc {
  *   WENOJS5 the original weights, eqs. omega and alpha, p = 2 (the paper's
  *           eps for it is 1e-6; eps is the caller's);
  *   WENOZ3  third-order WENO-Z (stencils {i, i+1}, {i-1, i}, weights
- *           (2/3, 1/3), tau_3 = |beta_0 - beta_1|).
+ *           (2/3, 1/3), tau_3 = |beta_0 - beta_1|);
+ *   WENOZ7  seventh-order WENO-Z (section 5.2): the four-point stencils
+ *           {i-r .. i-r+3}, r = 0..3, optimal weights (4/35, 18/35, 12/35,
+ *           1/35), tau_7 = |beta_0 + 3 beta_1 - 3 beta_2 - beta_3|; eight
+ *           stencil points per interface, so at the two outermost interfaces
+ *           of a line it reads one node past the three ghost layers: the
+ *           wrapped interior node on periodic lines, the third ghost layer
+ *           again otherwise.  Separable meshes; periodic, extrapolated or
+ *           Dirichlet ends.
  * The precision form takes WENOZ5 and TENO5; sensor routing TENO5. */
 enum osbli_scheme {
     OSBLI_WENOZ5 = 0, OSBLI_TENO5 = 1, OSBLI_TENO6 = 2, OSBLI_WENOJS5 = 3, OSBLI_WENOZ3 = 4,
-    OSBLI_CENTRAL4 = 5  /* fourth-order central path, below */
+    OSBLI_CENTRAL4 = 5, /* fourth-order central path, below */
+    OSBLI_WENOZ7 = 6
 };
 
 /* OSBLI_CENTRAL4 (section 2.6, central schemes for smooth problems; the

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libosbli.so")
-SOURCES = ["abi.hip", "convective.hip", "convective_teno6.hip", "convective_wenojs5.hip", "convective_wenoz3.hip",
+SOURCES = ["abi.hip", "convective.hip", "convective_teno6.hip", "convective_wenojs5.hip", "convective_wenoz3.hip", "convective_wenoz7.hip",
            "viscous.hip", "central.hip", "bc.hip", "metrics.hip", "sensor.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -144,7 +144,20 @@ int make_grid(const osbli_params *p, Grid &g, char *buf, size_t nb) {
     g.is[2] = g.n[0] * g.n[1];
     g.nint = g.n[0] * g.n[1] * g.n[2];
     if (!(p->gamma > 1.0)) { snprintf(buf, nb, "gamma must exceed 1"); return -1; }
-    if (p->scheme < OSBLI_WENOZ5 || p->scheme > OSBLI_CENTRAL4) { snprintf(buf, nb, "bad scheme"); return -1; }
+    if (p->scheme < OSBLI_WENOZ5 || p->scheme > OSBLI_WENOZ7) { snprintf(buf, nb, "bad scheme"); return -1; }
+    if (p->scheme == OSBLI_WENOZ7) {
+        if (p->mesh == OSBLI_MESH_GENERAL && p->ndim > 1) {
+            snprintf(buf, nb, "WENO-7Z takes separable meshes");
+            return -1;
+        }
+        for (int d = 0; d < p->ndim; ++d)
+            for (int s = 0; s < 2; ++s)
+                if (p->bc_kind[d][s] == OSBLI_ISOTHERMAL_WALL || p->bc_kind[d][s] == OSBLI_ADIABATIC_WALL) {
+                    snprintf(buf, nb, "WENO-7Z takes periodic, extrapolated or Dirichlet ends");
+                    return -1;
+                }
+        if (p->sensor) { snprintf(buf, nb, "sensor routing needs TENO5"); return -1; }
+    }
     if (p->scheme == OSBLI_CENTRAL4 && (p->mesh == OSBLI_MESH_GENERAL && p->ndim > 1)) {
         snprintf(buf, nb, "the central path takes separable meshes of uniform spacing");
         return -1;

@@ -195,10 +195,48 @@ __device__ __forceinline__ double recon3_z(double fm1, double f0, double fp1, do
     return (a0 * q0 + a1 * q1) * rcp64(a0 + a1);
 }
 
+// WENO-7Z (seventh-order WENO-Z, the highest order of section 5.2) at
+// x_{i+1/2} from f_{i-3..i+3}: four candidate stencils S_r = {i-r .. i-r+3},
+// each the cell-average reconstruction of its cubic evaluated at x_{i+1/2};
+// Jiang-Shu indicator of that cubic over cell i,
+//   beta_r = A_r^2/36 + (13/12) B_r^2 + (781/720) C_r^2
+// with A_r, B_r, C_r six, two and six times the cubic's first, second and
+// third Taylor coefficients about the cell centre (A with the third folded
+// in), written on the first differences d1..d6 of the seven values and taken
+// times 4 (with 4 eps, which leaves the ratios unchanged); optimal weights
+// (4/35, 18/35, 12/35, 1/35), tau_7 = |beta_0 + 3 beta_1 - 3 beta_2 -
+// beta_3|, alpha_r = d_r (1 + (tau/(beta_r + eps))^2); the four ratios
+// share one division and the normalisation takes another.
+__device__ __forceinline__ double recon7_z(double fm3, double fm2, double fm1, double f0, double fp1, double fp2,
+                                           double fp3, double eps) {
+    const double d1 = fm2 - fm3, d2 = fm1 - fm2, d3 = f0 - fm1, d4 = fp1 - f0, d5 = fp2 - fp1, d6 = fp3 - fp2;
+    const double q0 = f0 + 0.75 * d4 - (1.0 / 3.0) * d5 + (1.0 / 12.0) * d6;
+    const double q1 = f0 + (1.0 / 12.0) * d3 + 0.5 * d4 - (1.0 / 12.0) * d5;
+    const double q2 = f0 - (1.0 / 12.0) * d2 + (1.0 / 3.0) * d3 + 0.25 * d4;
+    const double q3 = f0 + 0.25 * d1 - (5.0 / 6.0) * d2 + (13.0 / 12.0) * d3;
+    auto ind = [](double a, double b, double c) {
+        return ((1.0 / 9.0) * a) * a + ((13.0 / 3.0) * b) * b + ((781.0 / 180.0) * c) * c;
+    };
+    const double b0 = ind(11.0 * d4 - 7.0 * d5 + 2.0 * d6, 3.0 * d5 - 2.0 * d4 - d6, d4 - 2.0 * d5 + d6);
+    const double b1 = ind(2.0 * d3 + 5.0 * d4 - d5, d4 - d3, d3 - 2.0 * d4 + d5);
+    const double b2 = ind(5.0 * d3 + 2.0 * d4 - d2, d4 - d3, d2 - 2.0 * d3 + d4);
+    const double b3 = ind(2.0 * d1 - 7.0 * d2 + 11.0 * d3, d1 - 3.0 * d2 + 2.0 * d3, d1 - 2.0 * d2 + d3);
+    const double tau = fabs(b0 + 3.0 * b1 - 3.0 * b2 - b3);
+    const double eps4 = 4.0 * eps;
+    const double e0 = b0 + eps4, e1 = b1 + eps4, e2 = b2 + eps4, e3 = b3 + eps4;
+    const double e01 = e0 * e1, e23 = e2 * e3;
+    const double tq = tau * rcp64(e01 * e23);
+    const double x0 = tq * (e1 * e23), x1 = tq * (e0 * e23), x2 = tq * (e01 * e3), x3 = tq * (e01 * e2);
+    const double a0 = (4.0 / 35.0) * (1.0 + x0 * x0), a1 = (18.0 / 35.0) * (1.0 + x1 * x1);
+    const double a2 = (12.0 / 35.0) * (1.0 + x2 * x2), a3 = (1.0 / 35.0) * (1.0 + x3 * x3);
+    return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) * rcp64((a0 + a1) + (a2 + a3));
+}
+
 // LLF split of one characteristic field over the six points and the two
 // reconstructions: ghat = recon+(g+_{i-2..i+2}) + recon-(g-_{i+3..i-1})
 // (TENO6: recon+(g+_{i-2..i+3}) + recon-(g-_{i+3..i-2}); WENO-3Z:
-// recon+(g+_{i-1..i+1}) + recon-(g-_{i+2..i})).  Takes V, gh = g/2 and
+// recon+(g+_{i-1..i+1}) + recon-(g-_{i+2..i}); WENO-7Z reads W = 8 points,
+// recon+(g+_{i-3..i+3}) + recon-(g-_{i+4..i-2})).  Takes V, gh = g/2 and
 // ha = alpha/2, so g+- = (g +- alpha V)/2 = gh +- ha V.
 // SHARED: one division serves both sides: with D+- = prod_r(beta_r+eps),
 // tau+/D+ = tau+ D- / (D+ D-) and likewise for the other side (D+ D- >=
@@ -206,16 +244,20 @@ __device__ __forceinline__ double recon3_z(double fm1, double f0, double fp1, do
 // saves five divisions per interface but keeps both sides' indicators live
 // at once, which the marching sweeps can afford and the lane-per-interface
 // sweep cannot (it spills), so that one divides per side.
-template <int SCHEME, bool SHARED>
-__device__ __forceinline__ double split_recon(const double (&V)[6], const double (&gh)[6], double ha,
+template <int SCHEME, bool SHARED, int W>
+__device__ __forceinline__ double split_recon(const double (&V)[W], const double (&gh)[W], double ha,
                                               const Phys &ph, bool *kept = nullptr) {
-    double gp[6], gm[6];
+    double gp[W], gm[W];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < W; ++k) {
         gp[k] = gh[k] + ha * V[k];
         gm[k] = gh[k] - ha * V[k];
     }
-    if constexpr (SCHEME == OSBLI_TENO6) {
+    if constexpr (SCHEME == OSBLI_WENOZ7) {
+        // eight points i-3..i+4: recon+(g+_{i-3..i+3}) + recon-(g-_{i+4..i-2})
+        return recon7_z(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], gp[6], ph.eps) +
+               recon7_z(gm[7], gm[6], gm[5], gm[4], gm[3], gm[2], gm[1], ph.eps);
+    } else if constexpr (SCHEME == OSBLI_TENO6) {
         return recon6_teno(gp[0], gp[1], gp[2], gp[3], gp[4], gp[5], ph.CT, ph.eps, ph.teno_fast, kept) +
                recon6_teno(gm[5], gm[4], gm[3], gm[2], gm[1], gm[0], ph.CT, ph.eps, ph.teno_fast, kept);
     } else if constexpr (SCHEME == OSBLI_WENOJS5) {
@@ -245,24 +287,26 @@ __device__ __forceinline__ double split_recon(const double (&V)[6], const double
     }
 }
 
-// Interface flux in the local frame (unit |S|).  Outputs: mass, normal
+// Interface flux in the local frame (unit |S|) from the W stencil points
+// i-W/2+1 .. i+W/2 (W = 6, or 8 for WENO-7Z).  Outputs: mass, normal
 // momentum, tangential momenta, energy.
-template <int ND, int SCHEME, bool SHARED = true>
-__device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph, double &Fr, double &Fn,
+template <int ND, int SCHEME, bool SHARED = true, int W = 6>
+__device__ __forceinline__ void char_flux(const Loc<ND> (&P)[W], const Phys &ph, double &Fr, double &Fn,
                                           double (&Ft)[2], double &FE, bool *kept = nullptr) {
     constexpr int NT = ND - 1;  // tangents
+    constexpr int L = W / 2 - 1, R = W / 2;  // the nodes either side of the interface
     // averaged state at the half node (Roe, or arithmetic mean with unit weights)
     double sl = 1.0, sr = 1.0;
     if (ph.roe) {
-        sl = sqrt64(P[2].r);
-        sr = sqrt64(P[3].r);
+        sl = sqrt64(P[L].r);
+        sr = sqrt64(P[R].r);
     }
     const double iw = rcp64(sl + sr);
-    const double un = (sl * (P[2].mn * P[2].ri) + sr * (P[3].mn * P[3].ri)) * iw;
+    const double un = (sl * (P[L].mn * P[L].ri) + sr * (P[R].mn * P[R].ri)) * iw;
     double ut[2] = {0.0, 0.0};
 #pragma unroll
-    for (int s = 0; s < NT; ++s) ut[s] = (sl * (P[2].mt[s] * P[2].ri) + sr * (P[3].mt[s] * P[3].ri)) * iw;
-    const double Hh = (sl * ((P[2].E + P[2].p) * P[2].ri) + sr * ((P[3].E + P[3].p) * P[3].ri)) * iw;
+    for (int s = 0; s < NT; ++s) ut[s] = (sl * (P[L].mt[s] * P[L].ri) + sr * (P[R].mt[s] * P[R].ri)) * iw;
+    const double Hh = (sl * ((P[L].E + P[L].p) * P[L].ri) + sr * ((P[R].E + P[R].p) * P[R].ri)) * iw;
     double K = un * un;
 #pragma unroll
     for (int s = 0; s < NT; ++s) K += ut[s] * ut[s];
@@ -274,9 +318,9 @@ __device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph,
     // directly from hu = u_n/2 and the halved combinations A, B below, so no
     // product is scaled by 1/2 afterwards (powers of two: exact).
     const double hb = 0.5 * b, hia = 0.5 * ia;
-    double hu[6], A[6], B[6], am[6], ap[6], a0 = 0.0;
+    double hu[W], A[W], B[W], am[W], ap[W], a0 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < W; ++k) {
         hu[k] = P[k].mn * (0.5 * P[k].ri);
         double um = un * P[k].mn;
 #pragma unroll
@@ -289,43 +333,43 @@ __device__ __forceinline__ void char_flux(const Loc<ND> (&P)[6], const Phys &ph,
     }
     double aminus = am[0], aplus = ap[0];
 #pragma unroll
-    for (int k = 1; k < 6; ++k) {
+    for (int k = 1; k < W; ++k) {
         aminus = fmax(aminus, am[k]);
         aplus = fmax(aplus, ap[k]);
     }
-    double V[6], gh[6];
+    double V[W], gh[W];
     // field u_n - a: V = (A + B)|full / 2, g = u_n V + p (b u_n - (b un + 1/a)) / 2
     const double cm = 0.25 * (b * un + ia), cp = 0.25 * (b * un - ia), hbun = hb * un;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < W; ++k) {
         V[k] = A[k] + B[k];
         gh[k] = hu[k] * V[k] + P[k].p * (hb * hu[k] - cm);
     }
-    const double h0 = split_recon<SCHEME, SHARED>(V, gh, 0.5 * aminus, ph, kept);
+    const double h0 = split_recon<SCHEME, SHARED, W>(V, gh, 0.5 * aminus, ph, kept);
     // field u_n + a
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < W; ++k) {
         V[k] = A[k] - B[k];
         gh[k] = hu[k] * V[k] + P[k].p * (hb * hu[k] - cp);
     }
-    const double h4 = split_recon<SCHEME, SHARED>(V, gh, 0.5 * aplus, ph, kept);
+    const double h4 = split_recon<SCHEME, SHARED, W>(V, gh, 0.5 * aplus, ph, kept);
     // entropy field: V = rho - b (K rho - u.m + E), g = u_n V + p b (un - u_n)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < W; ++k) {
         V[k] = P[k].r - 2.0 * A[k];
         gh[k] = hu[k] * V[k] + P[k].p * (hbun - b * hu[k]);
     }
-    const double h1 = split_recon<SCHEME, SHARED>(V, gh, a0, ph, kept);
+    const double h1 = split_recon<SCHEME, SHARED, W>(V, gh, a0, ph, kept);
     // shear fields: V = m_t - ut rho, g = u_n V
     double ht[2] = {0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < NT; ++s) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < W; ++k) {
             V[k] = P[k].mt[s] - ut[s] * P[k].r;
             gh[k] = hu[k] * V[k];
         }
-        ht[s] = split_recon<SCHEME, SHARED>(V, gh, a0, ph, kept);
+        ht[s] = split_recon<SCHEME, SHARED, W>(V, gh, a0, ph, kept);
     }
     // back to physical space: F = R ghat
     const double hs = h0 + h1 + h4;

@@ -33,6 +33,7 @@ hipError_t launch_convective(const Grid &g, const Phys &ph, const Metrics &m, co
         case OSBLI_WENOJS5:
             return cvl::launch_convective_s<OSBLI_WENOJS5>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
         case OSBLI_WENOZ3: return cvl::launch_convective_s<OSBLI_WENOZ3>(g, ph, m, U, R, flags, dir, first, mask, sq, s);
+        case OSBLI_WENOZ7: return cvl::launch_convective_wz7(g, ph, m, U, R, flags, dir, first, mask, sq, s);
         default: return hipErrorInvalidValue;
     }
 }

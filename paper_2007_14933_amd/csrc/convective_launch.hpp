@@ -91,6 +91,8 @@ extern template hipError_t launch_convective_s<OSBLI_TENO5> OSBLI_CONVECTIVE_SIG
 extern template hipError_t launch_convective_s<OSBLI_TENO6> OSBLI_CONVECTIVE_SIG;
 extern template hipError_t launch_convective_s<OSBLI_WENOJS5> OSBLI_CONVECTIVE_SIG;
 extern template hipError_t launch_convective_s<OSBLI_WENOZ3> OSBLI_CONVECTIVE_SIG;
+// seventh-order WENO-Z: kernels of its own (eight-point stencils)
+hipError_t launch_convective_wz7 OSBLI_CONVECTIVE_SIG;
 
 }  // namespace cvl
 }  // namespace osbli

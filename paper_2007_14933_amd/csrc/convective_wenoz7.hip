@@ -1,0 +1,121 @@
+// Convective sweeps with seventh-order WENO-Z (section 5.2), plain FP64
+// form, separable meshes.  The reconstruction reads eight points per
+// interface, so this scheme has kernels of its own: a wave owns 64
+// consecutive interfaces of one line (63 new nodes), each lane evaluates the
+// characteristic flux of its interface from the eight points i-3 .. i+4
+// read directly from the state, and the node between two lanes takes the
+// difference of their fluxes (the left one by a lane shuffle).  At the two
+// outermost interfaces of a line the stencil reaches one node past the
+// three ghost layers: that node is the wrapped interior node on periodic
+// lines and the third ghost layer again otherwise.
+#include "convective_launch.hpp"
+
+namespace osbli {
+namespace cvl {
+namespace {
+
+template <int ND, int DIR>
+__global__ void __launch_bounds__(64 * kWaves)
+k_sweep_wz7(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t chunks,
+            int64_t waves, int first, unsigned *flags) {
+    constexpr int NC = ND + 2;
+    constexpr int NT = ND - 1;
+    constexpr int O1 = DIR == 0 ? 1 : 0;
+    constexpr int O2 = DIR == 2 ? 1 : 2;
+    const int64_t w = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (w >= waves) return;  // wave-uniform; no block-wide synchronisation below
+    const int lane = threadIdx.x & 63;
+    const int64_t line = w / chunks, chunk = w - line * chunks;
+    const int64_t N = g.n[DIR];
+    // this lane's interface p + 1/2 (p = -1 .. N-1); lanes past the line end
+    // evaluate the last interface and write nothing
+    const int64_t praw = chunk * 63 - 1 + lane;
+    const int64_t p = praw < N ? praw : N - 1;
+    int64_t q[3];
+    q[DIR] = 0;
+    q[O1] = line % g.n[O1];
+    q[O2] = line / g.n[O1];
+    const int64_t base = ext_index(g, q[0], q[1], q[2]);
+    const int64_t st = g.es[DIR], cs = g.enpts;
+    const bool per = g.periodic[DIR] != 0;
+    const int64_t gl = g.h[DIR];
+    bool bad = false;
+    Loc<ND> P[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        int64_t pos = p - 3 + k;
+        if (pos < -gl) pos = per ? pos + N : -gl;
+        if (pos > N - 1 + gl) pos = per ? pos - N : N - 1 + gl;
+        Pt<ND> pt;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pt.U[c] = U[base + pos * st + c * cs];
+        finish_point<ND>(ph, pt, bad);
+        P[k].r = pt.U[0];
+        P[k].mn = pt.U[1 + DIR];
+        if (NT >= 1) P[k].mt[0] = pt.U[1 + Axes<ND, DIR>::T1];
+        if (NT >= 2) P[k].mt[1] = pt.U[1 + Axes<ND, DIR>::T2];
+        P[k].E = pt.U[ND + 1];
+        P[k].p = pt.p;
+        P[k].a = pt.a;
+        P[k].ri = pt.ri;
+    }
+    double Fr, Fn, Ft[2], FE;
+    char_flux<ND, OSBLI_WENOZ7, true, 8>(P, ph, Fr, Fn, Ft, FE);
+    double F[NC];
+    F[0] = Fr;
+    F[1 + DIR] = Fn;
+    if (NT >= 1) F[1 + Axes<ND, DIR>::T1] = Ft[0];
+    if (NT >= 2) F[1 + Axes<ND, DIR>::T2] = Ft[1];
+    F[NC - 1] = FE;
+    double Fl[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Fl[c] = __shfl_up(F[c], 1, 64);
+    // node p: between the interfaces of lanes lane - 1 and lane
+    if (lane >= 1 && praw >= 0 && praw < N) {
+        const double sc = m.invh[DIR][p];
+        const int64_t oi = int_index(g, q[0], q[1], q[2]) + p * g.is[DIR];
+        double v[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = -sc * (F[c] - Fl[c]);
+        add_residual<NC>(R, g.nint, oi, v, first);
+    }
+    if (bad) atomicOr(flags, kFlagNonPhys);
+}
+
+template <int ND, int DIR>
+hipError_t launch_wz7_dir(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
+                          unsigned *flags, int first, hipStream_t s) {
+    constexpr int O1 = DIR == 0 ? 1 : 0;
+    constexpr int O2 = DIR == 2 ? 1 : 2;
+    const int64_t lines = g.n[O1] * g.n[O2];
+    const int64_t chunks = (g.n[DIR] + 62) / 63;
+    const int64_t waves = lines * chunks;
+    const int64_t nb = (waves + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL((k_sweep_wz7<ND, DIR>), dim3((unsigned)nb), dim3(64 * kWaves), 0, s, U, R, g, ph, m, chunks,
+                       waves, first, flags);
+    return hipGetLastError();
+}
+
+template <int ND>
+hipError_t launch_wz7_nd(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
+                         unsigned *flags, int dir, int first, hipStream_t s) {
+    if (dir == 0) return launch_wz7_dir<ND, 0>(g, ph, m, U, R, flags, first, s);
+    if (dir == 1) return launch_wz7_dir<ND, (ND >= 2 ? 1 : 0)>(g, ph, m, U, R, flags, first, s);
+    return launch_wz7_dir<ND, (ND >= 3 ? 2 : 0)>(g, ph, m, U, R, flags, first, s);
+}
+
+}  // namespace
+
+// separable meshes only (validated at set-up); no routing, FP64 form
+hipError_t launch_convective_wz7(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
+                                 unsigned *flags, int dir, int first, const uint8_t *, int64_t, hipStream_t s) {
+    if (m.general) return hipErrorInvalidValue;
+    switch (g.nd) {
+        case 1: return launch_wz7_nd<1>(g, ph, m, U, R, flags, dir, first, s);
+        case 2: return launch_wz7_nd<2>(g, ph, m, U, R, flags, dir, first, s);
+        default: return launch_wz7_nd<3>(g, ph, m, U, R, flags, dir, first, s);
+    }
+}
+
+}  // namespace cvl
+}  // namespace osbli

@@ -73,6 +73,12 @@ def test_workspace_sizes(lib):
     (lambda p: (setattr(p, "scheme", B.TENO6), setattr(p, "form", B.FORM_MIXED)), "precision form: fifth order only"),
     (lambda p: (setattr(p, "scheme", B.WENOJS5), setattr(p, "sensor", 1)), "routing needs TENO5"),
     (lambda p: setattr(p, "rk", 3), "Runge-Kutta scheme"),
+    (lambda p: setattr(p, "scheme", 7), "scheme past WENO-7Z"),
+    (lambda p: (setattr(p, "scheme", B.WENOZ7), setattr(p, "form", B.FORM_MIXED)), "precision form: WENO-7Z"),
+    (lambda p: (setattr(p, "scheme", B.WENOZ7), setattr(p, "sensor", 1)), "routing needs TENO5 (WENO-7Z)"),
+    (lambda p: (setattr(p, "scheme", B.WENOZ7), setattr(p, "mesh", B.MESH_GENERAL)), "WENO-7Z general mesh"),
+    (lambda p: (setattr(p, "scheme", B.WENOZ7), p.bc_kind[1].__setitem__(0, B.ISOTHERMAL_WALL),
+                p.bc_kind[1].__setitem__(1, B.ISOTHERMAL_WALL)), "WENO-7Z with walls"),
     (lambda p: (p.bc_kind[0].__setitem__(0, 5), p.bc_kind[0].__setitem__(1, 5)), "bc kind"),
 ])
 def test_invalid_parameters_rejected_without_device(lib, mutate, why):

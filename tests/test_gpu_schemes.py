@@ -1,12 +1,15 @@
 """Parity of the HIP path with the FP64 oracle for the further schemes:
 sixth-order TENO with the strong-stability-preserving RK3 (the paper's
 production configuration, sections 2.5 and 2.7), the original WENO-JS5
-weights, third-order WENO-Z on the Shu-Osher case with Dirichlet ends
-(section 5.2), and the five-stage fourth-order RK.  Same bars as the plain
-parity tests: max normwise relative difference per conserved quantity
-<= 1e-11 after the run, single residuals <= 1e-13 of the flux scale, ghosts
-<= 1e-13; the RK coefficients, which both sides derive independently, agree
-to 1e-15.  Every case prints its name before touching the GPU."""
+weights, third- and seventh-order WENO-Z on the Shu-Osher case with
+Dirichlet ends (section 5.2), and the five-stage fourth-order RK.  Same
+bars as the plain parity tests: max normwise relative difference per
+conserved quantity <= 1e-11 after the run (for the ill-conditioned runs
+listed in SENSITIVE, four times the oracle's own response to a 1e-14
+perturbation of the state), single residuals <= 1e-13 of the flux scale,
+ghosts <= 1e-13; the RK coefficients, which both sides derive
+independently, agree to 1e-15.  Every case prints its name before touching
+the GPU."""
 import math
 
 import numpy as np
@@ -53,6 +56,13 @@ def cases():
                                                 rk=I.RK4), dict(nsteps=30))
     wf = I.wall_flow(24, 20, 16, L=(10.0, 8.0, 6.0))
     c["wall_24x20x16_teno6_ssp"] = (wf.with_(**T6, **SSP), dict(nsteps=60))
+    # seventh-order WENO-Z (eight-point stencils, the outer node past the
+    # ghost layers): Shu-Osher with Dirichlet ends, a periodic 1D wave with
+    # RK4, a 2D Riemann problem with extrapolated ends, the viscous TGV
+    c["shuosher320_wenoz7"] = (I.shu_osher(320, scheme=I.WENOZ7), dict(nsteps=2000, dt_fixed=2e-4))
+    c["dwave1d_64_wenoz7_rk4"] = (I.density_wave_1d(64, scheme=I.WENOZ7, rk=I.RK4), dict(nsteps=200))
+    c["riemann2d_40_wenoz7"] = (I.riemann2d(40, 13, scheme=I.WENOZ7), dict(nsteps=100))
+    c["tgv16_wenoz7"] = (I.tgv(16, scheme=I.WENOZ7), dict(nsteps=40))
     X, Y = I.sinusoidal_mesh(40, 26)
     dw = I.density_wave(40, mesh="uniform")
     U0 = np.zeros(I.ext_shape(2, (40, 26, 1)))
@@ -68,6 +78,27 @@ def cases():
 CASES = cases()
 
 
+# Runs whose outcome is ill-conditioned in the state: on 2D Riemann problems
+# the WENO-7Z weights amplify rounding (oracle against oracle, a 1e-15
+# relative perturbation of the initial state moves seed 5 by 1.2e-9 after
+# 100 steps, where WENO-Z5 moves by 1e-12), so rounding-level differences
+# between two correct implementations grow far past 1e-11.  Their bar is
+# the oracle's own response to a 1e-14 perturbation (a few tens of ulps, the
+# size of the rounding both sides make in a step), with a margin of 4.
+SENSITIVE = {"riemann2d_40_wenoz7"}
+
+
+def state_sensitivity(prob, kw, draws=2, amp=1e-14, seed=3):
+    rng = np.random.default_rng(seed)
+    Ua, _ = oracle_run(prob, **kw)
+    worst = 0.0
+    for _ in range(draws):
+        U0 = prob.U0 * (1.0 + amp * rng.standard_normal(prob.U0.shape))
+        Ub, _ = oracle_run(prob.with_(U0=U0), **kw)
+        worst = max(worst, float(normwise_rel(O.interior(prob, Ub), O.interior(prob, Ua)).max()))
+    return worst
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_run_parity(name):
     prob, kw = CASES[name]
@@ -76,11 +107,13 @@ def test_run_parity(name):
     Uo, to = oracle_run(prob, **kw)
     assert abs(tg - to) <= 1e-12 * max(1.0, abs(to)), (tg, to)
     err = normwise_rel(O.interior(prob, Ug), O.interior(prob, Uo))
-    say("   t=%.6g  normwise rel diff per component:" % tg, err)
-    assert np.all(np.isfinite(err)) and err.max() <= TOL_RUN, err
+    tol = max(TOL_RUN, 4.0 * state_sensitivity(prob, kw)) if name in SENSITIVE else TOL_RUN
+    say("   t=%.6g  normwise rel diff per component:" % tg, err, "bar %.2e" % tol)
+    assert np.all(np.isfinite(err)) and err.max() <= tol, err
 
 
-@pytest.mark.parametrize("name", [n for n in CASES if not n.startswith("shuosher")] + ["shuosher320_wenoz3"])
+@pytest.mark.parametrize("name", [n for n in CASES if not n.startswith("shuosher")]
+                         + ["shuosher320_wenoz3", "shuosher320_wenoz7"])
 def test_residual_and_ghosts(name):
     prob, _ = CASES[name]
     say("[gpu schemes residual]", name, prob.n)
