@@ -1,10 +1,11 @@
 // Convective sweeps with seventh-order WENO-Z (section 5.2), plain FP64
 // form, separable meshes.  The reconstruction reads eight points per
-// interface, so this scheme has kernels of its own: a wave owns 64
+// interface, so this scheme has kernels of its own.  Along x a wave owns 64
 // consecutive interfaces of one line (63 new nodes), each lane evaluates the
 // characteristic flux of its interface from the eight points i-3 .. i+4
 // read directly from the state, and the node between two lanes takes the
-// difference of their fluxes (the left one by a lane shuffle).  At the two
+// difference of their fluxes (the left one by a lane shuffle); along y and
+// z the lanes lie across 64 consecutive x lines and march.  At the two
 // outermost interfaces of a line the stencil reaches one node past the
 // three ghost layers: that node is the wrapped interior node on periodic
 // lines and the third ghost layer again otherwise.
@@ -82,13 +83,98 @@ k_sweep_wz7(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys p
     if (bad) atomicOr(flags, kFlagNonPhys);
 }
 
+// y and z: lanes across 64 consecutive lines (consecutive x, so every point
+// load of the wave is one contiguous row), each lane marching its line over
+// a segment: the flux of interface f from its eight points, the node f from
+// this flux and the previous one (kept in registers)
+template <int ND, int DIR>
+__global__ void __launch_bounds__(64 * kWaves)
+k_sweep_wz7_march(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t seg,
+                  int64_t nseg, int64_t waves, int first, unsigned *flags) {
+    constexpr int NC = ND + 2;
+    constexpr int NT = ND - 1;
+    constexpr int O1 = DIR == 0 ? 1 : 0;
+    constexpr int O2 = DIR == 2 ? 1 : 2;
+    const int64_t w = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (w >= waves) return;  // wave-uniform; no block-wide synchronisation below
+    const int lane = threadIdx.x & 63;
+    const int64_t sg = w % nseg, line0 = (w / nseg) * 64;
+    const int64_t lines = g.n[O1] * g.n[O2];
+    const int64_t line = line0 + lane;
+    const bool active = line < lines;
+    const int64_t lc = active ? line : lines - 1;
+    const int64_t N = g.n[DIR];
+    const int64_t p0 = sg * seg, p1 = p0 + seg < N ? p0 + seg : N;
+    int64_t q[3];
+    q[DIR] = 0;
+    q[O1] = lc % g.n[O1];
+    q[O2] = lc / g.n[O1];
+    const int64_t base = ext_index(g, q[0], q[1], q[2]);
+    const int64_t ibase = int_index(g, q[0], q[1], q[2]);
+    const int64_t st = g.es[DIR], cs = g.enpts;
+    const bool per = g.periodic[DIR] != 0;
+    const int64_t gl = g.h[DIR];
+    const double *__restrict__ ih = m.invh[DIR];
+    bool bad = false;
+    double Fp[NC];
+    for (int64_t f = p0 - 1; f < p1; ++f) {
+        Loc<ND> P[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int64_t pos = f - 3 + k;
+            if (pos < -gl) pos = per ? pos + N : -gl;
+            if (pos > N - 1 + gl) pos = per ? pos - N : N - 1 + gl;
+            Pt<ND> pt;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) pt.U[c] = U[base + pos * st + c * cs];
+            finish_point<ND>(ph, pt, bad);
+            P[k].r = pt.U[0];
+            P[k].mn = pt.U[1 + DIR];
+            if (NT >= 1) P[k].mt[0] = pt.U[1 + Axes<ND, DIR>::T1];
+            if (NT >= 2) P[k].mt[1] = pt.U[1 + Axes<ND, DIR>::T2];
+            P[k].E = pt.U[ND + 1];
+            P[k].p = pt.p;
+            P[k].a = pt.a;
+            P[k].ri = pt.ri;
+        }
+        double Fr, Fn, Ft[2], FE;
+        char_flux<ND, OSBLI_WENOZ7, true, 8>(P, ph, Fr, Fn, Ft, FE);
+        double F[NC];
+        F[0] = Fr;
+        F[1 + DIR] = Fn;
+        if (NT >= 1) F[1 + Axes<ND, DIR>::T1] = Ft[0];
+        if (NT >= 2) F[1 + Axes<ND, DIR>::T2] = Ft[1];
+        F[NC - 1] = FE;
+        if (f >= p0 && active) {
+            const double sc = ih[f];
+            double v[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[c] = -sc * (F[c] - Fp[c]);
+            add_residual<NC>(R, g.nint, ibase + f * g.is[DIR], v, first);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Fp[c] = F[c];
+    }
+    if (bad) atomicOr(flags, kFlagNonPhys);
+}
+
 template <int ND, int DIR>
 hipError_t launch_wz7_dir(const Grid &g, const Phys &ph, const Metrics &m, const double *U, double *R,
                           unsigned *flags, int first, hipStream_t s) {
     constexpr int O1 = DIR == 0 ? 1 : 0;
     constexpr int O2 = DIR == 2 ? 1 : 2;
     const int64_t lines = g.n[O1] * g.n[O2];
-    const int64_t chunks = (g.n[DIR] + 62) / 63;
+    const int64_t N = g.n[DIR];
+    if (DIR != 0) {
+        const int64_t seg = default_segment(N, lines);
+        const int64_t nseg = (N + seg - 1) / seg;
+        const int64_t waves = ((lines + 63) / 64) * nseg;
+        const int64_t nb = (waves + kWaves - 1) / kWaves;
+        hipLaunchKernelGGL((k_sweep_wz7_march<ND, DIR>), dim3((unsigned)nb), dim3(64 * kWaves), 0, s, U, R, g, ph, m,
+                           seg, nseg, waves, first, flags);
+        return hipGetLastError();
+    }
+    const int64_t chunks = (N + 62) / 63;
     const int64_t waves = lines * chunks;
     const int64_t nb = (waves + kWaves - 1) / kWaves;
     hipLaunchKernelGGL((k_sweep_wz7<ND, DIR>), dim3((unsigned)nb), dim3(64 * kWaves), 0, s, U, R, g, ph, m, chunks,
