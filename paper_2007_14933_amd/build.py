@@ -31,10 +31,18 @@ FLAGS = [
 # and training arithmetic follow their FP64 definitions operation by operation
 NO_CONTRACT = {"sensor.hip"}
 
+# translation units built without loop strength reduction: in the z-marching
+# viscous kernel it turns every address stream of the march into a 64-bit
+# induction variable of its own, which spills the registers the loads issued
+# ahead need
+NO_LSR = {"viscous.hip"}
+
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     extra = ["-ffp-contract=off"] if src in NO_CONTRACT else []
+    if src in NO_LSR:
+        extra += ["-mllvm", "-disable-lsr"]
     cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

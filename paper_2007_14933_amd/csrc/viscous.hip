@@ -188,10 +188,46 @@ k_visc_flux(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys p
 constexpr int kZX = 64, kZY = 8, kZC = 32;
 constexpr int kHX = kZX + 4, kHY = kZY + 4;
 
+// the tile's halo: two rows above and below the tile (kHX wide) and two
+// columns either side of its kZY rows; one position per thread
+constexpr int kHalo = 4 * kHX + 4 * kZY;
+static_assert(kHalo <= kZX * kZY, "one halo position per thread");
+
+__device__ __forceinline__ void halo_pos(int h, int &cx, int &cy) {
+    if (h < 4 * kHX) {
+        const int r = h / kHX;
+        cx = h - r * kHX;
+        cy = r < 2 ? r : kZY + r;
+    } else {
+        const int r = h - 4 * kHX, s = r & 3;
+        cy = 2 + (r >> 2);
+        cx = s < 2 ? s : kZX + s;
+    }
+}
+
+// primitives from the conserved values of one node (the arithmetic of phi_at)
+__device__ __forceinline__ void phi_of(const double (&u)[5], const Phys &ph, double (&phi)[4]) {
+    const double ri = 1.0 / u[0];
+    double ke = 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        phi[m] = u[1 + m] * ri;
+        ke += u[1 + m] * u[1 + m];
+    }
+    const double p = ph.gm1 * (u[4] - 0.5 * ke * ri);
+    phi[3] = ph.gamma * ph.M2 * p * ri;
+}
+
 // Tiles are placed on the XCDs as the node tiles are (one contiguous run of
-// tiles per XCD), so that the halo columns shared by neighbouring tiles are
-// read through one L2.
-__global__ void __launch_bounds__(kZX * kZY, 4)
+// tiles per XCD).  The loads are issued ahead of their use: a column's
+// conserved values at z+3 one step ahead, the halo of plane z+2 two steps
+// ahead, together with the columns' own z+2 loads of the neighbouring tiles,
+// which read the same nodes at that time, so the halo comes from the L2 (a
+// halo read at its own plane was served from HBM: the XCD had streamed two
+// planes of every resident tile through the L2 since).  One block per CU
+// (at most 256 registers per lane): at four waves per SIMD the loads held in
+// flight spilled.
+__global__ void __launch_bounds__(kZX * kZY, 2)
 k_visc_flux_zm(const double *__restrict__ U, double *__restrict__ G, Grid g, Phys ph, Metrics m, int tx_n,
                int ty_n, int ntiles, int per) {
     constexpr int NV = 4;
@@ -206,40 +242,59 @@ k_visc_flux_zm(const double *__restrict__ U, double *__restrict__ G, Grid g, Phy
     const int64_t z0 = (int64_t)bz * kZC;
     const int64_t z1 = z0 + kZC < Nz ? z0 + kZC : Nz;
     const bool own = x < Nx && y < Ny;
-    const int64_t xc = x < Nx ? x : Nx - 1, yc = y < Ny ? y : Ny - 1;
     const int64_t cs = g.enpts, sz = g.es[2];
     const bool perx = g.periodic[0] != 0, pery = g.periodic[1] != 0, perz = g.periodic[2] != 0;
     const bool intx = perx || (x >= 2 && x <= Nx - 3);
     const bool inty = pery || (y >= 2 && y <= Ny - 3);
-    const int64_t ecol = ext_index(g, xc, yc, 0);
+    // a column beyond the grid holds the ghost (or, further out, the last
+    // ghost) node of its position: such values reach only unused stencil slots
+    const int64_t ecol = ext_index(g, x < Nx + 2 ? x : Nx + 2, y < Ny + 2 ? y : Ny + 2, 0);
+    const bool hal = tid < kHalo;
+    int hx = 0, hy = 0;
+    halo_pos(hal ? tid : 0, hx, hy);
+    int64_t hgx = x0 - 2 + hx, hgy = y0 - 2 + hy;
+    hgx = hgx > Nx + 2 ? Nx + 2 : hgx;
+    hgy = hgy > Ny + 2 ? Ny + 2 : hgy;
+    const int64_t hcol = ext_index(g, hgx, hgy, 0);
 
     double w[5][NV];  // primitives of this column at z-2 .. z+2
 #pragma unroll
     for (int k = 1; k < 5; ++k) phi_at<3>(U, ecol + (z0 - 3 + k) * sz, cs, ph, w[k]);
+    double ou[5];     // conserved values of this column at z+2
+    double hu[2][5];  // conserved values at the halo position, planes z and z+1
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        ou[c] = U[ecol + (z0 + 2) * sz + c * cs];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) hu[k][c] = hal ? U[hcol + (z0 + k) * sz + c * cs] : 1.0;
+    }
 
+#pragma unroll 1
     for (int64_t z = z0; z < z1; ++z) {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int v = 0; v < NV; ++v) w[k][v] = w[k + 1][v];
-        phi_at<3>(U, ecol + (z + 2) * sz, cs, ph, w[4]);
-        const int b = (int)((z - z0) & 1);
-        // the tile's own nodes come from the columns' windows (w[2] is this
-        // plane); only the halo and the nodes beyond the grid are loaded
-        for (int t = tid; t < kHX * kHY; t += kZX * kZY) {
-            const int cx = t % kHX, cy = t / kHX;
-            int64_t gx = x0 - 2 + cx, gy = y0 - 2 + cy;
-            if (cx >= 2 && cx < kZX + 2 && cy >= 2 && cy < kZY + 2 && gx < Nx && gy < Ny) continue;
-            gx = gx > Nx + 2 ? Nx + 2 : gx;
-            gy = gy > Ny + 2 ? Ny + 2 : gy;
-            double f[NV];
-            phi_at<3>(U, ext_index(g, gx, gy, z), cs, ph, f);
+        phi_of(ou, ph, w[4]);
+        double hn[5];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) tile[b][v][cy][cx] = f[v];
+        for (int c = 0; c < 5; ++c) {
+            ou[c] = U[ecol + (z + 3) * sz + c * cs];  // z + 3 <= Nz + 2: the last ghost plane
+            hn[c] = hal ? U[hcol + (z + 2) * sz + c * cs] : 1.0;
         }
-        if (own) {
+        const int b = (int)((z - z0) & 1);
+        if (hal) {
+            double f[NV];
+            phi_of(hu[0], ph, f);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) tile[b][v][ty + 2][tx + 2] = w[2][v];
+            for (int v = 0; v < NV; ++v) tile[b][v][hy][hx] = f[v];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tile[b][v][ty + 2][tx + 2] = w[2][v];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            hu[0][c] = hu[1][c];
+            hu[1][c] = hn[c];
         }
         __syncthreads();
         if (own) {
