@@ -55,9 +55,11 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
     constexpr int NT = ND - 1;
     constexpr int O1 = DIR == 0 ? 1 : 0;
     constexpr int O2 = DIR == 2 ? 1 : 2;
-    // 1/h along the line: read only, so (with the wave-uniform segment) the
-    // per-node factor is a scalar load
-    const double *__restrict__ ih = m.invh[DIR];
+    // 1/h along the line, read only for the kernel's lifetime: read through
+    // the constant address space, the wave-uniform per-node factor is a
+    // scalar load (as a vector load, waiting for it waited for every vector
+    // memory operation issued before it)
+    const __attribute__((address_space(4))) double *ih = (const __attribute__((address_space(4))) double *)m.invh[DIR];
     const int64_t n1 = g.n[O1], n2 = g.n[O2], N = g.n[DIR];
     const int64_t lines = n1 * n2;
     const int lane = threadIdx.x & 63;
@@ -107,9 +109,17 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
                                              0, 0);
         }
     };
-    auto read_ahead = [&](int slot, Pt<ND> &w) {
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the slot's global-to-LDS load has landed
-        __builtin_amdgcn_sched_barrier(0);   // and no LDS read is scheduled above that wait
+    auto read_ahead = [&](int slot, Pt<ND> &w, bool after) {
+        // wait until the slot's global-to-LDS load has landed.  The vector
+        // memory counter drains in issue order, and after that load the
+        // previous step issued its NC residual loads (unless first) and its NC
+        // residual stores (every lane of an ahead-loading wave is active, and
+        // anything else the compiler adds only raises the count), so the wait
+        // leaves those stores in flight instead of waiting for them
+        if (!after) __builtin_amdgcn_s_waitcnt(0x0F70);           // vmcnt(0)
+        else if (first) __builtin_amdgcn_s_waitcnt(0x0F70 | NC);  // vmcnt(NC)
+        else __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * NC));       // vmcnt(2 NC)
+        __builtin_amdgcn_sched_barrier(0);  // and no LDS read is scheduled above that wait
 #pragma unroll
         for (int c = 0; c < NC; ++c) w.U[c] = ab[slot][c][lane];
         finish_point<ND>(ph, w, bad);
@@ -196,8 +206,9 @@ __device__ __forceinline__ void sweep_wave(const double *__restrict__ U, double 
 #pragma unroll
             for (int k = 0; k < 5; ++k) w[k] = w[k + 1];
             if (ahead) {
-                read_ahead((int)((f + 3) & 1), w[5]);
+                read_ahead((int)((f + 3) & 1), w[5], f > p0);
                 if (f + 1 < p1) load_ahead(f + 4, (int)((f + 4) & 1));
+                __builtin_amdgcn_sched_barrier(0);  // the residual loads stay behind the load
             } else {
                 fetch(f + 3, w[5]);
             }
