@@ -535,8 +535,10 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
     if (bad) atomicOr(flags, kFlagNonPhys);
 }
 
+// three waves per SIMD (168 registers); TENO6's four stencils spill there,
+// so it runs at two (180 registers, x sweep 0.87 -> 0.86 ms at 256^3)
 template <int ND, int SCHEME, bool MIX, bool ROUTE>
-__global__ void __launch_bounds__(64 * kWaves, 3)
+__global__ void __launch_bounds__(64 * kWaves, SCHEME == OSBLI_TENO6 ? 2 : 3)
 k_sweep_xl(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys ph, Metrics m, int64_t totalJ,
            int first, unsigned *flags, const uint8_t *__restrict__ mask) {
     __shared__ XlLds<ND> sm[kWaves];
