@@ -452,9 +452,9 @@ __device__ __forceinline__ void sweep_x_lanes(const double *__restrict__ U, doub
     };
     // Every lane stages the point q + 3 of its row.  Lanes 0..4 also stage
     // the points q0 - 2 .. q0 + 2 of lane 0's row, lanes 5..9 the points
-    // -3 .. 1 of a row starting inside the wave; the other lanes read their
-    // own point a second time (a cache hit), so that all loads of the wave
-    // are in flight together.
+    // -3 .. 1 of a row starting inside the wave (the other lanes' second
+    // point is their own; the compiler keeps only the extra lanes' loads,
+    // inside their branch, so the two batches arrive one after the other).
     int64_t xb = rowb, xp = q + 3;
     bool extra = false;
     if (lane < 5) {
