@@ -281,6 +281,19 @@ def form_error(prob, form, steps, cfl):
     return res
 
 
+def sweep_valu_frac(prob, sweep_ms, launches):
+    """Effective rate of the convective sweeps against the FP64 vector peak
+    (the precision form's FP32 runs at the same rate: packed FP32 is not
+    used): nominal TENO5 flops of the interfaces of `launches` sweep launches
+    (averaged over the directions) over their measured time."""
+    from paper_2007_14933_amd import cost
+    nd = prob.ndim
+    per = cost.flops_per_interface(nd, 1) * sum(cost.interfaces_per_sweep(prob.n, nd, d) for d in range(nd)) / nd
+    if sweep_ms <= 0.0:
+        return None
+    return round(per * launches / (sweep_ms * 1e-3) / 1e12 / cost.PEAK_FP64_VALU_TFLOPS, 4)
+
+
 def tgv_learned(prob, args, plain_value, plain_extra):
     """The headline TGV with learned routing (FP64 and FP32 reconstruction):
     same steps as the plain run; relative L1 of rho against the plain run's
@@ -300,7 +313,7 @@ def tgv_learned(prob, args, plain_value, plain_extra):
         v = npts * 3 * args.steps / w / 1e6
         sw = sum(p["sweep_%s" % a][1] for a in "xyz") / max(1, sum(p["sweep_%s" % a][0] for a in "xyz"))
         res[name] = {"value": round(v, 3), "speedup_vs_plain": round(v / plain_value, 3),
-                     "sweep_avg_ms": round(sw, 4),
+                     "sweep_avg_ms": round(sw, 4), "valu_frac_effective": sweep_valu_frac(prob, sw, 1),
                      "sensor_ms_per_step": round(p["sensor"][1] / max(1, args.steps), 4),
                      "smooth_fraction_last": ex["smooth_fraction_last"],
                      "rel_L1_rho_vs_plain": float("%.3e" % (np.abs(ex["rho"] - ref).mean() / np.abs(ref).mean())),
@@ -392,6 +405,7 @@ def sensor_form(cfl):
         sweeps = sum(prof["sweep_%s" % a][1] for a in "xy")
         r = {"value": round(v, 3), "steps": s.nsteps_done, "t_end": round(s.t, 6),
              "gpu_ms": round(ev0.elapsed_time(ev1), 3), "sweep_ms": round(sweeps, 3),
+             "valu_frac_effective": sweep_valu_frac(prob, sweeps, sum(prof["sweep_%s" % a][0] for a in "xy")),
              "sensor_ms": round(prof["sensor"][1], 3),
              "hbm_compulsory_frac": round(npts * 3 * s.nsteps_done * cost.compulsory_bytes_per_point(2) / wall
                                           / 1e9 / cost.PEAK_HBM_GBS, 4)}
@@ -646,7 +660,7 @@ def main():
         sm = sum(pm["sweep_%s" % a][1] for a in "xyz") / max(1, sum(pm["sweep_%s" % a][0] for a in "xyz"))
         out["forms"] = {"mixed_fp32": {
             "value": round(vm, 3), "speedup_vs_fp64": round(vm / value, 3),
-            "sweep_avg_ms": round(sm, 4),
+            "sweep_avg_ms": round(sm, 4), "valu_frac_effective": sweep_valu_frac(prob, sm, 1),
             "error_vs_fp64": form_error(prob, 1, 10, args.cfl)}}
         log("learned routing on TGV")
         out["forms"]["tgv_learned"] = tgv_learned(prob, args, value, plain_extra)
