@@ -500,7 +500,7 @@ def batch_form(steps, warmup, cfl, tune, full):
     (single-grid calls, a few steps each) for the batching gain."""
     import numpy as np
     import torch
-    from paper_2007_14933_amd import inputs
+    from paper_2007_14933_amd import cost, inputs
     from paper_2007_14933_amd import sensor as SN
     from paper_2007_14933_amd.batch import Batch
     from paper_2007_14933_amd.solver import Solver
@@ -531,6 +531,8 @@ def batch_form(steps, warmup, cfl, tune, full):
         b.check()
         r = {"value": round(act_pts * 3 * steps / wall / 1e6, 3), "ms_per_step": round(wall * 1e3 / steps, 4),
              "gpu_ms_per_step": round(ev0.elapsed_time(ev1) / steps, 4), "steps": steps,
+             "hbm_compulsory_frac": round(act_pts * 3 * steps * cost.compulsory_bytes_per_point(2) / wall / 1e9
+                                          / cost.PEAK_HBM_GBS, 4),
              "tiles_tuned": bool(tune)}
         if tiles:
             r["tiles"] = {"%dx%d" % k: list(v) for k, v in sorted(tiles.items())}
