@@ -85,7 +85,8 @@ k_sweep_wz7(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys p
 
 // y and z: lanes across 64 consecutive lines (consecutive x, so every point
 // load of the wave is one contiguous row), each lane marching its line over
-// a segment: the flux of interface f from its eight points, the node f from
+// a segment with its eight stencil points in registers (one new point, with
+// its 1/rho, p and a, per step): the flux of interface f, the node f from
 // this flux and the previous one (kept in registers)
 template <int ND, int DIR>
 __global__ void __launch_bounds__(64 * kWaves)
@@ -116,27 +117,32 @@ k_sweep_wz7_march(const double *__restrict__ U, double *__restrict__ R, Grid g, 
     const int64_t gl = g.h[DIR];
     const double *__restrict__ ih = m.invh[DIR];
     bool bad = false;
+    // the point at position pos (outer-node reading past the ghost layers)
+    auto point = [&](int64_t pos, Loc<ND> &P) {
+        if (pos < -gl) pos = per ? pos + N : -gl;
+        if (pos > N - 1 + gl) pos = per ? pos - N : N - 1 + gl;
+        Pt<ND> pt;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pt.U[c] = U[base + pos * st + c * cs];
+        finish_point<ND>(ph, pt, bad);
+        P.r = pt.U[0];
+        P.mn = pt.U[1 + DIR];
+        if (NT >= 1) P.mt[0] = pt.U[1 + Axes<ND, DIR>::T1];
+        if (NT >= 2) P.mt[1] = pt.U[1 + Axes<ND, DIR>::T2];
+        P.E = pt.U[ND + 1];
+        P.p = pt.p;
+        P.a = pt.a;
+        P.ri = pt.ri;
+    };
+    // window of the eight stencil points f-3 .. f+4, one new point per step
+    Loc<ND> P[8];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) point(p0 - 5 + k, P[k]);
     double Fp[NC];
     for (int64_t f = p0 - 1; f < p1; ++f) {
-        Loc<ND> P[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            int64_t pos = f - 3 + k;
-            if (pos < -gl) pos = per ? pos + N : -gl;
-            if (pos > N - 1 + gl) pos = per ? pos - N : N - 1 + gl;
-            Pt<ND> pt;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) pt.U[c] = U[base + pos * st + c * cs];
-            finish_point<ND>(ph, pt, bad);
-            P[k].r = pt.U[0];
-            P[k].mn = pt.U[1 + DIR];
-            if (NT >= 1) P[k].mt[0] = pt.U[1 + Axes<ND, DIR>::T1];
-            if (NT >= 2) P[k].mt[1] = pt.U[1 + Axes<ND, DIR>::T2];
-            P[k].E = pt.U[ND + 1];
-            P[k].p = pt.p;
-            P[k].a = pt.a;
-            P[k].ri = pt.ri;
-        }
+        for (int k = 0; k < 7; ++k) P[k] = P[k + 1];
+        point(f + 4, P[7]);
         double Fr, Fn, Ft[2], FE;
         char_flux<ND, OSBLI_WENOZ7, true, 8>(P, ph, Fr, Fn, Ft, FE);
         double F[NC];
