@@ -3,7 +3,8 @@
 // interface, so this scheme has kernels of its own.  Along x a wave owns 64
 // consecutive interfaces of one line (63 new nodes), each lane evaluates the
 // characteristic flux of its interface from the eight points i-3 .. i+4
-// read directly from the state, and the node between two lanes takes the
+// (the wave's 71 points loaded and finished once, into LDS), and the node
+// between two lanes takes the
 // difference of their fluxes (the left one by a lane shuffle); along y and
 // z the lanes lie across 64 consecutive x lines and march.  At the two
 // outermost interfaces of a line the stencil reaches one node past the
@@ -29,7 +30,7 @@ k_sweep_wz7(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys p
     const int64_t line = w / chunks, chunk = w - line * chunks;
     const int64_t N = g.n[DIR];
     // this lane's interface p + 1/2 (p = -1 .. N-1); lanes past the line end
-    // evaluate the last interface and write nothing
+    // write nothing
     const int64_t praw = chunk * 63 - 1 + lane;
     const int64_t p = praw < N ? praw : N - 1;
     int64_t q[3];
@@ -41,24 +42,45 @@ k_sweep_wz7(const double *__restrict__ U, double *__restrict__ R, Grid g, Phys p
     const bool per = g.periodic[DIR] != 0;
     const int64_t gl = g.h[DIR];
     bool bad = false;
-    Loc<ND> P[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        int64_t pos = p - 3 + k;
+    // the wave's 71 points (lane 0's stencil start .. lane 63's end), each
+    // loaded and finished once into LDS: lane l stages slot l, lanes 0..6
+    // also slots 64..70; slot k holds position (chunk * 63 - 1) - 3 + k
+    __shared__ double sp[kWaves][NC + 3][72];
+    double(*const sw)[72] = sp[threadIdx.x >> 6];
+    const int64_t pos0 = chunk * 63 - 4;
+    auto stage = [&](int slot) {
+        int64_t pos = pos0 + slot;
         if (pos < -gl) pos = per ? pos + N : -gl;
         if (pos > N - 1 + gl) pos = per ? pos - N : N - 1 + gl;
         Pt<ND> pt;
 #pragma unroll
         for (int c = 0; c < NC; ++c) pt.U[c] = U[base + pos * st + c * cs];
         finish_point<ND>(ph, pt, bad);
-        P[k].r = pt.U[0];
-        P[k].mn = pt.U[1 + DIR];
-        if (NT >= 1) P[k].mt[0] = pt.U[1 + Axes<ND, DIR>::T1];
-        if (NT >= 2) P[k].mt[1] = pt.U[1 + Axes<ND, DIR>::T2];
-        P[k].E = pt.U[ND + 1];
-        P[k].p = pt.p;
-        P[k].a = pt.a;
-        P[k].ri = pt.ri;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sw[c][slot] = pt.U[c];
+        sw[NC][slot] = pt.ri;
+        sw[NC + 1][slot] = pt.p;
+        sw[NC + 2][slot] = pt.a;
+    };
+    stage(lane);
+    if (lane < 7) stage(64 + lane);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // this lane's stencil p - 3 .. p + 4 is slots lane .. lane + 7 (lanes
+    // past the line end read valid points and write nothing)
+    Loc<ND> P[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int sl = lane + k;
+        P[k].r = sw[0][sl];
+        P[k].mn = sw[1 + DIR][sl];
+        if (NT >= 1) P[k].mt[0] = sw[1 + Axes<ND, DIR>::T1][sl];
+        if (NT >= 2) P[k].mt[1] = sw[1 + Axes<ND, DIR>::T2][sl];
+        P[k].E = sw[ND + 1][sl];
+        P[k].p = sw[NC + 1][sl];
+        P[k].a = sw[NC + 2][sl];
+        P[k].ri = sw[NC][sl];
     }
     double Fr, Fn, Ft[2], FE;
     char_flux<ND, OSBLI_WENOZ7, true, 8>(P, ph, Fr, Fn, Ft, FE);
